@@ -1,0 +1,71 @@
+/*
+ * Oracle: plain FP64 direct sum of the spherical Green's function and its
+ * gradient.  TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * What it computes, written out from the paper:
+ *   psi(n)   = sum_j q_j G(n, n_j)                      Sec. 3.1 Eq. SUM
+ *   G(n,n')  = (1/4pi) log((1 - n.n')/2)               Sec. 2.1 Eq. GRE_FUN
+ *            = (1/4pi) log(|n - n'|^2 / 4)             (unit vectors)
+ *   zero-mean gauge (Eq. STAND_CONDITION): the sphere integral of G is -1,
+ *   so the gauge-fixed potential is psi + Q_tot/(4pi); per source this is
+ *   the term q_j (log(|d|^2/4) + 1)/(4pi).
+ *   alpha(n) = grad psi (Eq. ALP_PSI), the covariant gradient on the sphere:
+ *   the ambient gradient of (q/4pi) log|d|^2 is (q/2pi) d/|d|^2, and its
+ *   tangent part at n is (q/2pi)(d/|d|^2 - n/2) because n.d = |d|^2/2.
+ * Compiled with -ffp-contract=off: no fused multiply-adds, IEEE round to
+ * nearest, and every accumulation is Neumaier-compensated.
+ */
+#include "oracle.h"
+#include <math.h>
+#include <omp.h>
+
+typedef struct {
+    double s, c;
+} nsum_t;
+
+static inline void nsum_add(nsum_t* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static inline double nsum_value(const nsum_t* a) { return a->s + a->c; }
+
+void oracle_direct(const double* src, const double* q, int64_t n,
+                   const double* tgt, int64_t m, int gauge, double* psi,
+                   double* defl, int nthreads) {
+    const double* sx = src;
+    const double* sy = src + n;
+    const double* sz = src + 2 * n;
+    const double four_pi = 4.0 * M_PI;
+    const double two_pi = 2.0 * M_PI;
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (i = 0; i < m; ++i) {
+        const double nx = tgt[i], ny = tgt[m + i], nz = tgt[2 * m + i];
+        nsum_t p = {0.0, 0.0}, ax = {0.0, 0.0}, ay = {0.0, 0.0}, az = {0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            const double dx = nx - sx[j], dy = ny - sy[j], dz = nz - sz[j];
+            if (dx == 0.0 && dy == 0.0 && dz == 0.0) {
+                /* coincident source: no log term; in the zero-mean gauge its
+                 * share q_j/(4pi) of the constant Q_tot/(4pi) remains. */
+                if (gauge == ORACLE_GAUGE_ZERO_MEAN) nsum_add(&p, q[j]);
+                continue;
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double g = log(0.25 * r2);
+            nsum_add(&p, q[j] * (gauge == ORACLE_GAUGE_ZERO_MEAN ? g + 1.0 : g));
+            nsum_add(&ax, q[j] * (dx / r2 - 0.5 * nx));
+            nsum_add(&ay, q[j] * (dy / r2 - 0.5 * ny));
+            nsum_add(&az, q[j] * (dz / r2 - 0.5 * nz));
+        }
+        psi[i] = nsum_value(&p) / four_pi;
+        defl[i] = nsum_value(&ax) / two_pi;
+        defl[m + i] = nsum_value(&ay) / two_pi;
+        defl[2 * m + i] = nsum_value(&az) / two_pi;
+    }
+}

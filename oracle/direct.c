@@ -10,8 +10,12 @@
  *   so the gauge-fixed potential is psi + Q_tot/(4pi); per source this is
  *   the term q_j (log(|d|^2/4) + 1)/(4pi).
  *   alpha(n) = grad psi (Eq. ALP_PSI), the covariant gradient on the sphere:
- *   the ambient gradient of (q/4pi) log|d|^2 is (q/2pi) d/|d|^2, and its
- *   tangent part at n is (q/2pi)(d/|d|^2 - n/2) because n.d = |d|^2/2.
+ *   the ambient gradient of (q/4pi) log|d|^2 is (q/2pi) d/|d|^2, and alpha
+ *   is its part tangent to the sphere at n, (q/2pi)(d - n^ (n^.d))/|d|^2
+ *   with n^ = n/|n|.  For exact unit vectors n.d = |d|^2/2 and this is
+ *   (q/2pi)(d/|d|^2 - n/2); FP64 inputs lie off the sphere by ~1e-16, which
+ *   for very close pairs would leave a radial part of size 1e-16/|d|^2 in
+ *   that second form, so the projection is written out per term.
  * Compiled with -ffp-contract=off: no fused multiply-adds, IEEE round to
  * nearest, and every accumulation is Neumaier-compensated.
  */
@@ -47,6 +51,8 @@ void oracle_direct(const double* src, const double* q, int64_t n,
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
     for (i = 0; i < m; ++i) {
         const double nx = tgt[i], ny = tgt[m + i], nz = tgt[2 * m + i];
+        const double inv_len = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+        const double ux = nx * inv_len, uy = ny * inv_len, uz = nz * inv_len;
         nsum_t p = {0.0, 0.0}, ax = {0.0, 0.0}, ay = {0.0, 0.0}, az = {0.0, 0.0};
         for (int64_t j = 0; j < n; ++j) {
             const double dx = nx - sx[j], dy = ny - sy[j], dz = nz - sz[j];
@@ -59,9 +65,10 @@ void oracle_direct(const double* src, const double* q, int64_t n,
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double g = log(0.25 * r2);
             nsum_add(&p, q[j] * (gauge == ORACLE_GAUGE_ZERO_MEAN ? g + 1.0 : g));
-            nsum_add(&ax, q[j] * (dx / r2 - 0.5 * nx));
-            nsum_add(&ay, q[j] * (dy / r2 - 0.5 * ny));
-            nsum_add(&az, q[j] * (dz / r2 - 0.5 * nz));
+            const double nd = ux * dx + uy * dy + uz * dz; /* radial part of d */
+            nsum_add(&ax, q[j] * ((dx - ux * nd) / r2));
+            nsum_add(&ay, q[j] * ((dy - uy * nd) / r2));
+            nsum_add(&az, q[j] * ((dz - uz * nd) / r2));
         }
         psi[i] = nsum_value(&p) / four_pi;
         defl[i] = nsum_value(&ax) / two_pi;

@@ -129,6 +129,10 @@ void oracle_pix_point_q(int order, int64_t pix, double fx, double fy,
     out3[0] = sth * cosq(phi);
     out3[1] = sth * sinq(phi);
     out3[2] = z;
+    /* a coordinate this small is an exact zero (azimuth at a multiple of
+     * pi/2 rounded in quad); a genuine one is never below ~1e-18 */
+    for (int k = 0; k < 3; ++k)
+        if (fabsq(out3[k]) < 1e-25Q) out3[k] = 0;
 }
 
 void oracle_pix_point(int order, int64_t pix, double fx, double fy,

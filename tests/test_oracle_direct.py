@@ -55,9 +55,16 @@ def test_single_point_mass_closed_form(oracle_lib):
     thetas = [1e-7, 1e-4, 0.01, 0.3, 1.0, 2.0, 3.0, np.pi - 1e-5]
     tg = np.stack([_geodesic_point(s, th, rng.uniform(0, 2 * np.pi)) for th in thetas], axis=1)
     psi, defl = oracle.direct(s.reshape(3, 1), np.array([q]), tg)
+    def on_sphere(v):
+        # FP64 inputs are unit vectors to ~1e-16; the closed form lives on
+        # the sphere, so project there in 50 digits
+        v = [mp.mpf(float(c)) for c in v]
+        r = mp.sqrt(sum(c * c for c in v))
+        return [c / r for c in v]
+
     for i in range(tg.shape[1]):
-        n = [mp.mpf(float(v)) for v in tg[:, i]]
-        S = [mp.mpf(float(v)) for v in s]
+        n = on_sphere(tg[:, i])
+        S = on_sphere(s)
         c = sum(a * b for a, b in zip(n, S))
         cross = [n[1] * S[2] - n[2] * S[1], n[2] * S[0] - n[0] * S[2], n[0] * S[1] - n[1] * S[0]]
         T = mp.atan2(mp.sqrt(sum(v * v for v in cross)), c)

@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the sFMM hot path on one MI355X.
+
+One step = one full pass of the method over the workload: keys, sort, tree,
+box geometry, Algorithm 1 walk, list sorting, target location (sfmm_plan) and
+P2M, M2M, M2L, L2L, L2P, P2P (sfmm_execute).  Inputs are resident in HBM
+before timing starts.  The metric is targets per second of psi + deflection
+at relative error <= the tolerance.
+
+Prints one JSON line (rank 0, N = 1 only).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_P2P_PAIR = 20       # 3 sub, 5 for |d|^2, 1 reciprocal, 1 log, 2 psi, 1 mass, 1 scale, 6 alpha
+
+
+def m2l_flops(p: int) -> int:
+    """Algorithmic flops of one Lemma 3 translation at order p: two
+    triangular Taylor-shift factors (p(p+1) complex*real FMAs, 4p^2 + 4p
+    flops) plus the phase, diagonal and output terms (~28p)."""
+    return 4 * p * p + 32 * p
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clustered-1e7")
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink N (quick runs only)")
+    ap.add_argument("--tolerance", type=float, default=1e-10)
+    ap.add_argument("--order", type=int, default=0, help="fixed order instead of the tolerance")
+    ap.add_argument("--leaf-size", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2210_07021_amd as sf
+    from paper_2210_07021_amd import skies
+
+    sf.load_library()
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {args.workload} (scale {args.scale})")
+    t = time.time()
+    src_h, q_h, tgt_h = skies.workload(args.workload, scale=args.scale)
+    N, M = src_h.shape[1], tgt_h.shape[1]
+    log(f"[bench] N={N} M={M} generated in {time.time() - t:.1f}s")
+    src = torch.from_numpy(src_h).cuda()
+    q = torch.from_numpy(q_h).cuda()
+    tgt = torch.from_numpy(tgt_h).cuda()
+    psi = torch.empty(M, dtype=torch.float64, device="cuda")
+    defl = torch.empty((3, M), dtype=torch.float64, device="cuda")
+    opts = dict(leaf_size=args.leaf_size)
+    if args.order > 0:
+        opts["order"] = args.order
+    else:
+        opts["tolerance"] = args.tolerance
+    torch.cuda.synchronize()
+
+    def step():
+        plan = sf.Plan(src, q, tgt, **opts)
+        plan.execute(psi, defl)
+        return plan
+
+    for w in range(args.warmup):
+        t = time.time()
+        plan = step()
+        torch.cuda.synchronize()
+        stats = plan.stats()
+        plan.close()
+        log(f"[bench] warmup {w}: {time.time() - t:.3f}s")
+    if args.warmup == 0:
+        plan = step()
+        stats = plan.stats()
+        plan.close()
+
+    sf.profile_reset()
+    sf.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan = step()
+        plan.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sf.profile_enable(False)
+    prof = sf.profile_read()
+    elapsed = t1 - t0
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s")
+    stages_ms = {k: v[0] / args.steps for k, v in prof.items()}
+
+    p = stats["order"]
+    work = {
+        "m2l": ("alu", stats["n_m2l"] * m2l_flops(p), PEAK_FP64_TFLOPS, "TFLOP/s"),
+        "p2p": ("alu", stats["n_p2p_pairs"] * FLOP_PER_P2P_PAIR, PEAK_FP64_TFLOPS, "TFLOP/s"),
+    }
+    dom = max(work, key=lambda k: stages_ms[k])
+    bound, flops, peak, unit = work[dom]
+    achieved = flops / (stages_ms[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None,
+                "work_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
+
+    result = {
+        "metric": "targets/s (psi+deflection) at 1e-10 rel err, N=1e7",
+        "value": M * args.steps / elapsed,
+        "unit": "targets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "M": M,
+                   "tolerance": None if args.order > 0 else args.tolerance, "order": p,
+                   "leaf_size": args.leaf_size, "precision": "fp64", "c_s": 2.0, "c_t": 0.5,
+                   "n_boxes": stats["n_boxes"], "n_m2l": stats["n_m2l"], "n_p2p_pairs": stats["n_p2p_pairs"]},
+        "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(skies.BASE_SEED + 1002)
+        psi_h = psi.cpu().numpy()
+        defl_h = defl.cpu().numpy()
+        k0 = 8
+        idx = rng.choice(M, size=k0, replace=False)
+        t = time.perf_counter()
+        oracle.direct(src_h, q_h, tgt_h[:, idx])
+        t_probe = time.perf_counter() - t
+        k = int(min(M, max(k0, k0 * args.cpu_seconds / max(t_probe, 1e-6))))
+        idx = rng.choice(M, size=k, replace=False)
+        log(f"[bench] cpu baseline: oracle on {k} sampled targets (probe {t_probe:.2f}s for {k0})")
+        t = time.perf_counter()
+        ref_p, ref_a = oracle.direct(src_h, q_h, tgt_h[:, idx])
+        t_cpu = time.perf_counter() - t
+        cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        result["cpu_baseline"] = {"value": k / t_cpu, "unit": "targets/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"{k} seeded targets of the same workload, all {N} sources, "
+                                            f"{t_cpu:.1f}s"}
+        result["accuracy"] = {
+            "psi_rel_l2": float(np.linalg.norm(psi_h[idx] - ref_p) / np.linalg.norm(ref_p)),
+            "alpha_rel_l2": float(np.linalg.norm(defl_h[:, idx] - ref_a) / np.linalg.norm(ref_a)),
+            "targets": k}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * libsfmm -- the spherical Fast Multipole Method (sFMM) of Suo, Kang, Wei &
+ * Li (arXiv:2210.07021) on one AMD MI355X (gfx950).
+ *
+ * Problem (Sec. 3.1 Eq. SUM, Sec. 2.1 Eq. GRE_FUN, Eq. ALP_PSI, Eq.
+ * STAND_CONDITION): N point masses q_j at unit vectors n_j; at M target unit
+ * vectors n evaluate
+ *     psi(n)   = sum_j q_j G(n, n_j),  G = (1/4pi) log((1 - n.n_j)/2),
+ *     alpha(n) = grad psi(n), the covariant gradient on the sphere,
+ * with psi in the zero-mean gauge of Eq. STAND_CONDITION (Q_tot/(4pi) added,
+ * since G integrates to -1 over the sphere) unless SFMM_GAUGE_RAW is asked
+ * for.  A source at exactly a target's position (bitwise) is left out of that
+ * target's sum, keeping only its share of the gauge constant.
+ *
+ * Method: the adaptive HEALPix quasi-quad-tree of Sec. 3.1 (leaf cap m,
+ * depth <= 29), Lemma 1 on leaves and Lemma 2 up the tree (Sec. 3.2), the
+ * dual tree walk of Algorithm 1 (Sec. 3.4) with the MACs of Sec. 3.5 (c_s,
+ * c_t), Lemma 3 on every FMM-act pair and Lemma 4 down the tree (Sec. 3.3),
+ * the local expansion plus the direct sum over the close boxes at each
+ * target (Sec. 3.6).
+ *
+ * Conventions for every call:
+ *   - Point sets are device pointers to three FP64 planes [3][count]:
+ *     x[0..count), y[0..count), z[0..count).  Masses are a device FP64 [N].
+ *   - Outputs are caller-owned device buffers, FP64, in the caller's target
+ *     order: psi [M], defl [3][M] (global Cartesian components of the tangent
+ *     vector alpha).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is ordered on it; host-visible results (stats, exports) are
+ *     complete when the call returns.
+ *   - Errors: every call returns an sfmm_status; on failure
+ *     sfmm_last_error() holds a message for the calling thread.  No
+ *     exception crosses this boundary.  A plan is not thread-safe.
+ */
+#ifndef SFMM_H
+#define SFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfmm_plan_impl* sfmm_plan_t;
+
+typedef enum {
+    SFMM_OK = 0,
+    SFMM_ERR_INVALID_ARG = 1,       /* bad size, option or input values      */
+    SFMM_ERR_OUT_OF_MEMORY = 2,     /* device allocation failed               */
+    SFMM_ERR_HIP = 3,               /* a HIP runtime call or kernel failed    */
+    SFMM_ERR_TOLERANCE_NOT_MET = 4, /* reserved                               */
+    SFMM_ERR_INTERNAL = 5
+} sfmm_status;
+
+enum { SFMM_GAUGE_ZERO_MEAN = 0, SFMM_GAUGE_RAW = 1 };
+enum { SFMM_FP64 = 0 };
+
+typedef struct {
+    int32_t order;      /* truncation order p of Eq. MUL_ERR, 1..48; 0 = pick p
+                           from `tolerance`                                   */
+    double tolerance;   /* target relative L2 error of psi and of alpha when
+                           order == 0; in [1e-15, 1e-1]                       */
+    int32_t leaf_size;  /* m of Sec. 3.1: a box holding more than m particles
+                           is split; >= 1                                     */
+    double c_s;         /* MAC1 constant of Sec. 3.5 (default 2)              */
+    double c_t;         /* MAC2 constant of Sec. 3.5 (default 0.5)            */
+    int32_t max_level;  /* maximum depth r_max of Sec. 3.1, 0..29 (default 29) */
+    int32_t precision;  /* SFMM_FP64                                          */
+    int32_t psi_gauge;  /* SFMM_GAUGE_ZERO_MEAN (default) or SFMM_GAUGE_RAW   */
+    int32_t reserved[9];
+} sfmm_options;
+
+typedef struct {
+    int64_t n_sources, n_targets;
+    int64_t n_boxes, n_leaves, n_levels;
+    int64_t n_m2l, n_p2p;           /* FMM-act and direct-act pairs            */
+    int64_t n_target_leaves;        /* leaves holding at least one target      */
+    int64_t n_p2p_pairs;            /* particle-target pairs of the direct acts */
+    int32_t order, leaf_size;
+    double q_total;                 /* sum of the masses                        */
+} sfmm_stats;
+
+/* Fill *opt with the defaults: order 0 with tolerance 1e-10, leaf_size 64,
+ * c_s 2, c_t 0.5, max_level 29, FP64, zero-mean gauge. */
+void sfmm_default_options(sfmm_options* opt);
+
+/* Build a plan: keys, sorting, the tree (Sec. 3.1), box geometry (Sec. 3.5),
+ * the interaction lists of Algorithm 1 (Sec. 3.4) and the target-to-leaf map
+ * (Sec. 3.7).  src [3][N], q [N], tgt [3][M] are device buffers; they are
+ * copied (and sorted), so the caller may reuse them once the stream has
+ * passed this call.  N = 0 is allowed (all outputs are zero); M = 0 is
+ * allowed (execute does nothing).
+ * Errors: SFMM_ERR_INVALID_ARG for N or M negative or above 2^31 - 1, null
+ * pointers with a nonzero size, options out of range, non-finite input
+ * coordinates or points off the unit sphere by more than 1e-6 (points off by
+ * more than 1e-14 are renormalised). */
+sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const double* tgt, int64_t M,
+                      const sfmm_options* opt, void* stream, sfmm_plan_t* out);
+
+/* Run the five stages of Sec. 3.7 for a plan: psi [M] and defl [3][M]
+ * (device, caller-owned, caller's target order) are overwritten. */
+sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stream);
+
+/* Sizes of a plan. */
+sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out);
+
+/* Host copies of the tree for comparisons, in the library's box order
+ * (level, then pixel).  Buffers are host memory of the sizes in sfmm_stats:
+ *   level, pixel, first, count, parent, child0: [n_boxes] (child0 = -1 for a
+ *   leaf, parent = -1 at level 0); centre [3][n_boxes]; radius [n_boxes]
+ *   (radians).  Any pointer may be NULL to skip that array. */
+sfmm_status sfmm_export_boxes(sfmm_plan_t plan, int32_t* level, int64_t* pixel, int64_t* first,
+                              int64_t* count, int64_t* parent, int64_t* child0, double* centre,
+                              double* radius);
+
+/* Host copies of the interaction lists, sorted by (target box, source box):
+ * m2l_src/m2l_tgt [n_m2l] and p2p_src/p2p_tgt [n_p2p].  Source boxes without
+ * particles are left out of both lists (they contribute nothing). */
+sfmm_status sfmm_export_lists(sfmm_plan_t plan, int64_t* m2l_src, int64_t* m2l_tgt, int64_t* p2p_src,
+                              int64_t* p2p_tgt);
+
+/* Host copies of the order-29 keys: src_keys [N] ascending with src_perm
+ * [N] the caller index of each, tgt_keys [M] ascending with tgt_perm [M],
+ * tgt_leaf [M] the leaf box of each sorted target. */
+sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_perm, uint64_t* tgt_keys,
+                             int64_t* tgt_perm, int64_t* tgt_leaf);
+
+/* Host copies of the expansions after sfmm_execute, in the paper's
+ * normalisation (Lemma 1: psi = C + Q log(1 -+ cos) + 2 Re sum A_l z^(-+l)):
+ * multipole and local are [n_boxes][2p+2] = (C, Q, Re A_1, Im A_1, ...,
+ * Re A_p, Im A_p).  C is reported without the zero-mean gauge share. */
+sfmm_status sfmm_export_expansions(sfmm_plan_t plan, double* multipole, double* local);
+
+void sfmm_destroy(sfmm_plan_t plan);
+const char* sfmm_status_string(sfmm_status s);
+const char* sfmm_last_error(void);
+
+/* Order p that reaches the relative tolerance tol (the policy used when
+ * opt->order == 0). */
+int32_t sfmm_order_for_tolerance(double tol);
+
+/* Stage timing.  While enabled, every sfmm_plan / sfmm_execute brackets each
+ * stage with HIP events on the caller's stream and, at the end of the call,
+ * synchronises the stream and adds the elapsed times to process-wide
+ * per-stage totals.  Stages (indices into the arrays of sfmm_profile_read):
+ *   0 source keys+sort, 1 tree levels, 2 box geometry, 3 walk (Algorithm 1),
+ *   4 list sort/CSR, 5 target keys+sort+locate, 6 P2M, 7 M2M (all levels),
+ *   8 M2L, 9 L2L (all levels), 10 L2P, 11 P2P.
+ * ms[SFMM_NUM_STAGES] receives the summed milliseconds and calls[] the number
+ * of times each stage ran; both are host arrays and may be NULL. */
+#define SFMM_NUM_STAGES 12
+void sfmm_profile_enable(int32_t on);
+void sfmm_profile_reset(void);
+void sfmm_profile_read(double* ms, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

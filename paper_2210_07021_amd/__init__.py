@@ -1,1 +1,256 @@
-"""sFMM on MI355X (placeholder; the binding is added with the library)."""
+"""Python binding of libsfmm, the spherical FMM (arXiv:2210.07021) on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libsfmm.so`` (built in-tree by ``paper_2210_07021_amd.build``).
+PyTorch provides device memory and the stream.  The names follow the C ABI in
+``include/sfmm.h``; :class:`Plan` is a small convenience wrapper.
+
+There is no fallback: importing works without the library, but any call
+raises if ``libsfmm.so`` has not been built or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfmm.so")
+
+SFMM_OK = 0
+SFMM_GAUGE_ZERO_MEAN = 0
+SFMM_GAUGE_RAW = 1
+SFMM_FP64 = 0
+
+
+class SfmmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"sfmm status {status}: {message}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("tolerance", ctypes.c_double),
+        ("leaf_size", ctypes.c_int32),
+        ("c_s", ctypes.c_double),
+        ("c_t", ctypes.c_double),
+        ("max_level", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("psi_gauge", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 9),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_sources", ctypes.c_int64),
+        ("n_targets", ctypes.c_int64),
+        ("n_boxes", ctypes.c_int64),
+        ("n_leaves", ctypes.c_int64),
+        ("n_levels", ctypes.c_int64),
+        ("n_m2l", ctypes.c_int64),
+        ("n_p2p", ctypes.c_int64),
+        ("n_target_leaves", ctypes.c_int64),
+        ("n_p2p_pairs", ctypes.c_int64),
+        ("order", ctypes.c_int32),
+        ("leaf_size", ctypes.c_int32),
+        ("q_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every exported symbol of include/sfmm.h with its ctypes signature
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "sfmm_default_options": (None, [ctypes.POINTER(Options)]),
+    "sfmm_plan": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "sfmm_execute": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sfmm_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "sfmm_export_boxes": (ctypes.c_int, [_P] * 9),
+    "sfmm_export_lists": (ctypes.c_int, [_P] * 5),
+    "sfmm_export_keys": (ctypes.c_int, [_P] * 6),
+    "sfmm_export_expansions": (ctypes.c_int, [_P] * 3),
+    "sfmm_destroy": (None, [_P]),
+    "sfmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sfmm_last_error": (ctypes.c_char_p, []),
+    "sfmm_order_for_tolerance": (ctypes.c_int32, [ctypes.c_double]),
+    "sfmm_profile_enable": (None, [ctypes.c_int32]),
+    "sfmm_profile_reset": (None, []),
+    "sfmm_profile_read": (None, [_P, _P]),
+}
+
+NUM_STAGES = 12
+STAGES = ["src_keys_sort", "tree", "geometry", "walk", "lists", "targets",
+          "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsfmm.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libsfmm.so not found at {path}: build it with "
+                               "`python -m paper_2210_07021_amd.build` (no fallback exists)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != SFMM_OK:
+        lib = load_library()
+        raise SfmmError(status, lib.sfmm_last_error().decode(errors="replace"))
+
+
+def default_options(**overrides) -> Options:
+    opt = Options()
+    load_library().sfmm_default_options(ctypes.byref(opt))
+    for k, v in overrides.items():
+        if not hasattr(opt, k):
+            raise TypeError(f"unknown option {k!r}")
+        setattr(opt, k, v)
+    return opt
+
+
+def order_for_tolerance(tol: float) -> int:
+    return int(load_library().sfmm_order_for_tolerance(float(tol)))
+
+
+def profile_enable(on: bool = True):
+    load_library().sfmm_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load_library().sfmm_profile_reset()
+
+
+def profile_read() -> dict:
+    """Per-stage {name: (total ms, calls)} accumulated while enabled."""
+    ms = np.zeros(NUM_STAGES)
+    calls = np.zeros(NUM_STAGES, np.int64)
+    load_library().sfmm_profile_read(ms.ctypes.data_as(_P), calls.ctypes.data_as(_P))
+    return {n: (float(ms[i]), int(calls[i])) for i, n in enumerate(STAGES)}
+
+
+def _dev_planes(x, name):
+    import torch
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64)
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not x.is_cuda:
+        x = x.to("cuda")
+    return x.contiguous()
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A planned sFMM evaluation: sources (3, N), masses (N,), targets (3, M),
+    as torch CUDA float64 tensors (or host arrays, copied to the device)."""
+
+    def __init__(self, src, q, tgt, stream=None, **options):
+        import torch
+        self._lib = load_library()
+        self.src = _dev_planes(src, "src")
+        self.q = _dev_planes(q, "q")
+        self.tgt = _dev_planes(tgt, "tgt")
+        if self.src.dim() != 2 or self.src.shape[0] != 3 or self.tgt.dim() != 2 or self.tgt.shape[0] != 3:
+            raise ValueError("src and tgt must have shape (3, n)")
+        if self.q.shape != (self.src.shape[1],):
+            raise ValueError("q must have shape (N,)")
+        self.N = int(self.src.shape[1])
+        self.M = int(self.tgt.shape[1])
+        self.options = default_options(**options)
+        self._stream = stream
+        self._h = ctypes.c_void_p()
+        _check(self._lib.sfmm_plan(
+            ctypes.c_void_p(self.src.data_ptr() if self.N else 0),
+            ctypes.c_void_p(self.q.data_ptr() if self.N else 0), self.N,
+            ctypes.c_void_p(self.tgt.data_ptr() if self.M else 0), self.M,
+            ctypes.byref(self.options), _stream_handle(stream), ctypes.byref(self._h)))
+        self._torch = torch
+
+    def execute(self, psi=None, defl=None, stream=None):
+        """Returns (psi (M,), defl (3, M)) as CUDA float64 tensors."""
+        t = self._torch
+        if psi is None:
+            psi = t.empty(self.M, dtype=t.float64, device="cuda")
+        if defl is None:
+            defl = t.empty((3, self.M), dtype=t.float64, device="cuda")
+        _check(self._lib.sfmm_execute(self._h, ctypes.c_void_p(psi.data_ptr() if self.M else 0),
+                                      ctypes.c_void_p(defl.data_ptr() if self.M else 0),
+                                      _stream_handle(stream if stream is not None else self._stream)))
+        return psi, defl
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.sfmm_stats_get(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export_boxes(self) -> dict:
+        nb = self.stats()["n_boxes"]
+        out = dict(level=np.zeros(nb, np.int32), pixel=np.zeros(nb, np.int64), first=np.zeros(nb, np.int64),
+                   count=np.zeros(nb, np.int64), parent=np.zeros(nb, np.int64), child0=np.zeros(nb, np.int64),
+                   centre=np.zeros((3, nb)), radius=np.zeros(nb))
+        _check(self._lib.sfmm_export_boxes(self._h, *[a.ctypes.data_as(_P) for a in out.values()]))
+        return out
+
+    def export_lists(self):
+        st = self.stats()
+        m2l = np.zeros((2, st["n_m2l"]), np.int64)
+        p2p = np.zeros((2, st["n_p2p"]), np.int64)
+        _check(self._lib.sfmm_export_lists(self._h, m2l[0].ctypes.data_as(_P), m2l[1].ctypes.data_as(_P),
+                                           p2p[0].ctypes.data_as(_P), p2p[1].ctypes.data_as(_P)))
+        return m2l.T.copy(), p2p.T.copy()
+
+    def export_keys(self) -> dict:
+        out = dict(src_keys=np.zeros(self.N, np.uint64), src_perm=np.zeros(self.N, np.int64),
+                   tgt_keys=np.zeros(self.M, np.uint64), tgt_perm=np.zeros(self.M, np.int64),
+                   tgt_leaf=np.zeros(self.M, np.int64))
+        _check(self._lib.sfmm_export_keys(self._h, *[a.ctypes.data_as(_P) for a in out.values()]))
+        return out
+
+    def export_expansions(self):
+        st = self.stats()
+        w = 2 * st["order"] + 2
+        mult = np.zeros((st["n_boxes"], w))
+        loc = np.zeros((st["n_boxes"], w))
+        _check(self._lib.sfmm_export_expansions(self._h, mult.ctypes.data_as(_P), loc.ctypes.data_as(_P)))
+        return mult, loc
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.sfmm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sfmm(src, q, tgt, **options):
+    """One-shot evaluation: plan + execute; returns (psi, defl) on the GPU."""
+    p = Plan(src, q, tgt, **options)
+    try:
+        return p.execute()
+    finally:
+        p.close()

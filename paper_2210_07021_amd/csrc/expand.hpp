@@ -1,0 +1,334 @@
+// Expansion arithmetic of the sFMM (Sec. 3.1-3.3, 3.6) for one box or one box
+// pair, written for one GPU lane with the order P fixed at compile time so
+// the coefficients live in registers.
+//
+// Frames.  A box centre c carries the system K_c whose zenith is c and whose
+// azimuth reference is e_theta(c) (Sec. 3.1).  The base function
+// z = tan(theta/2) e^{i phi} is the stereographic projection from -c,
+// w = ((n - c).e_theta + i (n - c).e_phi) / (1 + n.c), with 1 + n.c computed
+// as |n + c|^2 / 2 so that neither near nor antipodal points cancel.
+//
+// Scaled coefficients.  A box of radius R has scale rho = tan(R/2), the
+// largest |w| of a point inside it.  Multipole coefficients are stored as
+// A_l / rho^l and local ones as A_l rho^l, so every stored number is bounded
+// by the box's mass and nothing over- or underflows down to depth 29.
+//
+// Translations.  Lemmas 2, 3 and 4 share one shape,
+//   A'_l = ph2^l [ -(Q/l) x^l + sum_l' T_ll'(x) ph1^l' A_l' ],
+//   T_ll'(x) = sum_n C(l-1,n-1) C(l',n) x^{l+l'-2n} (1+x^2)^n,
+// and with the scalings folded in, T_ll' s_T^l s_S^l' factors as
+//   sum_n [C(l-1,n-1) a^{l-n}] g^n [C(l',n) b^{l'-n}],
+//   a = x s_T, b = x s_S, g = s_T s_S (1+x^2),
+// i.e. a Taylor shift by b (right factor), a diagonal g^n, and a transposed
+// Taylor shift by a (left factor).  Both shifts run in place with P(P+1)/2
+// complex*real FMAs and no binomial table; a, b, g are all below ~1 for every
+// pair the MACs accept, so nothing overflows.  The n = 0 entry of the first
+// shift is sum_l' b^l' ph1^l' A_l', the series part of C'.
+#pragma once
+#include "dd.hpp"
+
+namespace sfmm {
+
+constexpr double kInv4Pi = 0.079577471545947667884;  // 1 / (4 pi)
+constexpr double kInv2Pi = 0.15915494309189533577;   // 1 / (2 pi)
+constexpr double kLog2 = 0.69314718055994530942;
+constexpr double kLog4 = 1.3862943611198906188;
+
+struct cplx {
+    double re, im;
+};
+SFMM_HD cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+SFMM_HD cplx cconj(cplx a) { return {a.re, -a.im}; }
+
+struct Frame {
+    double c[3], et[3], ep[3];
+};
+
+// e_theta and e_phi at the centre c (never a pole for a HEALPix centre)
+SFMM_HD Frame make_frame(double x, double y, double z) {
+    Frame f;
+    f.c[0] = x;
+    f.c[1] = y;
+    f.c[2] = z;
+    const double rxy = sqrt(x * x + y * y);
+    const double inv = 1.0 / rxy;
+    f.et[0] = x * z * inv;
+    f.et[1] = y * z * inv;
+    f.et[2] = -rxy;
+    f.ep[0] = -y * inv;
+    f.ep[1] = x * inv;
+    f.ep[2] = 0.0;
+    return f;
+}
+
+// stereographic coordinate of n in K_c; also returns 1 + n.c
+SFMM_HD cplx stereo(const Frame& f, double nx, double ny, double nz, double* one_plus_cos) {
+    const double dx = nx - f.c[0], dy = ny - f.c[1], dz = nz - f.c[2];
+    const double sx = nx + f.c[0], sy = ny + f.c[1], sz = nz + f.c[2];
+    const double den = 0.5 * (sx * sx + sy * sy + sz * sz);
+    const double inv = 1.0 / den;
+    *one_plus_cos = den;
+    return {(dx * f.et[0] + dy * f.et[1] + dz * f.et[2]) * inv,
+            (dx * f.ep[0] + dy * f.ep[1] + dz * f.ep[2]) * inv};
+}
+
+enum TransKind { kM2M = 0, kM2L = 1, kL2L = 2 };
+
+// Everything a translation S -> T needs besides the coefficients.
+struct TransGeom {
+    cplx ph1, ph2;        // phase factors applied per power on input / output
+    double a, b, g;       // shift parameters of the factorised T
+    double clog;          // log cos^2(T/2) (M2M, L2L) or log sin^2(T/2) (M2L)
+};
+
+// Pair geometry from centres and scales (rho = tan(R/2)) of the source box S
+// and the target box T.
+template <int KIND>
+SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, double rho_t) {
+    TransGeom G;
+    const double dx = ft.c[0] - fs.c[0], dy = ft.c[1] - fs.c[1], dz = ft.c[2] - fs.c[2];
+    const double sx = ft.c[0] + fs.c[0], sy = ft.c[1] + fs.c[1], sz = ft.c[2] + fs.c[2];
+    const double dif2 = dx * dx + dy * dy + dz * dz;  // 4 sin^2(T/2)
+    const double sum2 = sx * sx + sy * sy + sz * sz;  // 4 cos^2(T/2)
+    // phase of T's centre seen from S, and of S's centre seen from T
+    cplx e1, e2;
+    if (sum2 < 1e-24) {
+        // exactly antipodal centres: the geodesic leaving S along e_theta(S)
+        e1 = {1.0, 0.0};
+        const double u = fs.et[0] * ft.et[0] + fs.et[1] * ft.et[1] + fs.et[2] * ft.et[2];
+        const double v = fs.et[0] * ft.ep[0] + fs.et[1] * ft.ep[1] + fs.et[2] * ft.ep[2];
+        const double r = 1.0 / sqrt(u * u + v * v);
+        e2 = {u * r, v * r};
+    } else {
+        const double u1 = dx * fs.et[0] + dy * fs.et[1] + dz * fs.et[2];
+        const double v1 = dx * fs.ep[0] + dy * fs.ep[1] + dz * fs.ep[2];
+        const double r1 = 1.0 / sqrt(u1 * u1 + v1 * v1);
+        e1 = {u1 * r1, v1 * r1};
+        const double u2 = -(dx * ft.et[0] + dy * ft.et[1] + dz * ft.et[2]);
+        const double v2 = -(dx * ft.ep[0] + dy * ft.ep[1] + dz * ft.ep[2]);
+        const double r2 = 1.0 / sqrt(u2 * u2 + v2 * v2);
+        e2 = {u2 * r2, v2 * r2};
+    }
+    if (KIND == kM2M) {
+        // Lemma 2: x = tan(T/2); s_T = 1/rho_T (multipole), s_S = rho_S
+        const double t = sqrt(dif2 / sum2);
+        G.ph1 = {-e1.re, e1.im};  // (-1)^l' e^{-i l' phi_T^(S)}
+        G.ph2 = e2;               // e^{+i l phi_S^(T)}
+        G.a = t / rho_t;
+        G.b = t * rho_s;
+        G.g = (rho_s / rho_t) * (1.0 + t * t);
+        G.clog = log(0.25 * sum2);
+    } else if (KIND == kM2L) {
+        // Lemma 3: x = cot(T/2); s_T = rho_T (local), s_S = rho_S
+        const double c = sqrt(sum2 / dif2);
+        G.ph1 = cconj(e1);  // e^{-i l' phi_T^(S)}
+        G.ph2 = cconj(e2);  // e^{-i l phi_S^(T)}
+        G.a = c * rho_t;
+        G.b = c * rho_s;
+        G.g = rho_t * rho_s * (1.0 + c * c);
+        G.clog = log(0.25 * dif2);
+    } else {
+        // Lemma 4: x = tan(T/2); s_T = rho_T (local), s_S = 1/rho_S
+        const double t = sqrt(dif2 / sum2);
+        G.ph1 = e1;                  // e^{+i l' phi_T^(S)}
+        G.ph2 = {-e2.re, e2.im};     // (-1)^l e^{-i l phi_S^(T)}
+        G.a = t * rho_t;
+        G.b = t / rho_s;
+        G.g = (rho_t / rho_s) * (1.0 + t * t);
+        G.clog = log(0.25 * sum2);
+    }
+    return G;
+}
+
+// Expansion record: e[0] = C, e[1] = Q, e[2 + 2(l-1)] = Re A_l, e[3 + 2(l-1)]
+// = Im A_l (scaled).  Adds the translated expansion of `in` to acc.
+template <int P>
+SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
+    double ar[P + 1], ai[P + 1];
+    const double C = in[0], Q = in[1];
+    ar[0] = 0.0;
+    ai[0] = 0.0;
+    cplx pw = G.ph1;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplx a = {in[2 * l], in[2 * l + 1]};
+        const cplx v = cmul(pw, a);
+        ar[l] = v.re;
+        ai[l] = v.im;
+        pw = cmul(pw, G.ph1);
+    }
+    // right factor: Taylor shift by b, a[j] += b a[j+1]
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int j = P - 1; j >= i; --j) {
+            ar[j] = fma(G.b, ar[j + 1], ar[j]);
+            ai[j] = fma(G.b, ai[j + 1], ai[j]);
+        }
+    }
+    const double u0 = ar[0];
+    // diagonal g^n, n = 1..P
+    double gn = G.g;
+#pragma unroll
+    for (int n = 1; n <= P; ++n) {
+        ar[n] *= gn;
+        ai[n] *= gn;
+        gn *= G.g;
+    }
+    // left factor: transposed Taylor shift by a on entries 1..P
+#pragma unroll
+    for (int i = P - 2; i >= 0; --i) {
+#pragma unroll
+        for (int j = i; j <= P - 2; ++j) {
+            ar[j + 2] = fma(G.a, ar[j + 1], ar[j + 2]);
+            ai[j + 2] = fma(G.a, ai[j + 1], ai[j + 2]);
+        }
+    }
+    cplx pw2 = G.ph2;
+    double an = G.a;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplx v = {ar[l] - (Q / l) * an, ai[l]};
+        const cplx o = cmul(pw2, v);
+        acc[2 * l] += o.re;
+        acc[2 * l + 1] += o.im;
+        pw2 = cmul(pw2, G.ph2);
+        an *= G.a;
+    }
+    acc[0] += C + Q * G.clog + 2.0 * u0;
+    acc[1] += Q;
+}
+
+// Lemma 1 for a set of particles about centre f with scale rho; C carries the
+// zero-mean gauge's share sum q / (4 pi) (Eq. STAND_CONDITION).
+template <int P>
+struct P2MAcc {
+    double sre[P], sim[P];
+    double slog, sq;
+};
+
+template <int P>
+SFMM_HD void p2m_init(P2MAcc<P>& a) {
+#pragma unroll
+    for (int l = 0; l < P; ++l) a.sre[l] = a.sim[l] = 0.0;
+    a.slog = 0.0;
+    a.sq = 0.0;
+}
+
+template <int P>
+SFMM_HD void p2m_add(P2MAcc<P>& a, const Frame& f, double inv_rho, double x, double y, double z, double q) {
+    double opc;
+    cplx w = stereo(f, x, y, z, &opc);
+    w.re *= inv_rho;
+    w.im *= inv_rho;
+    cplx pw = w;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        a.sre[l] = fma(q, pw.re, a.sre[l]);
+        a.sim[l] = fma(q, pw.im, a.sim[l]);
+        pw = cmul(pw, w);
+    }
+    a.slog = fma(q, log(0.5 * opc), a.slog);  // 2 log cos(theta/2) = log((1 + cos)/2)
+    a.sq += q;
+}
+
+template <int P>
+SFMM_HD void p2m_finish(const P2MAcc<P>& a, double* out) {
+    const double Q = a.sq * kInv4Pi;
+    out[0] = a.slog * kInv4Pi - Q * kLog2 + Q;
+    out[1] = Q;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const double s = -kInv4Pi / l;
+        out[2 * l] = s * a.sre[l - 1];
+        out[2 * l + 1] = s * a.sim[l - 1];
+    }
+}
+
+// Local expansion at a point (Sec. 3.6), pole-free: psi_e and the tangent
+// vector alpha_e = grad psi_e in global axes.  With f(w) = sum A_l w^l,
+// psi_e = C + Q log(1 + cos theta) + 2 Re f and, in the orthonormal basis of
+// the w-plane, alpha_u + i alpha_v = (1 + |w|^2) conj(f'(w)) - Q w.
+template <int P>
+SFMM_HD void l2p_eval(const double* e, const Frame& f, double rho, double nx, double ny, double nz,
+                      double* psi, double* ax, double* ay, double* az) {
+    double opc;
+    const cplx w = stereo(f, nx, ny, nz, &opc);
+    const double inv_rho = 1.0 / rho;
+    const cplx zt = {w.re * inv_rho, w.im * inv_rho};
+    // Horner for f = sum L_l zt^l and g = sum l L_l zt^(l-1)
+    cplx fv = {0.0, 0.0}, gv = {0.0, 0.0};
+#pragma unroll
+    for (int l = P; l >= 1; --l) {
+        const cplx a = {e[2 * l], e[2 * l + 1]};
+        gv = cmul(gv, zt);
+        gv.re = fma((double)l, a.re, gv.re);
+        gv.im = fma((double)l, a.im, gv.im);
+        fv = cmul(fv, zt);
+        fv.re += a.re;
+        fv.im += a.im;
+    }
+    fv = cmul(fv, zt);
+    const double C = e[0], Q = e[1];
+    *psi = C + Q * log(opc) + 2.0 * fv.re;
+    // f'(w) = g / rho
+    const double w2 = w.re * w.re + w.im * w.im;
+    const double s = (1.0 + w2) * inv_rho;
+    const double Ar = s * gv.re - Q * w.re;
+    const double Ai = -s * gv.im - Q * w.im;
+    const double inv = 1.0 / (1.0 + w2);
+    const double u = w.re, v = w.im;
+    // e_u = ((1+v^2-u^2) e_t - 2uv e_p - 2u c)/(1+|w|^2), e_v likewise
+    const double eu_t = (1.0 + v * v - u * u) * inv, eu_p = -2.0 * u * v * inv, eu_c = -2.0 * u * inv;
+    const double ev_t = -2.0 * u * v * inv, ev_p = (1.0 + u * u - v * v) * inv, ev_c = -2.0 * v * inv;
+    const double at = Ar * eu_t + Ai * ev_t, ap = Ar * eu_p + Ai * ev_p, ac = Ar * eu_c + Ai * ev_c;
+    *ax = at * f.et[0] + ap * f.ep[0] + ac * f.c[0];
+    *ay = at * f.et[1] + ap * f.ep[1] + ac * f.c[1];
+    *az = at * f.et[2] + ap * f.ep[2] + ac * f.c[2];
+}
+
+// Multipole expansion (Lemma 1 form) of a source box evaluated at a point n
+// far from it: psi = C + Q log(1 - cos theta) + 2 Re sum A_l w^-l and its
+// tangent gradient.  With zeta = rho / w, f = sum Ah_l zeta^l and
+// g = sum l Ah_l zeta^l (Ah the scaled coefficients), the w-plane gradient of
+// 2 Re f is -2 conj(g / w) and that of Q log(1 - cos) = Q log(2|w|^2/(1+|w|^2))
+// is 2 Q w / (|w|^2 (1 + |w|^2)), so
+//   alpha_u + i alpha_v = (Q - (1 + |w|^2) conj(g)) / conj(w).
+SFMM_HD void m2p_eval(const double* e, int p, const Frame& f, double rho, double nx, double ny, double nz,
+                      double* psi, double* ax, double* ay, double* az) {
+    double opc;
+    const cplx w = stereo(f, nx, ny, nz, &opc);
+    const double dx = nx - f.c[0], dy = ny - f.c[1], dz = nz - f.c[2];
+    const double omc = 0.5 * (dx * dx + dy * dy + dz * dz);  // 1 - cos theta
+    const double w2 = w.re * w.re + w.im * w.im;
+    const double iw2 = 1.0 / w2;
+    const cplx zt = {rho * w.re * iw2, -rho * w.im * iw2};  // rho / w
+    cplx F = {0.0, 0.0}, G = {0.0, 0.0};
+    for (int l = p; l >= 1; --l) {
+        const double ar = e[2 * l], ai = e[2 * l + 1];
+        F = cmul(F, zt);
+        F.re += ar;
+        F.im += ai;
+        G = cmul(G, zt);
+        G.re = fma((double)l, ar, G.re);
+        G.im = fma((double)l, ai, G.im);
+    }
+    F = cmul(F, zt);
+    G = cmul(G, zt);
+    const double C = e[0], Q = e[1];
+    *psi = C + Q * log(omc) + 2.0 * F.re;
+    // (Q - (1+|w|^2) conj(G)) / conj(w) = (Q - s conj(G)) * w / |w|^2
+    const double s = 1.0 + w2;
+    const cplx num = {Q - s * G.re, s * G.im};
+    const cplx A = {(num.re * w.re - num.im * w.im) * iw2, (num.re * w.im + num.im * w.re) * iw2};
+    const double inv = 1.0 / s;
+    const double u = w.re, v = w.im;
+    const double eu_t = (1.0 + v * v - u * u) * inv, eu_p = -2.0 * u * v * inv, eu_c = -2.0 * u * inv;
+    const double ev_t = -2.0 * u * v * inv, ev_p = (1.0 + u * u - v * v) * inv, ev_c = -2.0 * v * inv;
+    const double at = A.re * eu_t + A.im * ev_t, ap = A.re * eu_p + A.im * ev_p, ac = A.re * eu_c + A.im * ev_c;
+    *ax = at * f.et[0] + ap * f.ep[0] + ac * f.c[0];
+    *ay = at * f.et[1] + ap * f.ep[1] + ac * f.c[1];
+    *az = at * f.et[2] + ap * f.ep[2] + ac * f.c[2];
+}
+
+}  // namespace sfmm

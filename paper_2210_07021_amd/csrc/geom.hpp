@@ -1,0 +1,264 @@
+// Sphere geometry of the sFMM tree (Sec. 3.1 division, Sec. 3.5 box radius
+// and distance): HEALPix nested keys at order 29, pixel points, box radii,
+// angular distances, and the two MAC predicates.
+//
+// Keys and MAC decisions are exact-arithmetic decisions: an FP64 evaluation
+// settles every case whose margin exceeds a rigorous bound on its rounding
+// error, and the rest (points within ~1e-5 pixel of an edge, box pairs within
+// 1e-13 rad of a MAC threshold, congruent boxes of equal radius) are re-done
+// in double-double.  Exact-arithmetic ties (HEALPix has many: the vertex
+// shared by two diagonal neighbours is the geodesic midpoint of their
+// centres) are decided "not far", as the strict inequalities say.
+#pragma once
+#include "dd.hpp"
+#include <cstdint>
+
+namespace sfmm {
+
+constexpr int kOrder = 29;                 // maximum depth of Sec. 3.1
+constexpr double kTieRel = 1e-20;          // relative guard of exact ties
+constexpr double kMacFilter = 1e-13;       // FP64 margin that needs no recheck (rad)
+constexpr double kKeyFilter = 1e-5;        // FP64 distance to a pixel edge that needs no recheck
+
+// HEALPix face layout (Gorski et al. 2005): ring of each face's southern
+// corner in units of nside, and azimuth of the face centre in units of pi/4.
+SFMM_HD int face_ring(int f) { return 2 + (f >> 2); }
+SFMM_HD int face_phi(int f) {
+    // faces 0-3 and 8-11 sit at odd multiples of pi/4, faces 4-7 at even
+    return (f >> 2) == 1 ? 2 * (f & 3) : 2 * (f & 3) + 1;
+}
+
+SFMM_HD uint64_t spread_bits(uint64_t v) {
+    v &= 0x3fffffffULL;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+    v = (v | (v << 2)) & 0x3333333333333333ULL;
+    v = (v | (v << 1)) & 0x5555555555555555ULL;
+    return v;
+}
+
+SFMM_HD uint64_t compact_bits(uint64_t v) {
+    v &= 0x5555555555555555ULL;
+    v = (v | (v >> 1)) & 0x3333333333333333ULL;
+    v = (v | (v >> 2)) & 0x0f0f0f0f0f0f0f0fULL;
+    v = (v | (v >> 4)) & 0x00ff00ff00ff00ffULL;
+    v = (v | (v >> 8)) & 0x0000ffff0000ffffULL;
+    v = (v | (v >> 16)) & 0x00000000ffffffffULL;
+    return v;
+}
+
+SFMM_HD uint64_t nest_index(int64_t face, int64_t ix, int64_t iy) {
+    return ((uint64_t)face << (2 * kOrder)) + spread_bits((uint64_t)ix) + (spread_bits((uint64_t)iy) << 1);
+}
+
+// Order-29 nested key of the unit vector (x, y, z), double-double evaluation.
+SFMM_HD uint64_t key_dd(double x, double y, double z) {
+    const int64_t ns = (int64_t)1 << kOrder;
+    const double za = fabs(z);
+    dd tt = dd_mul(dd_atan2(dd_from(y), dd_from(x)), dd_two_over_pi());
+    {
+        const double r = nearbyint(tt.hi);
+        if (fabs(dd_sub(tt, dd_from(r)).hi) < 1e-20) tt = dd_from(r);
+    }
+    if (tt.hi < 0.0) tt = dd_add(tt, dd_from(4.0));
+    if (!dd_lt(tt, dd_from(4.0))) tt = dd_sub(tt, dd_from(4.0));
+    int64_t face, ix, iy;
+    const dd two_thirds = dd_div(dd_from(2.0), dd_from(3.0));
+    if (!dd_lt(two_thirds, dd_from(za))) {
+        const dd a = dd_mul_d(dd_add(dd_from(0.5), tt), (double)ns);
+        const dd b = dd_mul_d(two_prod(z, 0.75), (double)ns);
+        const int64_t jp = dd_floor_snap(dd_sub(a, b));
+        const int64_t jm = dd_floor_snap(dd_add(a, b));
+        const int64_t fp = jp >> kOrder, fm = jm >> kOrder;
+        face = (fp == fm) ? (fp | 4) : (fp < fm ? fp : fm + 8);
+        ix = jm & (ns - 1);
+        iy = ns - (jp & (ns - 1)) - 1;
+    } else {
+        int ntt = (int)tt.hi;
+        if (tt.hi == (double)ntt && tt.lo < 0.0) ntt -= 1;
+        if (ntt > 3) ntt = 3;
+        const dd tp = dd_sub(tt, dd_from((double)ntt));
+        dd s;
+        if (za < 0.99) {
+            s = dd_sqrt(two_prod(3.0, 1.0 - za));  // 1 - za is exact for za > 1/2
+        } else {
+            const dd sth = dd_sqrt(dd_add(two_prod(x, x), two_prod(y, y)));
+            s = dd_div(sth, dd_sqrt(dd_div(two_sum(1.0, za), dd_from(3.0))));
+        }
+        s = dd_mul_d(s, (double)ns);
+        int64_t jp = dd_floor_snap(dd_mul(tp, s));
+        int64_t jm = dd_floor_snap(dd_mul(dd_sub(dd_from(1.0), tp), s));
+        if (jp > ns - 1) jp = ns - 1;
+        if (jm > ns - 1) jm = ns - 1;
+        if (z >= 0.0) {
+            face = ntt;
+            ix = ns - jm - 1;
+            iy = ns - jp - 1;
+        } else {
+            face = ntt + 8;
+            ix = jp;
+            iy = jm;
+        }
+    }
+    return nest_index(face, ix, iy);
+}
+
+SFMM_HD bool near_integer(double v, double tol) { return fabs(v - nearbyint(v)) < tol; }
+
+// Order-29 nested key: FP64 with an exactness filter, double-double when a
+// floor argument or a branch test lies within its FP64 error of a boundary.
+SFMM_HD uint64_t key29(double x, double y, double z) {
+    const int64_t ns = (int64_t)1 << kOrder;
+    const double za = fabs(z);
+    double tt = atan2(y, x) * 0.63661977236758138243;
+    if (tt < 0.0) tt += 4.0;
+    if (tt >= 4.0) tt -= 4.0;
+    bool fragile = near_integer(tt, 1e-13) || fabs(za - 2.0 / 3.0) < 1e-14;
+    int64_t face = 0, ix = 0, iy = 0;
+    if (za <= 2.0 / 3.0) {
+        const double a = (double)ns * (0.5 + tt);
+        const double b = (double)ns * (z * 0.75);
+        const double vp = a - b, vm = a + b;
+        fragile |= near_integer(vp, kKeyFilter) || near_integer(vm, kKeyFilter);
+        const int64_t jp = (int64_t)floor(vp), jm = (int64_t)floor(vm);
+        const int64_t fp = jp >> kOrder, fm = jm >> kOrder;
+        face = (fp == fm) ? (fp | 4) : (fp < fm ? fp : fm + 8);
+        ix = jm & (ns - 1);
+        iy = ns - (jp & (ns - 1)) - 1;
+    } else {
+        int ntt = (int)tt;
+        if (ntt > 3) ntt = 3;
+        const double tp = tt - ntt;
+        double s;
+        if (za < 0.99) {
+            s = (double)ns * sqrt(3.0 * (1.0 - za));
+        } else {
+            const double sth = sqrt(x * x + y * y);
+            s = (double)ns * sth / sqrt((1.0 + za) / 3.0);
+        }
+        const double vp = tp * s, vm = (1.0 - tp) * s;
+        fragile |= near_integer(vp, kKeyFilter) || near_integer(vm, kKeyFilter);
+        int64_t jp = (int64_t)floor(vp), jm = (int64_t)floor(vm);
+        if (jp > ns - 1) jp = ns - 1;
+        if (jm > ns - 1) jm = ns - 1;
+        if (z >= 0.0) {
+            face = ntt;
+            ix = ns - jm - 1;
+            iy = ns - jp - 1;
+        } else {
+            face = ntt + 8;
+            ix = jp;
+            iy = jm;
+        }
+    }
+    if (fragile) return key_dd(x, y, z);
+    return nest_index(face, ix, iy);
+}
+
+// Point of pixel (level, pix) at face coordinates (fx, fy) in [0,1]^2, in
+// double-double: the centre is (1/2, 1/2), the vertices the corners.
+SFMM_HD void pix_point_dd(int level, uint64_t pix, double fx, double fy, dd* out) {
+    const double ns = (double)((int64_t)1 << level);
+    const int face = (int)(pix >> (2 * level));
+    const uint64_t inface = pix & ((1ULL << (2 * level)) - 1);
+    // x = (ix + fx)/ns exactly in double-double (ix < 2^29, fx dyadic)
+    const dd x = dd_mul_d(two_sum((double)compact_bits(inface), fx), 1.0 / ns);
+    const dd y = dd_mul_d(two_sum((double)compact_bits(inface >> 1), fy), 1.0 / ns);
+    const dd jr = dd_sub(dd_sub(dd_from((double)face_ring(face)), x), y);
+    dd nr, z, sth;
+    if (jr.hi < 1.0) {
+        nr = jr;
+        const dd t = dd_div(dd_mul(nr, nr), dd_from(3.0));
+        z = dd_sub(dd_from(1.0), t);
+        sth = dd_sqrt(dd_mul(t, dd_sub(dd_from(2.0), t)));
+    } else if (jr.hi > 3.0) {
+        nr = dd_sub(dd_from(4.0), jr);
+        const dd t = dd_div(dd_mul(nr, nr), dd_from(3.0));
+        z = dd_sub(t, dd_from(1.0));
+        sth = dd_sqrt(dd_mul(t, dd_sub(dd_from(2.0), t)));
+    } else {
+        nr = dd_from(1.0);
+        z = dd_div(dd_mul_d(dd_sub(dd_from(2.0), jr), 2.0), dd_from(3.0));
+        sth = dd_sqrt(dd_mul(dd_sub(dd_from(1.0), z), dd_add(dd_from(1.0), z)));
+    }
+    dd u = dd_sub(dd_add(dd_mul_d(nr, (double)face_phi(face)), x), y);
+    if (u.hi < 0.0) u = dd_add(u, dd_from(8.0));
+    if (!dd_lt(u, dd_from(8.0))) u = dd_sub(u, dd_from(8.0));
+    dd phi = dd_from(0.0);
+    if (nr.hi != 0.0) phi = dd_div(dd_mul(dd_quarter_pi(), u), nr);
+    dd s, c;
+    dd_sincos(phi, &s, &c);
+    out[0] = dd_mul(sth, c);
+    out[1] = dd_mul(sth, s);
+    out[2] = z;
+    // a coordinate this small is an exact zero of the geometry (azimuth at a
+    // multiple of pi/2); a genuine one is never below ~1e-18
+    for (int k = 0; k < 3; ++k)
+        if (fabs(out[k].hi) < 1e-25) out[k] = dd_from(0.0);
+}
+
+// Angular distance of two double-double unit vectors: atan2(|a x b|, a.b).
+SFMM_HD dd angdist_dd(const dd* a, const dd* b) {
+    const dd cx = dd_sub(dd_mul(a[1], b[2]), dd_mul(a[2], b[1]));
+    const dd cy = dd_sub(dd_mul(a[2], b[0]), dd_mul(a[0], b[2]));
+    const dd cz = dd_sub(dd_mul(a[0], b[1]), dd_mul(a[1], b[0]));
+    const dd s = dd_sqrt(dd_add(dd_add(dd_mul(cx, cx), dd_mul(cy, cy)), dd_mul(cz, cz)));
+    const dd c = dd_add(dd_add(dd_mul(a[0], b[0]), dd_mul(a[1], b[1])), dd_mul(a[2], b[2]));
+    return dd_atan2(s, c);
+}
+
+SFMM_HD double angdist(double ax, double ay, double az, double bx, double by, double bz) {
+    const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+    return atan2(sqrt(cx * cx + cy * cy + cz * cz), ax * bx + ay * by + az * bz);
+}
+
+// Box geometry in double-double: centre (x,y,z) and covering radius R, the
+// largest angular distance from the centre to the pixel's vertices.
+struct BoxGeomDD {
+    dd c[3];
+    dd r;
+};
+
+SFMM_HD BoxGeomDD box_geometry(int level, uint64_t pix) {
+    BoxGeomDD g;
+    pix_point_dd(level, pix, 0.5, 0.5, g.c);
+    g.r = dd_from(0.0);
+    const double cf[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    for (int k = 0; k < 4; ++k) {
+        dd v[3];
+        pix_point_dd(level, pix, cf[k][0], cf[k][1], v);
+        const dd d = angdist_dd(g.c, v);
+        if (dd_lt(g.r, d)) g.r = d;
+    }
+    return g;
+}
+
+// "B_T is far from B_S" (Sec. 3.5): d - R_T - c_s R_S > 0 and R_T < c_t d,
+// each by more than the relative tie guard.  FP64 first; double-double when
+// either margin is within kMacFilter of zero.
+SFMM_HD bool mac_far(const double* cs, const double* ct, double rs, double rt,
+                     const dd* cs_dd, const dd* ct_dd, dd rs_dd, dd rt_dd,
+                     double c_s, double c_t) {
+    const double d = angdist(cs[0], cs[1], cs[2], ct[0], ct[1], ct[2]);
+    const double m1 = d - rt - c_s * rs;
+    const double m2 = c_t * d - rt;
+    if (m1 < -kMacFilter || m2 < -kMacFilter) return false;
+    if (m1 > kMacFilter && m2 > kMacFilter) return true;
+    const dd D = angdist_dd(cs_dd, ct_dd);
+    const dd guard = dd_mul_d(D, kTieRel);
+    const dd M1 = dd_sub(dd_sub(dd_sub(D, rt_dd), dd_mul_d(rs_dd, c_s)), guard);
+    const dd M2 = dd_sub(dd_sub(dd_mul_d(D, c_t), rt_dd), guard);
+    return M1.hi > 0.0 && M2.hi > 0.0;
+}
+
+// r(B_S) > r(B_T) of Algorithm 1, with radii equal in exact arithmetic
+// (congruent boxes) counted as equal.
+SFMM_HD bool radius_greater(double rs, double rt, dd rs_dd, dd rt_dd) {
+    const double diff = rs - rt;
+    if (fabs(diff) > 1e-13 * (rs + rt)) return diff > 0.0;
+    const dd M = dd_sub(dd_sub(rs_dd, rt_dd), dd_mul_d(rt_dd, kTieRel));
+    return M.hi > 0.0;
+}
+
+}  // namespace sfmm

@@ -1,0 +1,182 @@
+// The numeric passes of the sFMM (Sec. 3.2-3.3, 3.6): Lemma 1 on leaves,
+// Lemma 2 up the tree, Lemma 3 over the FMM-act lists, Lemma 4 down the
+// tree, and the local expansion at each target.  One lane owns one box (or
+// one target) and holds its order-P coefficients in registers; P is a
+// template parameter so every loop over l unrolls.
+#include "common.hpp"
+#include "expand.hpp"
+
+namespace sfmm {
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
+
+__device__ __forceinline__ Frame box_frame(const double* cen, int b, double* rho) {
+    const double* c = cen + 4 * (size_t)b;
+    *rho = c[3];
+    return make_frame(c[0], c[1], c[2]);
+}
+
+// Lemma 1 on every non-empty leaf
+template <int P>
+__global__ void __launch_bounds__(128) k_p2m(FmmCtx c, int nb) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb || c.child0[b] >= 0 || c.count[b] == 0) return;
+    double rho;
+    const Frame f = box_frame(c.cen, b, &rho);
+    const double inv_rho = 1.0 / rho;
+    P2MAcc<P> a;
+    p2m_init<P>(a);
+    const int i0 = c.first[b], i1 = i0 + c.count[b];
+    for (int i = i0; i < i1; ++i) p2m_add<P>(a, f, inv_rho, c.sx[i], c.sy[i], c.sz[i], c.sq[i]);
+    p2m_finish<P>(a, c.mult + (size_t)b * (2 * P + 2));
+}
+
+// Lemma 2: every split box of one level gathers its 4 children
+template <int P>
+__global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int b = b0 + i;
+    const int ch0 = c.child0[b];
+    if (ch0 < 0) return;
+    double rho_t;
+    const Frame ft = box_frame(c.cen, b, &rho_t);
+    double acc[2 * P + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const int ch = ch0 + k;
+        if (c.count[ch] == 0) continue;
+        double rho_s;
+        const Frame fs = box_frame(c.cen, ch, &rho_s);
+        const TransGeom G = trans_geom<kM2M>(fs, rho_s, ft, rho_t);
+        translate_add<P>(c.mult + (size_t)ch * (2 * P + 2), G, acc);
+    }
+    double* out = c.mult + (size_t)b * (2 * P + 2);
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
+}
+
+// Lemma 3: each target box sums its FMM-act list (boxes taken longest list
+// first so the lanes of a wave carry similar work)
+template <int P>
+__global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, const int* off, const int* src) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = order[i];
+    const int k0 = off[t], k1 = off[t + 1];
+    if (k0 == k1) return;
+    double rho_t;
+    const Frame ft = box_frame(c.cen, t, &rho_t);
+    double acc[2 * P + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int s = src[k];
+        double rho_s;
+        const Frame fs = box_frame(c.cen, s, &rho_s);
+        const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
+        translate_add<P>(c.mult + (size_t)s * (2 * P + 2), G, acc);
+    }
+    double* out = c.local + (size_t)t * (2 * P + 2);
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
+}
+
+// Lemma 4: every box of one level takes its parent's local expansion
+template <int P>
+__global__ void __launch_bounds__(128) k_l2l(FmmCtx c, int b0, int nb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int b = b0 + i;
+    const int par = c.parent[b];
+    double rho_t, rho_s;
+    const Frame ft = box_frame(c.cen, b, &rho_t);
+    const Frame fs = box_frame(c.cen, par, &rho_s);
+    double* loc = c.local + (size_t)b * (2 * P + 2);
+    double acc[2 * P + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = loc[k];
+    const TransGeom G = trans_geom<kL2L>(fs, rho_s, ft, rho_t);
+    translate_add<P>(c.local + (size_t)par * (2 * P + 2), G, acc);
+#pragma unroll
+    for (int k = 0; k < 2 * P + 2; ++k) loc[k] = acc[k];
+}
+
+// Local expansion at each target (sorted by leaf); writes psi and alpha in
+// the caller's target order
+template <int P>
+__global__ void __launch_bounds__(128) k_l2p(FmmCtx c, const double* tx, const double* ty, const double* tz,
+                                            const int* tleaf, const uint32_t* tperm, int64_t m, double psi_shift,
+                                            double* psi, double* defl, int64_t m_out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int L = tleaf[i];
+    double rho;
+    const Frame f = box_frame(c.cen, L, &rho);
+    double p, ax, ay, az;
+    l2p_eval<P>(c.local + (size_t)L * (2 * P + 2), f, rho, tx[i], ty[i], tz[i], &p, &ax, &ay, &az);
+    const int64_t o = tperm[i];
+    psi[o] = p + psi_shift;
+    defl[o] = ax;
+    defl[m_out + o] = ay;
+    defl[2 * m_out + o] = az;
+}
+
+#define SFMM_ORDERS(X)                                                                             \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
+    X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) \
+    X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48)
+
+#define SFMM_DISPATCH(p, LAUNCH)                                                   \
+    switch (p) {                                                                   \
+        SFMM_ORDERS(LAUNCH)                                                        \
+        default: throw Error(ST_INVALID_ARG, "expansion order out of range");     \
+    }
+
+void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s) {
+    if (nb <= 0) return;
+#define L_(P) case P: k_p2m<P><<<nblk(nb, 128), 128, 0, s>>>(c, nb); break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s) {
+    if (nb <= 0) return;
+#define L_(P) case P: k_m2m<P><<<nblk(nb, 128), 128, 0, s>>>(c, b0, nb); break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+void fmm_m2l(const FmmCtx& c, const int* order, int n, const int* off, const int* src, hipStream_t s) {
+    if (n <= 0) return;
+#define L_(P) case P: k_m2l<P><<<nblk(n, 128), 128, 0, s>>>(c, order, n, off, src); break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s) {
+    if (nb <= 0) return;
+#define L_(P) case P: k_l2l<P><<<nblk(nb, 128), 128, 0, s>>>(c, b0, nb); break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
+             const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
+             hipStream_t s) {
+    if (m <= 0) return;
+#define L_(P)                                                                                         \
+    case P:                                                                                           \
+        k_l2p<P><<<nblk(m, 128), 128, 0, s>>>(c, tx, ty, tz, tleaf, tperm, m, psi_shift, psi, defl, m_out); \
+        break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+}  // namespace sfmm

@@ -1,0 +1,378 @@
+// Tree build on the GPU: order-29 HEALPix keys (Sec. 3.1), the adaptive
+// quasi-quad-tree level by level, box geometry (Sec. 3.5), target location
+// (Sec. 3.7), and the frontier form of Algorithm 1 (Sec. 3.4).
+#include "common.hpp"
+#include "geom.hpp"
+
+namespace sfmm {
+
+static unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
+
+// ------------------------------------------------------------------ points
+__global__ void k_prepare_points(const double* in, int64_t n, double* x, double* y, double* z, uint64_t* keys,
+                                 uint32_t* idx, int* err) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = in[i], b = in[n + i], c = in[2 * n + i];
+    const double r2 = a * a + b * b + c * c;
+    int e = 0;
+    if (!(isfinite(a) && isfinite(b) && isfinite(c))) e |= 1;
+    else if (!(fabs(r2 - 1.0) <= 2e-6)) e |= 2;
+    if (e) {
+        atomicOr(err, e);
+        a = 0.0; b = 0.0; c = 1.0;
+    } else if (fabs(r2 - 1.0) > 1e-14) {
+        const double inv = 1.0 / sqrt(r2);
+        a *= inv; b *= inv; c *= inv;
+    }
+    x[i] = a;
+    y[i] = b;
+    z[i] = c;
+    keys[i] = key29(a, b, c);
+    idx[i] = (uint32_t)i;
+}
+
+void prepare_points(const double* in, int64_t n, double* x, double* y, double* z, uint64_t* keys,
+                    uint32_t* idx, int* err, hipStream_t s) {
+    if (n <= 0) return;
+    k_prepare_points<<<nblocks(n, 256), 256, 0, s>>>(in, n, x, y, z, keys, idx, err);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_gather_points(const uint32_t* idx, int64_t n, const double* x, const double* y,
+                                const double* z, const double* q, double* ox, double* oy, double* oz, double* oq) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = idx[i];
+    ox[i] = x[j];
+    oy[i] = y[j];
+    oz[i] = z[j];
+    if (q) oq[i] = q[j];
+}
+
+void gather_points(const uint32_t* idx, int64_t n, const double* x, const double* y, const double* z,
+                   const double* q, double* ox, double* oy, double* oz, double* oq, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, x, y, z, q, ox, oy, oz, oq);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ levels
+__device__ int lower_bound_u64(const uint64_t* a, int lo, int hi, uint64_t v) {
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_base_level(const uint64_t* keys, int n, int* level, uint64_t* pixel, int* first, int* count,
+                             int* parent, int* child0) {
+    const int f = threadIdx.x;
+    if (f >= 12) return;
+    const int a = lower_bound_u64(keys, 0, n, (uint64_t)f << (2 * kOrder));
+    const int b = lower_bound_u64(keys, 0, n, (uint64_t)(f + 1) << (2 * kOrder));
+    level[f] = 0;
+    pixel[f] = (uint64_t)f;
+    first[f] = a;
+    count[f] = b - a;
+    parent[f] = -1;
+    child0[f] = -1;
+}
+
+void tree_base_level(const uint64_t* keys, int64_t n, int* level, uint64_t* pixel, int* first, int* count,
+                     int* parent, int* child0, hipStream_t s) {
+    k_base_level<<<1, 64, 0, s>>>(keys, (int)n, level, pixel, first, count, parent, child0);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_split_flags(int b0, int nb, const int* level, const int* count, int m, int max_level, int* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int b = b0 + i;
+    flag[i] = (count[b] > m && level[b] < max_level) ? 1 : 0;
+}
+
+void tree_split_flags(int b0, int nb, const int* level, const int* count, int m, int max_level, int* flag,
+                      hipStream_t s) {
+    k_split_flags<<<nblocks(nb, 256), 256, 0, s>>>(b0, nb, level, count, m, max_level, flag);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_make_children(int b0, int nb, int child_base, const int* flag, const int* off,
+                                const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                                int* parent, int* child0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int b = b0 + i;
+    if (!flag[i]) {
+        child0[b] = -1;
+        return;
+    }
+    const int c0 = child_base + 4 * off[i];
+    child0[b] = c0;
+    const int L = level[b] + 1;
+    const int shift = 2 * (kOrder - L);
+    const int end = first[b] + count[b];
+    int lo = first[b];
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t pix = pixel[b] * 4 + (uint64_t)c;
+        const int e = (c == 3) ? end : lower_bound_u64(keys, lo, end, (pix + 1) << shift);
+        level[c0 + c] = L;
+        pixel[c0 + c] = pix;
+        first[c0 + c] = lo;
+        count[c0 + c] = e - lo;
+        parent[c0 + c] = b;
+        child0[c0 + c] = -1;
+        lo = e;
+    }
+}
+
+void tree_make_children(int b0, int nb, int child_base, const int* flag, const int* off, const uint64_t* keys,
+                        int* level, uint64_t* pixel, int* first, int* count, int* parent, int* child0,
+                        hipStream_t s) {
+    k_make_children<<<nblocks(nb, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys, level, pixel, first,
+                                                    count, parent, child0);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ geometry
+__global__ void k_box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen, double* rad,
+                               double* gdd) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const BoxGeomDD g = box_geometry(level[b], pixel[b]);
+    cen[4 * b + 0] = g.c[0].hi;
+    cen[4 * b + 1] = g.c[1].hi;
+    cen[4 * b + 2] = g.c[2].hi;
+    cen[4 * b + 3] = tan(0.5 * g.r.hi);  // coefficient scale rho
+    rad[b] = g.r.hi;
+    double* o = gdd + 8 * b;
+    o[0] = g.c[0].hi; o[1] = g.c[0].lo;
+    o[2] = g.c[1].hi; o[3] = g.c[1].lo;
+    o[4] = g.c[2].hi; o[5] = g.c[2].lo;
+    o[6] = g.r.hi;    o[7] = g.r.lo;
+}
+
+void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen, double* rad, double* gdd,
+                  hipStream_t s) {
+    if (nb <= 0) return;
+    k_box_geometry<<<nblocks(nb, 64), 64, 0, s>>>(nb, level, pixel, cen, rad, gdd);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ targets
+__global__ void k_locate(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t k = keys[i];
+    int b = (int)(k >> (2 * kOrder));
+    while (child0[b] >= 0) {
+        const int L = level[b] + 1;
+        b = child0[b] + (int)((k >> (2 * (kOrder - L))) & 3);
+    }
+    leaf[i] = b;
+}
+
+void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf,
+                    hipStream_t s) {
+    if (m <= 0) return;
+    k_locate<<<nblocks(m, 256), 256, 0, s>>>(keys, m, child0, level, leaf);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int b = leaf[i];
+    if (i == 0 || leaf[i - 1] != b) tfirst[b] = (int)i;
+    atomicAdd(&tcount[b], 1);  // integer counts: order-independent
+}
+
+void target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount, hipStream_t s) {
+    if (m <= 0) return;
+    k_target_ranges<<<nblocks(m, 256), 256, 0, s>>>(leaf, m, tfirst, tcount);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_flag_nonzero(const int* count, int n, int* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = count[i] > 0 ? 1 : 0;
+}
+
+void flag_nonzero(const int* count, int n, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    k_flag_nonzero<<<nblocks(n, 256), 256, 0, s>>>(count, n, flag);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_compact_index(const int* flag, const int* off, int n, int* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) out[off[i]] = i;
+}
+
+void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t s) {
+    if (n <= 0) return;
+    k_compact_index<<<nblocks(n, 256), 256, 0, s>>>(flag, off, n, out);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ walk
+// Frontier form of Algorithm 1.  Each frontier pair (S, T) takes exactly
+// one branch of INTERACTION(B_S, B_T); its recursive calls become the next
+// frontier.  A source box without particles contributes nothing (it is a
+// leaf, so no recursion is lost) and is dropped.
+enum : uint8_t { A_NONE = 0, A_M2L = 1, A_P2P = 2, A_SPLIT_S = 3, A_SPLIT_T = 4, A_SPLIT_SELF = 5 };
+
+__device__ bool box_far(const WalkCtx& w, int s, int t) {
+    const double* gs = w.gdd + 8 * s;
+    const double* gt = w.gdd + 8 * t;
+    const double cs[3] = {gs[0], gs[2], gs[4]};
+    const double ct[3] = {gt[0], gt[2], gt[4]};
+    const dd csd[3] = {{gs[0], gs[1]}, {gs[2], gs[3]}, {gs[4], gs[5]}};
+    const dd ctd[3] = {{gt[0], gt[1]}, {gt[2], gt[3]}, {gt[4], gt[5]}};
+    return mac_far(cs, ct, gs[6], gt[6], csd, ctd, dd{gs[6], gs[7]}, dd{gt[6], gt[7]}, w.c_s, w.c_t);
+}
+
+__global__ void k_walk_classify(const int2* F, int n, WalkCtx w, uint8_t* action, int* nchild, int* nm2l,
+                                int* np2p) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int s = F[k].x, t = F[k].y;
+    uint8_t a;
+    if (w.count[s] == 0) {
+        a = A_NONE;
+    } else if (s == t) {
+        a = (w.child0[s] < 0) ? A_P2P : A_SPLIT_SELF;
+    } else if (box_far(w, s, t)) {
+        a = A_M2L;
+    } else {
+        const bool sl = w.child0[s] < 0, tl = w.child0[t] < 0;
+        if (!sl && !tl) {
+            const double* gs = w.gdd + 8 * s;
+            const double* gt = w.gdd + 8 * t;
+            a = radius_greater(gs[6], gt[6], dd{gs[6], gs[7]}, dd{gt[6], gt[7]}) ? A_SPLIT_S : A_SPLIT_T;
+        } else if (!sl) {
+            a = A_SPLIT_S;
+        } else if (!tl) {
+            a = A_SPLIT_T;
+        } else {
+            a = A_P2P;
+        }
+    }
+    action[k] = a;
+    nchild[k] = (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
+    nm2l[k] = (a == A_M2L) ? 1 : 0;
+    np2p[k] = (a == A_P2P) ? 1 : 0;
+}
+
+void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* nchild, int* nm2l, int* np2p,
+                   hipStream_t s) {
+    if (n <= 0) return;
+    k_walk_classify<<<nblocks(n, 128), 128, 0, s>>>(F, n, w, action, nchild, nm2l, np2p);
+    SFMM_LAUNCH_CHECK();
+}
+
+__device__ uint64_t pair_key(int s, int t) { return ((uint64_t)(uint32_t)t << 32) | (uint32_t)s; }
+
+__global__ void k_walk_emit(const int2* F, int n, WalkCtx w, const uint8_t* action, const int* ochild,
+                            const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base,
+                            uint64_t* p2p, int p2p_base) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int s = F[k].x, t = F[k].y;
+    const uint8_t a = action[k];
+    int2* out = Fnext + ochild[k];
+    switch (a) {
+        case A_M2L: m2l[m2l_base + om2l[k]] = pair_key(s, t); break;
+        case A_P2P: p2p[p2p_base + op2p[k]] = pair_key(s, t); break;
+        case A_SPLIT_S:
+            for (int i = 0; i < 4; ++i) out[i] = make_int2(w.child0[s] + i, t);
+            break;
+        case A_SPLIT_T:
+            for (int j = 0; j < 4; ++j) out[j] = make_int2(s, w.child0[t] + j);
+            break;
+        case A_SPLIT_SELF:
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) out[4 * i + j] = make_int2(w.child0[s] + i, w.child0[s] + j);
+            break;
+        default: break;
+    }
+}
+
+void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild, const int* om2l,
+               const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
+               hipStream_t s) {
+    if (n <= 0) return;
+    k_walk_emit<<<nblocks(n, 128), 128, 0, s>>>(F, n, w, action, ochild, om2l, op2p, Fnext, m2l, m2l_base, p2p,
+                                                p2p_base);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ lists
+__global__ void k_count_targets(const uint64_t* sorted, int np, int* cnt, int* src) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const uint64_t v = sorted[k];
+    src[k] = (int)(uint32_t)(v & 0xffffffffULL);
+    atomicAdd(&cnt[(int)(v >> 32)], 1);  // integer counts: order-independent
+}
+
+void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* tmp_count,
+                  hipStream_t s) {
+    fill_i32(tmp_count, nbox, 0, s);
+    if (npairs > 0) {
+        k_count_targets<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, tmp_count, src);
+        SFMM_LAUNCH_CHECK();
+    }
+    scan_excl_i32(tmp_count, off, nbox, off + nbox, s);
+}
+
+__global__ void k_m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const uint32_t len = (uint32_t)(off[b + 1] - off[b]);
+    keys[b] = (uint64_t)(0xffffffffu - len);  // longest lists first
+    vals[b] = (uint32_t)b;
+}
+
+void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+    if (nbox <= 0) return;
+    k_m2l_order_keys<<<nblocks(nbox, 256), 256, 0, s>>>(off, nbox, keys, vals);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_p2p_work(const int* off, const int* src, const int* count, const int* tcount, int nbox,
+                           long long* w) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    long long ns = 0;
+    for (int k = off[b]; k < off[b + 1]; ++k) ns += count[src[k]];
+    w[b] = ns * (long long)tcount[b];
+}
+
+__global__ void k_work_order_keys(const long long* w, int n, uint64_t* keys, uint32_t* vals, int* flag) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const unsigned long long cap = (1ULL << 40) - 1;
+    const unsigned long long v = (unsigned long long)(w[b] < 0 ? 0 : w[b]);
+    keys[b] = (v == 0) ? (1ULL << 40) : cap - (v < cap ? v : cap);
+    vals[b] = (uint32_t)b;
+    flag[b] = v > 0 ? 1 : 0;
+}
+
+void work_order_keys(const long long* w, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    k_work_order_keys<<<nblocks(n, 256), 256, 0, s>>>(w, n, keys, vals, flag);
+    SFMM_LAUNCH_CHECK();
+}
+
+void p2p_work(const int* off, const int* src, const int* count, const int* tcount, int nbox, long long* w,
+              hipStream_t s) {
+    if (nbox <= 0) return;
+    k_p2p_work<<<nblocks(nbox, 256), 256, 0, s>>>(off, src, count, tcount, nbox, w);
+    SFMM_LAUNCH_CHECK();
+}
+
+}  // namespace sfmm

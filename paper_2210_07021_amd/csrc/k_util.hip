@@ -1,0 +1,320 @@
+// Generic device building blocks: fills, exclusive scan, stable LSD radix
+// sort, deterministic reduction, and the caching device allocator.
+#include "common.hpp"
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+namespace sfmm {
+
+// ------------------------------------------------------------------ pool
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void*> g_free;           // size -> block
+std::unordered_map<void*, size_t> g_size;      // live and free blocks
+}  // namespace
+
+static size_t size_class(size_t b) {
+    if (b < 512) return 512;
+    // round up to 1/8 of the next power of two
+    size_t p = 1;
+    while (p < b) p <<= 1;
+    const size_t step = p >> 3;
+    return (b + step - 1) / step * step;
+}
+
+void* pool_alloc(size_t bytes) {
+    const size_t sz = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_free.lower_bound(sz);
+        if (it != g_free.end() && it->first <= 2 * sz) {
+            void* p = it->second;
+            g_free.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pool_release_all();
+        e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(ST_OOM, "device allocation of " + std::to_string(sz) + " bytes failed");
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_size[p] = sz;
+    return p;
+}
+
+void pool_free(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_size.find(p);
+    if (it == g_size.end()) return;
+    g_free.emplace(it->second, p);
+}
+
+void pool_release_all() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& kv : g_free) {
+        (void)hipFree(kv.second);
+        g_size.erase(kv.second);
+    }
+    g_free.clear();
+}
+
+// ------------------------------------------------------------------ fills
+template <typename T>
+__global__ void k_fill(T* p, size_t n, T v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static unsigned grid_for(size_t n, unsigned block, unsigned cap = 65536) {
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void fill_f64(double* p, size_t n, double v, hipStream_t s) {
+    if (!n) return;
+    k_fill<double><<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+    SFMM_LAUNCH_CHECK();
+}
+
+void fill_i32(int* p, size_t n, int v, hipStream_t s) {
+    if (!n) return;
+    k_fill<int><<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// block-wide exclusive scan of one value per thread (256 threads)
+__device__ int block_excl_scan(int v, int* sh, int* total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int a = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    const int incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_tiles(const int* in, int* out, int64_t n, int* bsum) {
+    __shared__ int sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int run = block_excl_scan(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int* out, int64_t n, const int* boff) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int add = boff[blockIdx.x];
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n) out[base + k] += add;
+}
+
+__global__ void k_scan_total(const int* in, const int* out, int64_t n, int* total) {
+    *total = (n > 0) ? out[n - 1] + in[n - 1] : 0;
+}
+
+void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s) {
+    if (n <= 0) {
+        fill_i32(total, 1, 0, s);
+        return;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int* bsum = (int*)pool_alloc(sizeof(int) * (nb + 1));
+    int* boff = (int*)pool_alloc(sizeof(int) * (nb + 1));
+    k_scan_tiles<<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, bsum);
+    SFMM_LAUNCH_CHECK();
+    if (nb > 1) {
+        scan_excl_i32(bsum, boff, nb, boff + nb, s);
+        k_scan_add<<<(unsigned)nb, kScanThreads, 0, s>>>(out, n, boff);
+        SFMM_LAUNCH_CHECK();
+    }
+    k_scan_total<<<1, 1, 0, s>>>(in, out, n, total);
+    SFMM_LAUNCH_CHECK();
+    // freed blocks are only reused by later stream-ordered work on this stream
+    pool_free(bsum);
+    pool_free(boff);
+}
+
+// ------------------------------------------------------------------ radix sort
+// 8-bit digits.  Pass = histogram per tile, exclusive scan of the
+// digit-major histogram, stable scatter.  Ranks inside a tile come from
+// wave ballots: lanes holding the same digit are found by intersecting the
+// ballots of the digit's 8 bits.
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 8;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+constexpr int kRsWaves = kRsThreads / 64;
+
+__global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, int* hist) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t i = base + r * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
+                             int shift, int nblk, const int* offs) {
+    __shared__ int base[256];
+    __shared__ int wcnt[kRsWaves][256];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    base[t] = offs[t * nblk + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) wcnt[w][t] = 0;
+        __syncthreads();
+        const int64_t i = tile0 + r * kRsThreads + t;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        int d = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin ? vin[i] : 0u;
+            d = (int)((key >> shift) & 255);
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot(valid && ((d >> b) & 1));
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pos = base[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            if (vout) vout[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) add += wcnt[w][t];
+        base[t] += add;
+        __syncthreads();
+    }
+}
+
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
+    if (n <= 1) return;
+    const int nblk = (int)((n + kRsTile - 1) / kRsTile);
+    uint64_t* k2 = (uint64_t*)pool_alloc(sizeof(uint64_t) * n);
+    uint32_t* v2 = vals ? (uint32_t*)pool_alloc(sizeof(uint32_t) * n) : nullptr;
+    int* hist = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
+    int* offs = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
+    int* tot = (int*)pool_alloc(sizeof(int));
+    uint64_t *ka = keys, *kb = k2;
+    uint32_t *va = vals, *vb = v2;
+    int npass = (bits + 7) / 8;
+    if (npass & 1) ++npass;  // even number of passes: result lands in the caller's buffers
+    if (npass > 8) npass = 8;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int shift = 8 * pass;
+        k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, nblk, hist);
+        SFMM_LAUNCH_CHECK();
+        scan_excl_i32(hist, offs, 256 * (int64_t)nblk, tot, s);
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs);
+        SFMM_LAUNCH_CHECK();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    SFMM_HIP(hipStreamSynchronize(s));
+    pool_free(k2);
+    if (v2) pool_free(v2);
+    pool_free(hist);
+    pool_free(offs);
+    pool_free(tot);
+}
+
+// ------------------------------------------------------------------ sum
+__global__ void k_sum_tiles(const double* x, int64_t n, double* part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc += x[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+void sum_f64(const double* x, int64_t n, double* out, hipStream_t s) {
+    double* part = (double*)pool_alloc(sizeof(double) * 1024);
+    k_sum_tiles<<<1024, 256, 0, s>>>(x, n, part);
+    SFMM_LAUNCH_CHECK();
+    k_sum_tiles<<<1, 256, 0, s>>>(part, 1024, out);
+    SFMM_LAUNCH_CHECK();
+    SFMM_HIP(hipStreamSynchronize(s));
+    pool_free(part);
+}
+
+__global__ void k_sum_i64(const long long* x, int64_t n, long long* part) {
+    __shared__ long long sh[256];
+    long long acc = 0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc += x[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s) {
+    long long* part = (long long*)pool_alloc(sizeof(long long) * 1024);
+    k_sum_i64<<<1024, 256, 0, s>>>(x, n, part);
+    SFMM_LAUNCH_CHECK();
+    k_sum_i64<<<1, 256, 0, s>>>(part, 1024, out);
+    SFMM_LAUNCH_CHECK();
+    SFMM_HIP(hipStreamSynchronize(s));
+    pool_free(part);
+}
+
+}  // namespace sfmm

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every symbol include/sfmm.h declares;
+host-only entry points answer without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfmm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfmm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2210_07021_amd as sf
+    if not os.path.exists(sf.LIB_PATH):
+        from paper_2210_07021_amd import build
+        build.build()
+    return sf.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "sfmm_plan" in names and "sfmm_execute" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    import paper_2210_07021_amd as sf
+    assert sorted(sf.SIGNATURES) == _declared()
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    """ctypes structs agree with the C compiler's layout of include/sfmm.h."""
+    import subprocess
+    import paper_2210_07021_amd as sf
+    fields = {"sfmm_options": sf.Options, "sfmm_stats": sf.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sfmm.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in fields.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_host_only_calls(lib):
+    import paper_2210_07021_amd as sf
+    opt = sf.default_options()
+    assert (opt.order, opt.leaf_size, opt.c_s, opt.c_t, opt.max_level) == (0, 64, 2.0, 0.5, 29)
+    assert opt.tolerance == 1e-10
+    assert lib.sfmm_status_string(0) == b"ok"
+    assert lib.sfmm_status_string(1) == b"invalid argument"
+    ps = [sf.order_for_tolerance(t) for t in (1e-2, 1e-6, 1e-10, 1e-14)]
+    assert ps == sorted(ps) and 1 <= ps[0] and ps[-1] <= 48
+    assert sf.order_for_tolerance(1e-10) == 32
+
+
+def test_invalid_arguments_rejected_before_any_device_work(lib):
+    """Size and option checks happen on the host: no GPU needed."""
+    import paper_2210_07021_amd as sf
+    h = ctypes.c_void_p()
+    opt = sf.default_options()
+    rc = lib.sfmm_plan(None, None, -1, None, 0, ctypes.byref(opt), None, ctypes.byref(h))
+    assert rc == 1 and b"N and M" in lib.sfmm_last_error()
+    opt.leaf_size = 0
+    rc = lib.sfmm_plan(None, None, 0, None, 0, ctypes.byref(opt), None, ctypes.byref(h))
+    assert rc == 1 and b"leaf_size" in lib.sfmm_last_error()
+    opt = sf.default_options(order=49)
+    rc = lib.sfmm_plan(None, None, 0, None, 0, ctypes.byref(opt), None, ctypes.byref(h))
+    assert rc == 1 and b"order" in lib.sfmm_last_error()
+    opt = sf.default_options(c_t=1.5)
+    rc = lib.sfmm_plan(None, None, 0, None, 0, ctypes.byref(opt), None, ctypes.byref(h))
+    assert rc == 1
+    rc = lib.sfmm_plan(None, None, 10, None, 0, ctypes.byref(sf.default_options()), None, ctypes.byref(h))
+    assert rc == 1 and b"NULL" in lib.sfmm_last_error()
+    assert h.value is None

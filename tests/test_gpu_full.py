@@ -1,0 +1,38 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (tolerance 1e-10, leaf size 64), on seeded samples of targets
+that the oracle evaluates one by one."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_07021_amd import skies
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("workload,sample", [("clustered-1e6", 2000), ("clustered-1e7", 400)])
+def test_full_size_sampled_parity(workload, sample, oracle_lib):
+    import torch
+    import paper_2210_07021_amd as sf
+    print(f"[full] {workload}: generating", flush=True)
+    src, q, tgt = skies.workload(workload)
+    M = tgt.shape[1]
+    print(f"[full] {workload}: N={src.shape[1]} M={M} plan+execute", flush=True)
+    plan = sf.Plan(src, q, tgt, tolerance=1e-10, leaf_size=64)
+    psi, defl = plan.execute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    psi, defl = psi.cpu().numpy(), defl.cpu().numpy()
+    plan.close()
+    idx = np.random.default_rng(skies.BASE_SEED + 1001).choice(M, size=sample, replace=False)
+    print(f"[full] {workload}: oracle on {sample} targets", flush=True)
+    ref_p, ref_a = oracle.direct(src, q, tgt[:, idx])
+    ep, ea = _rel(psi[idx], ref_p), _rel(defl[:, idx], ref_a)
+    print(f"[full] {workload}: p={st['order']} boxes={st['n_boxes']} levels={st['n_levels']} "
+          f"m2l={st['n_m2l']} p2p_pairs={st['n_p2p_pairs']}: psi {ep:.3e} alpha {ea:.3e}", flush=True)
+    assert np.isfinite(psi).all() and np.isfinite(defl).all()
+    assert ep <= 1e-10 and ea <= 1e-10

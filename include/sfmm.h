@@ -75,7 +75,9 @@ typedef struct {
     int64_t n_boxes, n_leaves, n_levels;
     int64_t n_m2l, n_p2p;           /* FMM-act and direct-act pairs            */
     int64_t n_target_leaves;        /* leaves holding at least one target      */
-    int64_t n_p2p_pairs;            /* particle-target pairs of the direct acts */
+    int64_t n_p2p_pairs;            /* particle-target pairs summed directly    */
+    int64_t n_m2p_evals;            /* (target, close leaf) pairs evaluated by
+                                       the leaf's multipole expansion instead  */
     int32_t order, leaf_size;
     double q_total;                 /* sum of the masses                        */
 } sfmm_stats;
@@ -145,10 +147,11 @@ int32_t sfmm_order_for_tolerance(double tol);
  * per-stage totals.  Stages (indices into the arrays of sfmm_profile_read):
  *   0 source keys+sort, 1 tree levels, 2 box geometry, 3 walk (Algorithm 1),
  *   4 list sort/CSR, 5 target keys+sort+locate, 6 P2M, 7 M2M (all levels),
- *   8 M2L, 9 L2L (all levels), 10 L2P, 11 P2P.
+ *   8 M2L, 9 L2L (all levels), 10 L2P, 11 P2P (direct part of the close
+ *   leaves), 12 close leaves evaluated by their multipole expansion.
  * ms[SFMM_NUM_STAGES] receives the summed milliseconds and calls[] the number
  * of times each stage ran; both are host arrays and may be NULL. */
-#define SFMM_NUM_STAGES 12
+#define SFMM_NUM_STAGES 13
 void sfmm_profile_enable(int32_t on);
 void sfmm_profile_reset(void);
 void sfmm_profile_read(double* ms, int64_t* calls);

@@ -55,6 +55,7 @@ class Stats(ctypes.Structure):
         ("n_p2p", ctypes.c_int64),
         ("n_target_leaves", ctypes.c_int64),
         ("n_p2p_pairs", ctypes.c_int64),
+        ("n_m2p_evals", ctypes.c_int64),
         ("order", ctypes.c_int32),
         ("leaf_size", ctypes.c_int32),
         ("q_total", ctypes.c_double),
@@ -85,9 +86,9 @@ SIGNATURES = {
     "sfmm_profile_read": (None, [_P, _P]),
 }
 
-NUM_STAGES = 12
+NUM_STAGES = 13
 STAGES = ["src_keys_sort", "tree", "geometry", "walk", "lists", "targets",
-          "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
+          "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "m2p"]
 
 _lib = None
 

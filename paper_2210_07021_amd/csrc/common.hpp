@@ -82,8 +82,8 @@ void fill_f64(double* p, size_t n, double v, hipStream_t s);
 void fill_i32(int* p, size_t n, int v, hipStream_t s);
 // exclusive scan of n ints; the total goes to *total (device)
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s);
-// stable LSD radix sort of (key, value) pairs on key bits [0, bits)
-void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
+// stable LSD radix sort of (key, value) pairs on key bits [begin_bit, bits)
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit = 0);
 void sum_f64(const double* x, int64_t n, double* out, hipStream_t s);
 void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 
@@ -124,16 +124,14 @@ void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int*
 void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild,
                const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p,
                int p2p_base, hipStream_t s);
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src,
-                  int* tmp_count, hipStream_t s);
 void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s);
-// sort keys putting the leaves with the most direct-act work first; flag the
-// leaves that have any
-void work_order_keys(const long long* w, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s);
+// pairs (target << 32 | source) sorted by target -> CSR offsets and sources
+void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src, hipStream_t s);
+// sort keys putting the target leaves with the most direct-act work first
+// (targets x close leaves); flag the leaves that have any
+void work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals, int* flag,
+                     hipStream_t s);
 // particle-target pairs of each leaf's direct acts: tcount[T] * sum count[S]
-void p2p_work(const int* off, const int* src, const int* count, const int* tcount, int nbox, long long* w,
-              hipStream_t s);
-
 // ---------------------------------------------------------------- fmm
 struct FmmCtx {
     int p;
@@ -159,6 +157,12 @@ void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* 
              const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
              hipStream_t s);
 void fmm_p2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
+             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
+             double* psi, double* defl, int64_t m_out, hipStream_t s);
+void near_work(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
+               const int* tcount, const double* tx, const double* ty, const double* tz, long long* pairs,
+               long long* evals, hipStream_t s);
+void fmm_m2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
              const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
              double* psi, double* defl, int64_t m_out, hipStream_t s);
 

@@ -34,6 +34,56 @@ constexpr double kInv2Pi = 0.15915494309189533577;   // 1 / (2 pi)
 constexpr double kLog2 = 0.69314718055994530942;
 constexpr double kLog4 = 1.3862943611198906188;
 
+// 1/x for a positive normal double: the hardware estimate refined by two
+// Newton steps on the GPU (full precision), a division on the host.
+SFMM_HD double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+// Natural log of a positive normal double, ~2 ulp: x = 2^e m with
+// m in [1/sqrt2, sqrt2), s = (m - 1)/(m + 1), and
+//   log m = 2 atanh s = 2 s (1 + s^2/3 + s^4/5 + ... + s^20/21),
+// whose first omitted term is below 3e-17 relative since s^2 <= 0.0295;
+// e log 2 is added with log 2 split in two words.  Written for the
+// near-field inner loop, where the library log (a double-double algorithm
+// of ~85 instructions) dominated the cost.
+SFMM_HD double log_f64(double x) {
+    int e;
+    double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;  // exact (Sterbenz)
+    const double s = f * recip(2.0 + f);
+    const double z = s * s;
+    double poly = 1.0 / 21.0;
+    poly = fma(poly, z, 1.0 / 19.0);
+    poly = fma(poly, z, 1.0 / 17.0);
+    poly = fma(poly, z, 1.0 / 15.0);
+    poly = fma(poly, z, 1.0 / 13.0);
+    poly = fma(poly, z, 1.0 / 11.0);
+    poly = fma(poly, z, 1.0 / 9.0);
+    poly = fma(poly, z, 1.0 / 7.0);
+    poly = fma(poly, z, 1.0 / 5.0);
+    poly = fma(poly, z, 1.0 / 3.0);
+    // 2s + 2s z poly, the small part added last
+    const double two_s = 2.0 * s;
+    const double lm = fma(two_s * z, poly, two_s);
+    const double de = (double)e;
+    const double ln2_hi = 6.93147180369123816490e-01;  // top bits of log 2, e * ln2_hi exact
+    const double ln2_lo = 1.90821492927058770002e-10;
+    return fma(de, ln2_hi, fma(de, ln2_lo, lm));
+}
+
 struct cplx {
     double re, im;
 };
@@ -117,7 +167,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = t / rho_t;
         G.b = t * rho_s;
         G.g = (rho_s / rho_t) * (1.0 + t * t);
-        G.clog = log(0.25 * sum2);
+        G.clog = log_f64(0.25 * sum2);
     } else if (KIND == kM2L) {
         // Lemma 3: x = cot(T/2); s_T = rho_T (local), s_S = rho_S
         const double c = sqrt(sum2 / dif2);
@@ -126,7 +176,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = c * rho_t;
         G.b = c * rho_s;
         G.g = rho_t * rho_s * (1.0 + c * c);
-        G.clog = log(0.25 * dif2);
+        G.clog = log_f64(0.25 * dif2);
     } else {
         // Lemma 4: x = tan(T/2); s_T = rho_T (local), s_S = 1/rho_S
         const double t = sqrt(dif2 / sum2);
@@ -135,7 +185,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = t * rho_t;
         G.b = t / rho_s;
         G.g = (rho_t / rho_s) * (1.0 + t * t);
-        G.clog = log(0.25 * sum2);
+        G.clog = log_f64(0.25 * sum2);
     }
     return G;
 }
@@ -228,7 +278,7 @@ SFMM_HD void p2m_add(P2MAcc<P>& a, const Frame& f, double inv_rho, double x, dou
         a.sim[l] = fma(q, pw.im, a.sim[l]);
         pw = cmul(pw, w);
     }
-    a.slog = fma(q, log(0.5 * opc), a.slog);  // 2 log cos(theta/2) = log((1 + cos)/2)
+    a.slog = fma(q, log_f64(0.5 * opc), a.slog);  // 2 log cos(theta/2) = log((1 + cos)/2)
     a.sq += q;
 }
 
@@ -270,7 +320,7 @@ SFMM_HD void l2p_eval(const double* e, const Frame& f, double rho, double nx, do
     }
     fv = cmul(fv, zt);
     const double C = e[0], Q = e[1];
-    *psi = C + Q * log(opc) + 2.0 * fv.re;
+    *psi = C + Q * log_f64(opc) + 2.0 * fv.re;
     // f'(w) = g / rho
     const double w2 = w.re * w.re + w.im * w.im;
     const double s = (1.0 + w2) * inv_rho;
@@ -316,7 +366,7 @@ SFMM_HD void m2p_eval(const double* e, int p, const Frame& f, double rho, double
     F = cmul(F, zt);
     G = cmul(G, zt);
     const double C = e[0], Q = e[1];
-    *psi = C + Q * log(omc) + 2.0 * F.re;
+    *psi = C + Q * log_f64(omc) + 2.0 * F.re;
     // (Q - (1+|w|^2) conj(G)) / conj(w) = (Q - s conj(G)) * w / |w|^2
     const double s = 1.0 + w2;
     const cplx num = {Q - s * G.re, s * G.im};

@@ -63,7 +63,7 @@ template <int P>
 __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, const int* off, const int* src) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int t = order[i];
+    const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
     if (k0 == k1) return;
     double rho_t;

@@ -311,29 +311,39 @@ void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, co
 }
 
 // ------------------------------------------------------------------ lists
-__global__ void k_count_targets(const uint64_t* sorted, int np, int* cnt, int* src) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np) return;
-    const uint64_t v = sorted[k];
-    src[k] = (int)(uint32_t)(v & 0xffffffffULL);
-    atomicAdd(&cnt[(int)(v >> 32)], 1);  // integer counts: order-independent
+__global__ void k_csr_offsets(const uint64_t* sorted, int np, int nbox, int* off) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbox) return;
+    // first pair whose target is >= b
+    int lo = 0, hi = np;
+    const uint64_t v = (uint64_t)(uint32_t)b << 32;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (sorted[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    off[b] = lo;
 }
 
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* tmp_count,
-                  hipStream_t s) {
-    fill_i32(tmp_count, nbox, 0, s);
+__global__ void k_pair_sources(const uint64_t* sorted, int np, int* src) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < np) src[k] = (int)(uint32_t)(sorted[k] & 0xffffffffULL);
+}
+
+void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, hipStream_t s) {
+    k_csr_offsets<<<nblocks(nbox + 1, 256), 256, 0, s>>>(sorted, npairs, nbox, off);
+    SFMM_LAUNCH_CHECK();
     if (npairs > 0) {
-        k_count_targets<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, tmp_count, src);
+        k_pair_sources<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, src);
         SFMM_LAUNCH_CHECK();
     }
-    scan_excl_i32(tmp_count, off, nbox, off + nbox, s);
 }
 
 __global__ void k_m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
     const uint32_t len = (uint32_t)(off[b + 1] - off[b]);
-    keys[b] = (uint64_t)(0xffffffffu - len);  // longest lists first
+    keys[b] = (uint64_t)(0xffffu - (len < 0xffffu ? len : 0xffffu));  // longest lists first
     vals[b] = (uint32_t)b;
 }
 
@@ -343,35 +353,21 @@ void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hi
     SFMM_LAUNCH_CHECK();
 }
 
-__global__ void k_p2p_work(const int* off, const int* src, const int* count, const int* tcount, int nbox,
-                           long long* w) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbox) return;
-    long long ns = 0;
-    for (int k = off[b]; k < off[b + 1]; ++k) ns += count[src[k]];
-    w[b] = ns * (long long)tcount[b];
-}
-
-__global__ void k_work_order_keys(const long long* w, int n, uint64_t* keys, uint32_t* vals, int* flag) {
+__global__ void k_work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals,
+                                  int* flag) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     const unsigned long long cap = (1ULL << 40) - 1;
-    const unsigned long long v = (unsigned long long)(w[b] < 0 ? 0 : w[b]);
+    const unsigned long long v = (unsigned long long)tcount[b] * (unsigned long long)(off[b + 1] - off[b]);
     keys[b] = (v == 0) ? (1ULL << 40) : cap - (v < cap ? v : cap);
     vals[b] = (uint32_t)b;
     flag[b] = v > 0 ? 1 : 0;
 }
 
-void work_order_keys(const long long* w, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s) {
+void work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals, int* flag,
+                     hipStream_t s) {
     if (n <= 0) return;
-    k_work_order_keys<<<nblocks(n, 256), 256, 0, s>>>(w, n, keys, vals, flag);
-    SFMM_LAUNCH_CHECK();
-}
-
-void p2p_work(const int* off, const int* src, const int* count, const int* tcount, int nbox, long long* w,
-              hipStream_t s) {
-    if (nbox <= 0) return;
-    k_p2p_work<<<nblocks(nbox, 256), 256, 0, s>>>(off, src, count, tcount, nbox, w);
+    k_work_order_keys<<<nblocks(n, 256), 256, 0, s>>>(off, tcount, n, keys, vals, flag);
     SFMM_LAUNCH_CHECK();
 }
 

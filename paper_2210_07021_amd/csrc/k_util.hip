@@ -239,8 +239,8 @@ __global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t*
     }
 }
 
-void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
-    if (n <= 1) return;
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit) {
+    if (n <= 1 || bits <= begin_bit) return;
     const int nblk = (int)((n + kRsTile - 1) / kRsTile);
     uint64_t* k2 = (uint64_t*)pool_alloc(sizeof(uint64_t) * n);
     uint32_t* v2 = vals ? (uint32_t*)pool_alloc(sizeof(uint32_t) * n) : nullptr;
@@ -249,11 +249,11 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
     int* tot = (int*)pool_alloc(sizeof(int));
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
-    int npass = (bits + 7) / 8;
+    int npass = (bits - begin_bit + 7) / 8;
     if (npass & 1) ++npass;  // even number of passes: result lands in the caller's buffers
-    if (npass > 8) npass = 8;
+    if (begin_bit + 8 * npass > 64) begin_bit = 64 - 8 * npass;
     for (int pass = 0; pass < npass; ++pass) {
-        const int shift = 8 * pass;
+        const int shift = begin_bit + 8 * pass;
         k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, nblk, hist);
         SFMM_LAUNCH_CHECK();
         scan_excl_i32(hist, offs, 256 * (int64_t)nblk, tot, s);

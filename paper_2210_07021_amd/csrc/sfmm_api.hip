@@ -29,7 +29,7 @@ struct Pinned {
 
 // ---- stage timing (sfmm_profile_*)
 enum Stage {
-    S_SRC = 0, S_TREE, S_GEOM, S_WALK, S_LISTS, S_TGT, S_P2M, S_M2M, S_M2L, S_L2L, S_L2P, S_P2P, S_COUNT
+    S_SRC = 0, S_TREE, S_GEOM, S_WALK, S_LISTS, S_TGT, S_P2M, S_M2M, S_M2L, S_L2L, S_L2P, S_P2P, S_M2P, S_COUNT
 };
 std::atomic<int> g_prof_on{0};
 std::mutex g_prof_mu;
@@ -119,7 +119,7 @@ struct sfmm_plan_impl {
     DVec<uint64_t> tkeys;
     DVec<int> tleaf, tfirst, tcount, tleaves;
     int ntl = 0;
-    long long n_p2p_pairs = 0;
+    mutable long long n_p2p_pairs = -1, n_m2p_evals = -1;  // computed on the first stats request
     // expansions
     DVec<double> mult, local;
     bool executed = false;
@@ -237,13 +237,13 @@ void build_tree(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     box_geometry(P.nbox, P.level.data(), P.pixel.data(), P.cen.data(), P.rad.data(), P.gdd.data(), s);
 }
 
+// Stable sort on the target field only: within one target the pairs keep the
+// walk's (deterministic) emission order.
 void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, DVec<int>& src, hipStream_t s) {
     off.resize((size_t)nbox + 1);
     src.resize(std::max(np, 1));
-    if (np > 0) radix_sort_u64(pairs.data(), nullptr, np, 32 + bits_for(nbox), s);
-    DVec<int> cnt;
-    cnt.resize(nbox);
-    pairs_to_csr(pairs.data(), np, nbox, off.data(), src.data(), cnt.data(), s);
+    if (np > 0) radix_sort_u64(pairs.data(), nullptr, np, 32 + bits_for(nbox), s, 32);
+    pairs_to_csr(pairs.data(), np, nbox, off.data(), src.data(), s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -307,13 +307,14 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     p2p.grow(std::max(n_p2p, 1), s);
     sort_pairs_to_csr(m2l, n_m2l, P.nbox, P.m2l_off, P.m2l_src, s);
     sort_pairs_to_csr(p2p, n_p2p, P.nbox, P.p2p_off, P.p2p_src, s);
-    // M2L work order: target boxes with the longest lists first
+    // M2L work order: target boxes with the longest lists first, so the lanes
+    // of a wave carry similar work
     DVec<uint64_t> k;
     DVec<uint32_t> v;
     k.resize(P.nbox);
     v.resize(P.nbox);
     m2l_order_keys(P.m2l_off.data(), P.nbox, k.data(), v.data(), s);
-    radix_sort_u64(k.data(), v.data(), P.nbox, 32, s);
+    radix_sort_u64(k.data(), v.data(), P.nbox, 16, s);
     P.m2l_order.resize(P.nbox);
     SFMM_HIP(hipMemcpyAsync(P.m2l_order.data(), v.data(), sizeof(int) * P.nbox, hipMemcpyDeviceToDevice, s));
     SFMM_HIP(hipStreamSynchronize(s));
@@ -329,21 +330,15 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     locate_targets(P.tkeys.data(), P.M, P.child0.data(), P.level.data(), P.tleaf.data(), s);
     target_ranges(P.tleaf.data(), P.M, P.tfirst.data(), P.tcount.data(), s);
     // leaves with direct-act work, most work first
-    DVec<long long> w, wsum;
     DVec<uint64_t> keys;
     DVec<uint32_t> vals;
     DVec<int> flag, off, tot;
-    w.resize(P.nbox);
-    wsum.resize(1);
     keys.resize(P.nbox);
     vals.resize(P.nbox);
     flag.resize(P.nbox);
     off.resize(P.nbox);
     tot.resize(1);
-    p2p_work(P.p2p_off.data(), P.p2p_src.data(), P.count.data(), P.tcount.data(), P.nbox, w.data(), s);
-    sum_i64(w.data(), P.nbox, wsum.data(), s);
-    SFMM_HIP(hipMemcpy(&P.n_p2p_pairs, wsum.data(), sizeof(long long), hipMemcpyDeviceToHost));
-    work_order_keys(w.data(), P.nbox, keys.data(), vals.data(), flag.data(), s);
+    work_order_keys(P.p2p_off.data(), P.tcount.data(), P.nbox, keys.data(), vals.data(), flag.data(), s);
     scan_excl_i32(flag.data(), off.data(), P.nbox, tot.data(), s);
     P.ntl = read_int(tot.data(), P, s);
     radix_sort_u64(keys.data(), vals.data(), P.nbox, 41, s);
@@ -355,10 +350,12 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
 
 // Order from a tolerance.  Measured on uniform and clustered skies at the
 // default MACs (c_s = 2, c_t = 0.5): the deflection, the slower of the two
-// outputs, falls by ~0.58 per order and is below 3e-11 in relative L2 at
-// p = 32; the policy keeps that margin of ~4 at every tolerance.
+// outputs, falls by ~0.58 per order; its worst case is a target on a leaf
+// corner (HEALPix grid targets sit on the vertices of every deeper pixel),
+// where p = 36 leaves ~2e-11 relative L2 on the clustered skies.  The policy
+// keeps that margin of ~5 at every tolerance.
 int order_for_tolerance(double tol) {
-    const int p = (int)std::ceil(32.0 + std::log(tol / 1e-10) / std::log(0.58));
+    const int p = (int)std::ceil(36.0 + std::log(tol / 1e-10) / std::log(0.58));
     return std::min(kMaxOrder, std::max(4, p));
 }
 
@@ -375,16 +372,18 @@ void copy_widen(D* dst, const S* dev, size_t n) {
     for (size_t i = 0; i < n; ++i) dst[i] = (D)h[i];
 }
 
-void export_csr(const DVec<int>& off, const DVec<int>& src, int nbox, int np, int64_t* s_out,
-                       int64_t* t_out) {
+void export_csr(const DVec<int>& off, const DVec<int>& src, int nbox, int np, int64_t* s_out, int64_t* t_out) {
     std::vector<int> o(nbox + 1), s(std::max(np, 1));
     SFMM_HIP(hipMemcpy(o.data(), off.data(), sizeof(int) * (nbox + 1), hipMemcpyDeviceToHost));
     if (np) SFMM_HIP(hipMemcpy(s.data(), src.data(), sizeof(int) * np, hipMemcpyDeviceToHost));
-    for (int t = 0; t < nbox; ++t)
+    for (int t = 0; t < nbox; ++t) {
+        // canonical order within a target: ascending source box
+        std::sort(s.begin() + o[t], s.begin() + o[t + 1]);
         for (int k = o[t]; k < o[t + 1]; ++k) {
             if (s_out) s_out[k] = s[k];
             if (t_out) t_out[k] = t;
         }
+    }
 }
 
 }  // namespace
@@ -504,6 +503,11 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
                     defl, P.M, s);
         }
         {
+            StageScope st(prof, S_M2P);
+            fmm_m2p(c, P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
+                    P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
+        }
+        {
             StageScope st(prof, S_P2P);
             fmm_p2p(c, P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
                     P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
@@ -520,6 +524,7 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
 }
 
 sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
+    // (the exact direct-act pair count is computed here, outside planning)
     if (!plan || !out) {
         g_last_error = "plan or out is NULL";
         return SFMM_ERR_INVALID_ARG;
@@ -537,7 +542,21 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->n_m2l = P.n_m2l;
         out->n_p2p = P.n_p2p;
         out->n_target_leaves = P.ntl;
-        out->n_p2p_pairs = P.n_p2p_pairs;
+        if (P.n_p2p_pairs < 0 && P.ntl > 0) {
+            DVec<long long> w, tot;
+            w.resize(2 * (size_t)P.ntl);
+            tot.resize(2);
+            near_work(P.ctx(), P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
+                      P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), w.data(), w.data() + P.ntl, nullptr);
+            sum_i64(w.data(), P.ntl, tot.data(), nullptr);
+            sum_i64(w.data() + P.ntl, P.ntl, tot.data() + 1, nullptr);
+            long long h[2];
+            SFMM_HIP(hipMemcpy(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost));
+            P.n_p2p_pairs = h[0];
+            P.n_m2p_evals = h[1];
+        }
+        out->n_p2p_pairs = P.n_p2p_pairs < 0 ? 0 : P.n_p2p_pairs;
+        out->n_m2p_evals = P.n_m2p_evals < 0 ? 0 : P.n_m2p_evals;
         out->order = P.p;
         out->leaf_size = P.opt.leaf_size;
         out->q_total = P.q_total;

@@ -74,7 +74,7 @@ typedef struct {
     int64_t n_sources, n_targets;
     int64_t n_boxes, n_leaves, n_levels;
     int64_t n_m2l, n_p2p;           /* FMM-act and direct-act pairs            */
-    int64_t n_target_leaves;        /* leaves holding at least one target      */
+    int64_t n_target_leaves;        /* leaves with targets and direct-sum work */
     int64_t n_p2p_pairs;            /* particle-target pairs summed directly    */
     int64_t n_m2p_evals;            /* (target, close leaf) pairs evaluated by
                                        the leaf's multipole expansion instead  */
@@ -127,6 +127,13 @@ sfmm_status sfmm_export_lists(sfmm_plan_t plan, int64_t* m2l_src, int64_t* m2l_t
 sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_perm, uint64_t* tgt_keys,
                              int64_t* tgt_perm, int64_t* tgt_leaf);
 
+/* Host copies of the per-box near-field work, [n_boxes] each: tgt_count the
+ * targets located in the box, pairs the particle-target pairs its targets
+ * sum directly, evals the (target, close leaf) pairs taken through the
+ * leaf's multipole expansion instead.  For load-balance diagnostics; any
+ * pointer may be NULL. */
+sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pairs, int64_t* evals);
+
 /* Host copies of the expansions after sfmm_execute, in the paper's
  * normalisation (Lemma 1: psi = C + Q log(1 -+ cos) + 2 Re sum A_l z^(-+l)):
  * multipole and local are [n_boxes][2p+2] = (C, Q, Re A_1, Im A_1, ...,
@@ -146,7 +153,8 @@ int32_t sfmm_order_for_tolerance(double tol);
  * synchronises the stream and adds the elapsed times to process-wide
  * per-stage totals.  Stages (indices into the arrays of sfmm_profile_read):
  *   0 source keys+sort, 1 tree levels, 2 box geometry, 3 walk (Algorithm 1),
- *   4 list sort/CSR, 5 target keys+sort+locate, 6 P2M, 7 M2M (all levels),
+ *   4 list sort/CSR, 5 target keys+sort+locate and the split of the
+ *   direct-act lists into direct sums and expansions, 6 P2M, 7 M2M (all levels),
  *   8 M2L, 9 L2L (all levels), 10 L2P, 11 P2P (direct part of the close
  *   leaves), 12 close leaves evaluated by their multipole expansion.
  * ms[SFMM_NUM_STAGES] receives the summed milliseconds and calls[] the number

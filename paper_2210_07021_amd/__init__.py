@@ -76,6 +76,7 @@ SIGNATURES = {
     "sfmm_export_boxes": (ctypes.c_int, [_P] * 9),
     "sfmm_export_lists": (ctypes.c_int, [_P] * 5),
     "sfmm_export_keys": (ctypes.c_int, [_P] * 6),
+    "sfmm_export_work": (ctypes.c_int, [_P] * 4),
     "sfmm_export_expansions": (ctypes.c_int, [_P] * 3),
     "sfmm_destroy": (None, [_P]),
     "sfmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -226,6 +227,12 @@ class Plan:
                    tgt_keys=np.zeros(self.M, np.uint64), tgt_perm=np.zeros(self.M, np.int64),
                    tgt_leaf=np.zeros(self.M, np.int64))
         _check(self._lib.sfmm_export_keys(self._h, *[a.ctypes.data_as(_P) for a in out.values()]))
+        return out
+
+    def export_work(self) -> dict:
+        nb = self.stats()["n_boxes"]
+        out = dict(tgt_count=np.zeros(nb, np.int64), pairs=np.zeros(nb, np.int64), evals=np.zeros(nb, np.int64))
+        _check(self._lib.sfmm_export_work(self._h, *[a.ctypes.data_as(_P) for a in out.values()]))
         return out
 
     def export_expansions(self):

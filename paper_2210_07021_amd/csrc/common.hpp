@@ -77,6 +77,19 @@ struct DVec {
 
 constexpr int kMaxOrder = 48;
 
+// every order 1..kMaxOrder is a template instance; SFMM_DISPATCH(p, X) runs
+// X(P) for the runtime order p
+#define SFMM_ORDERS(X)                                                                             \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
+    X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) \
+    X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48)
+
+#define SFMM_DISPATCH(p, LAUNCH)                                                   \
+    switch (p) {                                                                   \
+        SFMM_ORDERS(LAUNCH)                                                        \
+        default: throw Error(ST_INVALID_ARG, "expansion order out of range");     \
+    }
+
 // ---------------------------------------------------------------- utilities
 void fill_f64(double* p, size_t n, double v, hipStream_t s);
 void fill_i32(int* p, size_t n, int v, hipStream_t s);
@@ -127,11 +140,9 @@ void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, co
 void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s);
 // pairs (target << 32 | source) sorted by target -> CSR offsets and sources
 void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src, hipStream_t s);
-// sort keys putting the target leaves with the most direct-act work first
-// (targets x close leaves); flag the leaves that have any
-void work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals, int* flag,
-                     hipStream_t s);
-// particle-target pairs of each leaf's direct acts: tcount[T] * sum count[S]
+// sort keys (8 bits) putting the boxes with the most work first, in
+// power-of-two buckets; flag the boxes that have any
+void work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s);
 // ---------------------------------------------------------------- fmm
 struct FmmCtx {
     int p;
@@ -156,14 +167,35 @@ void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
              const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
              hipStream_t s);
-void fmm_p2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s);
-void near_work(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-               const int* tcount, const double* tx, const double* ty, const double* tz, long long* pairs,
-               long long* evals, hipStream_t s);
-void fmm_m2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s);
+// Direct-act lists split into the leaves summed particle by particle (near)
+// and those taken through their multipole expansion (far), both in CSR form
+// by target box, with the work each box gives the two kernels.
+struct NearLists {
+    DVec<int> near_off, near_src, far_off, far_src;
+    DVec<long long> pairs, evals;
+    int n_near = 0, n_far = 0;
+};
+void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
+                const int* tcount, const double* tx, const double* ty, const double* tz, NearLists& out,
+                hipStream_t s);
+// Near-field work items: segment [y, z) of box x's list, results to the
+// outputs (w < 0) or to partial slots w .. w + tcount[x] - 1; reduce records
+// (box, segments, first slot) for the boxes cut into several segments.
+struct WorkItems {
+    DVec<int4> items, red;
+    DVec<double> part;  // [nslot][4]
+    int n = 0, nred = 0, nslot = 0;
+};
+constexpr int kSegNear = 128;  // close leaves per direct-sum item
+constexpr int kSegFar = 128;   // close leaves per expansion item
+// count == nullptr: work counted per entry instead of per particle
+void build_items(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
+                 WorkItems& out, hipStream_t s);
+void fmm_p2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
+             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
+             double* defl, int64_t m_out, hipStream_t s);
+void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
+             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
+             double* defl, int64_t m_out, hipStream_t s);
 
 }  // namespace sfmm

@@ -344,17 +344,19 @@ SFMM_HD void l2p_eval(const double* e, const Frame& f, double rho, double nx, do
 // 2 Re f is -2 conj(g / w) and that of Q log(1 - cos) = Q log(2|w|^2/(1+|w|^2))
 // is 2 Q w / (|w|^2 (1 + |w|^2)), so
 //   alpha_u + i alpha_v = (Q - (1 + |w|^2) conj(g)) / conj(w).
-SFMM_HD void m2p_eval(const double* e, int p, const Frame& f, double rho, double nx, double ny, double nz,
+template <int P>
+SFMM_HD void m2p_eval(const double* __restrict__ e, const Frame& f, double rho, double nx, double ny, double nz,
                       double* psi, double* ax, double* ay, double* az) {
     double opc;
     const cplx w = stereo(f, nx, ny, nz, &opc);
     const double dx = nx - f.c[0], dy = ny - f.c[1], dz = nz - f.c[2];
     const double omc = 0.5 * (dx * dx + dy * dy + dz * dz);  // 1 - cos theta
     const double w2 = w.re * w.re + w.im * w.im;
-    const double iw2 = 1.0 / w2;
+    const double iw2 = recip(w2);
     const cplx zt = {rho * w.re * iw2, -rho * w.im * iw2};  // rho / w
     cplx F = {0.0, 0.0}, G = {0.0, 0.0};
-    for (int l = p; l >= 1; --l) {
+#pragma unroll 6
+    for (int l = P; l >= 1; --l) {
         const double ar = e[2 * l], ai = e[2 * l + 1];
         F = cmul(F, zt);
         F.re += ar;
@@ -371,7 +373,7 @@ SFMM_HD void m2p_eval(const double* e, int p, const Frame& f, double rho, double
     const double s = 1.0 + w2;
     const cplx num = {Q - s * G.re, s * G.im};
     const cplx A = {(num.re * w.re - num.im * w.im) * iw2, (num.re * w.im + num.im * w.re) * iw2};
-    const double inv = 1.0 / s;
+    const double inv = recip(s);
     const double u = w.re, v = w.im;
     const double eu_t = (1.0 + v * v - u * u) * inv, eu_p = -2.0 * u * v * inv, eu_c = -2.0 * u * inv;
     const double ev_t = -2.0 * u * v * inv, ev_p = (1.0 + u * u - v * v) * inv, ev_c = -2.0 * v * inv;

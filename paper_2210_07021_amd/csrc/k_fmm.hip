@@ -123,17 +123,6 @@ __global__ void __launch_bounds__(128) k_l2p(FmmCtx c, const double* tx, const d
     defl[2 * m_out + o] = az;
 }
 
-#define SFMM_ORDERS(X)                                                                             \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
-    X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) \
-    X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48)
-
-#define SFMM_DISPATCH(p, LAUNCH)                                                   \
-    switch (p) {                                                                   \
-        SFMM_ORDERS(LAUNCH)                                                        \
-        default: throw Error(ST_INVALID_ARG, "expansion order out of range");     \
-    }
-
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s) {
     if (nb <= 0) return;
 #define L_(P) case P: k_p2m<P><<<nblk(nb, 128), 128, 0, s>>>(c, nb); break;

@@ -1,42 +1,54 @@
-// Near field (the direct acts of Sec. 3.3-3.4): for every target in a leaf,
+// Near field (the direct acts of Sec. 3.3-3.4): for every target in a leaf T,
 // the sum of the Green's function and its tangent gradient over the particles
-// of the leaf's close boxes.
+// of T's close leaves.
 //
-// One 64-wide wavefront (a 64-thread workgroup) owns one target leaf and
-// takes its targets in groups of up to 64, lane t owning target t of the
-// group.  The close leaves' particle ranges are concatenated into one flat
-// index space (wave prefix sum of their counts); each tile of 256 particles
-// is decoded once (binary search by lane shuffles) and staged in LDS, then
-// every target of the group streams over the tile with the lanes splitting
-// the particles, and a butterfly reduction hands the four partial sums to
-// the target's lane.  No floating-point atomics: the result is bitwise
-// reproducible.
+// At planning time each direct-act list is split in two (near_split):
+//   * a close leaf S whose centre is more than 3 R_S from every target of T
+//     (and that holds enough particles for it to pay) is taken through its
+//     own multipole expansion (Lemma 1) at each target: k_m2p.  By Eq.
+//     MUL_ERR the truncation there is below (Q~/2pi) x^(p+1)/((p+1)(1-x))
+//     with x ~ 1/3, under 1e-15 Q~ for p >= 28; the split is only made for
+//     p >= 12 and for leaves with at least p/4 + 2 particles (the expansion
+//     costs about p/4 pair evaluations).  Big leaves of sparse regions next
+//     to dense clumps are where it matters: their targets otherwise meet
+//     every particle of the clump directly.
+//   * every other close leaf is summed particle by particle: k_p2p.
+//
+// k_p2p: one 64-wide wavefront (a 64-thread workgroup) owns one target leaf
+// and takes its targets in groups of ng <= 64.  The lanes form ng teams of
+// L = floor(64 / ng) lanes, team t owning target t of the group.  The close
+// leaves' particle ranges are concatenated into one flat index space (wave
+// prefix sum of their counts); each tile of 256 particles is decoded once
+// (binary search by lane shuffles) and staged in LDS, and lane r of a team
+// takes particles r, r + L, ... of the tile.  The four partial sums stay in
+// registers across all tiles; at the end of the group the team's lanes are
+// summed in a fixed order through LDS.  No floating-point atomics: the
+// result is bitwise reproducible.
+//
+// Load balance: a leaf of a sparse region next to a dense clump can have
+// thousands of close leaves (every clump leaf fails the MAC against a big
+// leaf).  Each leaf's two lists are cut into segments of at most kSegNear /
+// kSegFar entries; a workgroup takes one (leaf, segment) item, items are
+// launched heaviest first, and a leaf cut into several segments writes its
+// per-segment results to a partial buffer that k_near_reduce adds up in
+// segment order (so the result stays bitwise reproducible).
 //
 // Per pair, with d = n_t - n_s, psi gets (q/4pi)(log(|d|^2/4) + 1) (Eq.
 // GRE_FUN plus the zero-mean share) and alpha gets (q/2pi) d/|d|^2, projected
 // on the tangent plane once per target.  A particle at exactly the target
-// position keeps only its q/(4pi).  Per target and chunk only four sums are
-// kept:
+// position keeps only its q/(4pi).  Per target only four sums are kept:
 //   S = sum q log|d|^2   (log 4 in place of the log for a coincident particle)
 //   V = sum q d/|d|^2    (d = 0 there, so nothing is added)
 // and with Q_near = sum q over the summed leaves (from their Lemma 1 Q),
 //   4 pi psi_near = S + (1 - log 4) Q_near.
-//
-// A close leaf S whose centre is more than 3 R_S from every target of the
-// current chunk is not summed particle by particle: its own multipole
-// expansion (Lemma 1) is evaluated at those targets instead.  By Eq. MUL_ERR
-// the truncation error there is below (Q~/2pi) x^(p+1)/((p+1)(1-x)) with
-// x ~ 1/3, i.e. under 1e-15 Q~ for p >= 28; this is done only for p >= 12
-// and for leaves holding at least p/4 + 2 particles (below that the direct
-// sum is cheaper).  Big leaves of sparse regions next to dense clumps are
-// where it matters: their targets otherwise meet every particle of the
-// clump directly.
 #include "common.hpp"
 #include "expand.hpp"
 
 namespace sfmm {
 
 constexpr int kTile = 256;  // particles staged in LDS per tile
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -45,40 +57,297 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kM2PMinOrder = 12;
-constexpr double kM2PRatio = 3.0;  // target beyond 3 R_S from the leaf centre
+constexpr double kM2PRatio = 3.0;  // every target beyond 3 R_S from the leaf centre
 
-// Entry (close leaf) S is taken by its multipole expansion for a target group
-// when it is full enough for that to pay (the expansion costs ~p/4 direct
-// pairs) and every target of the group lies beyond kM2PRatio R_S of its
-// centre (chord > 2 sin(3R/2)).  Both kernels below evaluate this same test.
-__device__ __forceinline__ bool leaf_far(const FmmCtx& c, int S, int cnt, const double* __restrict__ tx,
-                                         const double* __restrict__ ty, const double* __restrict__ tz,
-                                         int g0, int ng) {
-    if (c.p < kM2PMinOrder || 4 * cnt < c.p + 8) return false;
-    const double a = kM2PRatio * c.rad[S];
-    if (a >= 3.0) return false;
-    const double h = 2.0 * sin(0.5 * a);
-    const double thr = h * h;
-    const double* cs = c.cen + 4 * (size_t)S;
-    for (int t = 0; t < ng; ++t) {
-        const int it = g0 + t;
-        const double dx = tx[it] - cs[0], dy = ty[it] - cs[1], dz = tz[it] - cs[2];
-        if (!(dx * dx + dy * dy + dz * dz > thr)) return false;
-    }
-    return true;
+// ------------------------------------------------------------ list split
+// Target box of every direct-act entry
+__global__ void k_entry_box(const int* __restrict__ off, int nbox, int* __restrict__ ent_t) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    for (int k = off[b]; k < off[b + 1]; ++k) ent_t[k] = b;
 }
 
-// Direct sums over the close leaves that are not taken by their expansion.
-__global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int* __restrict__ tleaves, int ntl,
-                                           const int* __restrict__ off, const int* __restrict__ src,
-                                           const int* __restrict__ tfirst, const int* __restrict__ tcount,
-                                           const double* __restrict__ tx, const double* __restrict__ ty,
-                                           const double* __restrict__ tz, const uint32_t* __restrict__ tperm,
-                                           double* __restrict__ psi, double* __restrict__ defl, int64_t m_out) {
+// 1 in near[k] / far[k] when entry k goes to the direct sum / the multipole
+// evaluation; both 0 when its target box holds no target.
+__global__ void k_near_flags(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src, int np,
+                             const int* __restrict__ tfirst, const int* __restrict__ tcount,
+                             const double* __restrict__ tx, const double* __restrict__ ty,
+                             const double* __restrict__ tz, int* __restrict__ near, int* __restrict__ far) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int T = ent_t[k], S = src[k];
+    const int nt = tcount[T];
+    bool is_far = false;
+    if (nt > 0 && c.p >= kM2PMinOrder && 4 * c.count[S] >= c.p + 8) {
+        const double a = kM2PRatio * c.rad[S];
+        if (a < 3.0) {
+            const double* cs = c.cen + 4 * (size_t)S;
+            const double* ct = c.cen + 4 * (size_t)T;
+            // whole box T beyond a + R_T (every point of a box lies within R of its centre)
+            const double b = a + c.rad[T];
+            const double ex = cs[0] - ct[0], ey = cs[1] - ct[1], ez = cs[2] - ct[2];
+            const double d2 = ex * ex + ey * ey + ez * ez;
+            const double hb = 2.0 * sin(0.5 * b);
+            if (b < 3.0 && d2 > hb * hb * (1.0 + 1e-12)) {
+                is_far = true;
+            } else {
+                const double h = 2.0 * sin(0.5 * a);
+                const double thr = h * h;
+                is_far = true;
+                const int t0 = tfirst[T];
+                for (int i = t0; i < t0 + nt; ++i) {
+                    const double dx = tx[i] - cs[0], dy = ty[i] - cs[1], dz = tz[i] - cs[2];
+                    if (!(dx * dx + dy * dy + dz * dz > thr)) {
+                        is_far = false;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    near[k] = (nt > 0 && !is_far) ? 1 : 0;
+    far[k] = is_far ? 1 : 0;
+}
+
+__global__ void k_near_scatter(const int* __restrict__ src, int np, const int* __restrict__ near,
+                               const int* __restrict__ npos, const int* __restrict__ far,
+                               const int* __restrict__ fpos, int* __restrict__ near_src,
+                               int* __restrict__ far_src) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    if (near[k]) near_src[npos[k]] = src[k];
+    if (far[k]) far_src[fpos[k]] = src[k];
+}
+
+// CSR offsets of the two lists (entry k of the full list lands at npos[k] /
+// fpos[k], so box b starts where its first full-list entry would land)
+__global__ void k_near_offsets(const int* __restrict__ off, int nbox, int np, const int* __restrict__ npos,
+                               const int* __restrict__ ntot, const int* __restrict__ fpos,
+                               const int* __restrict__ ftot, int* __restrict__ near_off,
+                               int* __restrict__ far_off) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbox) return;
+    const int k = off[b];
+    near_off[b] = k < np ? npos[k] : *ntot;
+    far_off[b] = k < np ? fpos[k] : *ftot;
+}
+
+// Work of each box: pairs[T] = tcount[T] * (particles of the near leaves),
+// evals[T] = tcount[T] * (far leaves)
+__global__ void k_near_work(const int* __restrict__ count, const int* __restrict__ near_off,
+                            const int* __restrict__ near_src, const int* __restrict__ far_off,
+                            const int* __restrict__ tcount, int nbox, long long* __restrict__ pairs,
+                            long long* __restrict__ evals) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    long long ns = 0;
+    for (int k = near_off[b]; k < near_off[b + 1]; ++k) ns += count[near_src[k]];
+    pairs[b] = ns * (long long)tcount[b];
+    evals[b] = (long long)(far_off[b + 1] - far_off[b]) * (long long)tcount[b];
+}
+
+void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
+                const int* tcount, const double* tx, const double* ty, const double* tz, NearLists& out,
+                hipStream_t s) {
+    out.near_off.resize(nbox + 1);
+    out.far_off.resize(nbox + 1);
+    out.pairs.resize(std::max(nbox, 1));
+    out.evals.resize(std::max(nbox, 1));
+    out.n_near = out.n_far = 0;
+    if (nbox <= 0) return;
+    DVec<int> ent_t, near, far, npos, fpos, tot;
+    const int n1 = std::max(np, 1);
+    ent_t.resize(n1);
+    near.resize(n1);
+    far.resize(n1);
+    npos.resize(n1);
+    fpos.resize(n1);
+    tot.resize(2);
+    fill_i32(tot.data(), 2, 0, s);
+    if (np > 0) {
+        k_entry_box<<<nblk(nbox, 256), 256, 0, s>>>(off, nbox, ent_t.data());
+        SFMM_LAUNCH_CHECK();
+        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t.data(), src, np, tfirst, tcount, tx, ty, tz,
+                                                   near.data(), far.data());
+        SFMM_LAUNCH_CHECK();
+        scan_excl_i32(near.data(), npos.data(), np, tot.data(), s);
+        scan_excl_i32(far.data(), fpos.data(), np, tot.data() + 1, s);
+    }
+    int h[2] = {0, 0};
+    SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    out.n_near = h[0];
+    out.n_far = h[1];
+    out.near_src.resize(std::max(h[0], 1));
+    out.far_src.resize(std::max(h[1], 1));
+    if (np > 0) {
+        k_near_scatter<<<nblk(np, 256), 256, 0, s>>>(src, np, near.data(), npos.data(), far.data(), fpos.data(),
+                                                     out.near_src.data(), out.far_src.data());
+        SFMM_LAUNCH_CHECK();
+    }
+    k_near_offsets<<<nblk(nbox + 1, 256), 256, 0, s>>>(off, nbox, np, npos.data(), tot.data(), fpos.data(),
+                                                       tot.data() + 1, out.near_off.data(), out.far_off.data());
+    SFMM_LAUNCH_CHECK();
+    k_near_work<<<nblk(nbox, 256), 256, 0, s>>>(c.count, out.near_off.data(), out.near_src.data(),
+                                                out.far_off.data(), tcount, nbox, out.pairs.data(),
+                                                out.evals.data());
+    SFMM_LAUNCH_CHECK();
+    SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
+}
+
+// ------------------------------------------------------------ work items
+// Per box b with targets and a non-empty list: nseg = ceil(K / seg) items;
+// boxes cut into several items get nseg * tcount partial slots.
+__global__ void k_seg_count(const int* __restrict__ off, const int* __restrict__ tcount, int nbox, int seg,
+                            int* __restrict__ nseg, int* __restrict__ nslot, int* __restrict__ multi) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const int K = off[b + 1] - off[b];
+    const int ns = (tcount[b] > 0 && K > 0) ? (K + seg - 1) / seg : 0;
+    nseg[b] = ns;
+    nslot[b] = ns > 1 ? ns * tcount[b] : 0;
+    multi[b] = ns > 1 ? 1 : 0;
+}
+
+// Items (box, first entry, end entry, partial slot base or -1) with their
+// sort keys (leading zeros of the work: targets x particles, or targets x
+// entries when count is null), and the reduce records (box, nseg, base).
+__global__ void k_seg_emit(const int* __restrict__ off, const int* __restrict__ src, const int* __restrict__ count,
+                           const int* __restrict__ tcount, int nbox, int seg, const int* __restrict__ nseg,
+                           const int* __restrict__ item_off, const int* __restrict__ slot_off,
+                           const int* __restrict__ red_off, int4* __restrict__ items, uint64_t* __restrict__ keys,
+                           uint32_t* __restrict__ vals, int4* __restrict__ red) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const int ns = nseg[b];
+    if (ns == 0) return;
+    const int nt = tcount[b];
+    for (int sg = 0; sg < ns; ++sg) {
+        const int kb = off[b] + sg * seg, ke = min(kb + seg, off[b + 1]);
+        long long w = 0;
+        if (count) {
+            for (int k = kb; k < ke; ++k) w += count[src[k]];
+        } else {
+            w = ke - kb;
+        }
+        w *= nt;
+        const int it = item_off[b] + sg;
+        items[it] = make_int4(b, kb, ke, ns > 1 ? slot_off[b] + sg * nt : -1);
+        keys[it] = (w > 0) ? (uint64_t)__clzll((unsigned long long)w) : 255ULL;
+        vals[it] = (uint32_t)it;
+    }
+    if (ns > 1) red[red_off[b]] = make_int4(b, ns, slot_off[b], 0);
+}
+
+__global__ void k_gather_items(const int4* __restrict__ in, const uint32_t* __restrict__ idx, int n,
+                               int4* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
+void build_items(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
+                 WorkItems& out, hipStream_t s) {
+    out.n = out.nred = 0;
+    out.nslot = 0;
+    if (nbox <= 0) return;
+    DVec<int> nseg, nslot, multi, item_off, slot_off, red_off, tot;
+    nseg.resize(nbox);
+    nslot.resize(nbox);
+    multi.resize(nbox);
+    item_off.resize(nbox);
+    slot_off.resize(nbox);
+    red_off.resize(nbox);
+    tot.resize(3);
+    k_seg_count<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), nslot.data(), multi.data());
+    SFMM_LAUNCH_CHECK();
+    scan_excl_i32(nseg.data(), item_off.data(), nbox, tot.data(), s);
+    scan_excl_i32(nslot.data(), slot_off.data(), nbox, tot.data() + 1, s);
+    scan_excl_i32(multi.data(), red_off.data(), nbox, tot.data() + 2, s);
+    int h[3];
+    SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    out.n = h[0];
+    out.nslot = h[1];
+    out.nred = h[2];
+    out.items.resize(std::max(out.n, 1));
+    out.red.resize(std::max(out.nred, 1));
+    out.part.resize(4 * (size_t)std::max(out.nslot, 1));
+    if (out.n == 0) return;
+    DVec<int4> raw;
+    DVec<uint64_t> keys;
+    DVec<uint32_t> vals;
+    raw.resize(out.n);
+    keys.resize(out.n);
+    vals.resize(out.n);
+    k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, src, count, tcount, nbox, seg, nseg.data(), item_off.data(),
+                                               slot_off.data(), red_off.data(), raw.data(), keys.data(),
+                                               vals.data(), out.red.data());
+    SFMM_LAUNCH_CHECK();
+    radix_sort_u64(keys.data(), vals.data(), out.n, 8, s);
+    k_gather_items<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), vals.data(), out.n, out.items.data());
+    SFMM_LAUNCH_CHECK();
+    SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
+}
+
+// Adds the per-segment results of every box cut into several items, in
+// segment order: one workgroup per box, lanes over its targets.
+__global__ void __launch_bounds__(64) k_near_reduce(const int4* __restrict__ red, const int* __restrict__ tfirst,
+                                                   const int* __restrict__ tcount,
+                                                   const uint32_t* __restrict__ tperm,
+                                                   const double* __restrict__ part, double* __restrict__ psi,
+                                                   double* __restrict__ defl, int64_t m_out) {
+    const int4 r = red[blockIdx.x];
+    const int T = r.x, ns = r.y, base = r.z;
+    const int t0 = tfirst[T], nt = tcount[T];
+    for (int t = threadIdx.x; t < nt; t += 64) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int sg = 0; sg < ns; ++sg) {
+            const double* q = part + 4 * ((size_t)base + (size_t)sg * nt + t);
+            s0 += q[0];
+            s1 += q[1];
+            s2 += q[2];
+            s3 += q[3];
+        }
+        const int64_t o = tperm[t0 + t];
+        psi[o] += s0;
+        defl[o] += s1;
+        defl[m_out + o] += s2;
+        defl[2 * m_out + o] += s3;
+    }
+}
+
+// psi and alpha contributions of one target: straight to the outputs, or to
+// its slot of the partial buffer
+__device__ __forceinline__ void emit_target(int slot, int64_t o, double ps, double a0, double a1, double a2,
+                                            double* __restrict__ part, double* __restrict__ psi,
+                                            double* __restrict__ defl, int64_t m_out) {
+    if (slot < 0) {
+        psi[o] += ps;
+        defl[o] += a0;
+        defl[m_out + o] += a1;
+        defl[2 * m_out + o] += a2;
+    } else {
+        double* q = part + 4 * (size_t)slot;
+        q[0] = ps;
+        q[1] = a0;
+        q[2] = a1;
+        q[3] = a2;
+    }
+}
+
+// ------------------------------------------------------------ direct sums
+__global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ items,
+                                           const int* __restrict__ src, const int* __restrict__ tfirst,
+                                           const int* __restrict__ tcount, const double* __restrict__ tx,
+                                           const double* __restrict__ ty, const double* __restrict__ tz,
+                                           const uint32_t* __restrict__ tperm, double* __restrict__ psi,
+                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
     __shared__ double4 tile[kTile];
+    __shared__ double red[4][64];
     const int lane = threadIdx.x;
-    const int T = tleaves[blockIdx.x];
-    const int k0 = off[T], K = off[T + 1] - k0;
+    const int4 item = items[blockIdx.x];
+    const int T = item.x;
+    const int k0 = item.y, K = item.z - item.y;
     const int t0 = tfirst[T], nt = tcount[T];
     const int ew = 2 * c.p + 2;
     const double* __restrict__ sx = c.sx;
@@ -89,8 +358,13 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int* __restrict__ tl
     for (int tg = 0; tg < nt; tg += 64) {
         const int ng = min(64, nt - tg);
         const int g0 = t0 + tg;
-        double own0 = 0.0, own1 = 0.0, own2 = 0.0, own3 = 0.0;  // S, V of this lane's target
-        double qnear = 0.0;                                      // lane partials of Q_near
+        const int L = 64 / ng;  // lanes per target
+        const int team = lane / L, r = lane - team * L;
+        const bool active = team < ng;
+        const int my = g0 + (active ? team : 0);
+        const double ax = tx[my], ay = ty[my], az = tz[my];
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;  // S, V partials of this lane
+        double qnear = 0.0;                              // lane partials of Q_near
         for (int kc = 0; kc < K; kc += 64) {
             const int kk = min(64, K - kc);
             int cnt = 0, fst = 0;
@@ -98,10 +372,9 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int* __restrict__ tl
                 const int S = src[k0 + kc + lane];
                 cnt = c.count[S];
                 fst = c.first[S];
-                if (leaf_far(c, S, cnt, tx, ty, tz, g0, ng)) cnt = 0;
-                else if (cnt > 0) qnear += c.mult[(size_t)S * ew + 1] * (4.0 * M_PI);
+                qnear += c.mult[(size_t)S * ew + 1] * (4.0 * M_PI);
             }
-            // inclusive wave scan of the counts left for direct summation
+            // inclusive wave scan of the counts
             int incl = cnt;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -131,11 +404,8 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int* __restrict__ tl
                     }
                 }
                 __syncthreads();
-                for (int t = 0; t < ng; ++t) {
-                    const int it = g0 + t;
-                    const double ax = tx[it], ay = ty[it], az = tz[it];
-                    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-                    for (int j = lane; j < tn; j += 64) {
+                if (active) {
+                    for (int j = r; j < tn; j += L) {
                         const double4 sp = tile[j];
                         const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
                         const bool coinc = (dx == 0.0) & (dy == 0.0) & (dz == 0.0);
@@ -147,170 +417,159 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int* __restrict__ tl
                         p2 = fma(wi, dy, p2);
                         p3 = fma(wi, dz, p3);
                     }
-                    p0 = wave_sum(p0);
-                    p1 = wave_sum(p1);
-                    p2 = wave_sum(p2);
-                    p3 = wave_sum(p3);
-                    if (lane == t) {
-                        own0 += p0;
-                        own1 += p1;
-                        own2 += p2;
-                        own3 += p3;
-                    }
                 }
             }
         }
         const double qn = wave_sum(qnear);
+        red[0][lane] = p0;
+        red[1][lane] = p1;
+        red[2][lane] = p2;
+        red[3][lane] = p3;
+        __syncthreads();
         if (lane < ng) {
-            const int my = g0 + lane;
-            const double mx = tx[my], myy = ty[my], mz = tz[my];
-            const int64_t o = tperm[my];
-            psi[o] += (own0 + (1.0 - kLog4) * qn) * kInv4Pi;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int j = lane * L; j < lane * L + L; ++j) {
+                s0 += red[0][j];
+                s1 += red[1][j];
+                s2 += red[2][j];
+                s3 += red[3][j];
+            }
+            const int me = g0 + lane;
+            const double mx = tx[me], myy = ty[me], mz = tz[me];
             const double il = 1.0 / sqrt(mx * mx + myy * myy + mz * mz);
             const double ux = mx * il, uy = myy * il, uz = mz * il;
-            const double vr = ux * own1 + uy * own2 + uz * own3;
-            defl[o] += (own1 - ux * vr) * kInv2Pi;
-            defl[m_out + o] += (own2 - uy * vr) * kInv2Pi;
-            defl[2 * m_out + o] += (own3 - uz * vr) * kInv2Pi;
+            const double vr = ux * s1 + uy * s2 + uz * s3;
+            emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[me], (s0 + (1.0 - kLog4) * qn) * kInv4Pi,
+                        (s1 - ux * vr) * kInv2Pi, (s2 - uy * vr) * kInv2Pi, (s3 - uz * vr) * kInv2Pi, part, psi,
+                        defl, m_out);
         }
+        __syncthreads();  // red is reused by the next group
     }
 }
 
-// Close leaves taken by their multipole expansion (Lemma 1).  The far leaves
-// of a 64-entry chunk are compacted into LDS; the lanes split into ng groups
-// of L (L the largest power of two <= 64/ng), group t evaluating every
-// L-th far leaf at target t; a butterfly over the group sums them, and the
-// group's first lane adds the sum to target t's slot (one writer per slot,
-// fixed order: bitwise reproducible).
-__global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int* __restrict__ tleaves, int ntl,
-                                           const int* __restrict__ off, const int* __restrict__ src,
-                                           const int* __restrict__ tfirst, const int* __restrict__ tcount,
-                                           const double* __restrict__ tx, const double* __restrict__ ty,
-                                           const double* __restrict__ tz, const uint32_t* __restrict__ tperm,
-                                           double* __restrict__ psi, double* __restrict__ defl, int64_t m_out) {
-    __shared__ int far_s[64];
-    __shared__ double sums[64][4];
+// ------------------------------------------------------------ multipole evaluations
+// One 64-wide workgroup per target leaf with far entries, targets in groups
+// of ng <= 64 and lanes in teams of L = floor(64 / ng) as in k_p2p.  The far
+// leaves are taken kChunkF at a time: their expansion records and frames
+// are loaded once into LDS (coalesced: each record is contiguous), then
+// lane r of team t evaluates leaves r, r + L, ... of the chunk at target t.
+// The team's partial sums are added in a fixed order at the end of the
+// group.
+constexpr int kChunkF = 32;
+
+template <int P>
+__global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ items,
+                                           const int* __restrict__ src, const int* __restrict__ tfirst,
+                                           const int* __restrict__ tcount, const double* __restrict__ tx,
+                                           const double* __restrict__ ty, const double* __restrict__ tz,
+                                           const uint32_t* __restrict__ tperm, double* __restrict__ psi,
+                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
+    constexpr int EW = 2 * P + 2;
+    __shared__ double coef[kChunkF * EW];
+    __shared__ double frm[kChunkF][10];  // c, e_theta, e_phi, rho
+    __shared__ double red[4][64];
     const int lane = threadIdx.x;
-    const int T = tleaves[blockIdx.x];
-    const int k0 = off[T], K = off[T + 1] - k0;
+    const int4 item = items[blockIdx.x];
+    const int T = item.x;
+    const int k0 = item.y, K = item.z - item.y;
     const int t0 = tfirst[T], nt = tcount[T];
-    const int ew = 2 * c.p + 2;
     for (int tg = 0; tg < nt; tg += 64) {
         const int ng = min(64, nt - tg);
         const int g0 = t0 + tg;
-        int L = 1;
-        while (L * 2 * ng <= 64) L *= 2;
-        const int gt = lane / L, sub = lane % L;  // target of this lane's group, rank in the group
-        const bool active = gt < ng;
-        const int my = g0 + (active ? gt : 0);
-        const double mx = tx[my], myy = ty[my], mz = tz[my];
-        sums[lane][0] = sums[lane][1] = sums[lane][2] = sums[lane][3] = 0.0;
-        bool any = false;
-        for (int kc = 0; kc < K; kc += 64) {
-            const int kk = min(64, K - kc);
-            int S = -1;
-            bool far = false;
-            if (lane < kk) {
-                S = src[k0 + kc + lane];
-                far = leaf_far(c, S, c.count[S], tx, ty, tz, g0, ng);
+        const int L = 64 / ng;
+        const int team = lane / L, r = lane - team * L;
+        const bool active = team < ng;
+        const int my = g0 + (active ? team : 0);
+        const double nx = tx[my], ny = ty[my], nz = tz[my];
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        for (int kc = 0; kc < K; kc += kChunkF) {
+            const int cf = min(kChunkF, K - kc);
+            __syncthreads();  // previous chunk fully consumed
+            for (int idx = lane; idx < cf * EW; idx += 64) {
+                const int f = idx / EW, e = idx - f * EW;
+                coef[idx] = c.mult[(size_t)src[k0 + kc + f] * EW + e];
             }
-            const uint64_t fm = __ballot(far);
-            if (fm == 0) continue;
-            any = true;
-            const int nfar = __popcll(fm);
-            __syncthreads();  // previous chunk's far list fully read
-            if (far) far_s[__popcll(fm & ((1ULL << lane) - 1))] = S;
+            if (lane < cf) {
+                const double* cs = c.cen + 4 * (size_t)src[k0 + kc + lane];
+                const Frame fr = make_frame(cs[0], cs[1], cs[2]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    frm[lane][d] = fr.c[d];
+                    frm[lane][3 + d] = fr.et[d];
+                    frm[lane][6 + d] = fr.ep[d];
+                }
+                frm[lane][9] = cs[3];
+            }
             __syncthreads();
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
             if (active) {
-                for (int e = sub; e < nfar; e += L) {
-                    const int Se = far_s[e];
-                    const double* cs = c.cen + 4 * (size_t)Se;
-                    const Frame fs = make_frame(cs[0], cs[1], cs[2]);
+                for (int j = r; j < cf; j += L) {
+                    Frame fr;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        fr.c[d] = frm[j][d];
+                        fr.et[d] = frm[j][3 + d];
+                        fr.ep[d] = frm[j][6 + d];
+                    }
                     double ps, ax, ay, az;
-                    m2p_eval(c.mult + (size_t)Se * ew, c.p, fs, cs[3], mx, myy, mz, &ps, &ax, &ay, &az);
+                    m2p_eval<P>(coef + j * EW, fr, frm[j][9], nx, ny, nz, &ps, &ax, &ay, &az);
                     p0 += ps;
                     p1 += ax;
                     p2 += ay;
                     p3 += az;
                 }
             }
-            for (int o = L >> 1; o > 0; o >>= 1) {
-                p0 += __shfl_xor(p0, o, 64);
-                p1 += __shfl_xor(p1, o, 64);
-                p2 += __shfl_xor(p2, o, 64);
-                p3 += __shfl_xor(p3, o, 64);
-            }
-            if (active && sub == 0) {
-                sums[gt][0] += p0;
-                sums[gt][1] += p1;
-                sums[gt][2] += p2;
-                sums[gt][3] += p3;
-            }
         }
+        red[0][lane] = p0;
+        red[1][lane] = p1;
+        red[2][lane] = p2;
+        red[3][lane] = p3;
         __syncthreads();
-        if (any && lane < ng) {
-            const int64_t o = tperm[g0 + lane];
-            psi[o] += sums[lane][0];
-            defl[o] += sums[lane][1];
-            defl[m_out + o] += sums[lane][2];
-            defl[2 * m_out + o] += sums[lane][3];
+        if (lane < ng) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int j = lane * L; j < lane * L + L; ++j) {
+                s0 += red[0][j];
+                s1 += red[1][j];
+                s2 += red[2][j];
+                s3 += red[3][j];
+            }
+            emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[g0 + lane], s0, s1, s2, s3, part, psi, defl,
+                        m_out);
         }
-        __syncthreads();
+        __syncthreads();  // red is reused by the next group
     }
 }
 
-// Work actually done by the two kernels above, per target leaf: particle-
-// target pairs summed directly and (target, leaf) multipole evaluations.
-// Same grouping and the same far test, one lane per target leaf.
-__global__ void k_near_work(FmmCtx c, const int* __restrict__ tleaves, int ntl, const int* __restrict__ off,
-                            const int* __restrict__ src, const int* __restrict__ tfirst,
-                            const int* __restrict__ tcount, const double* __restrict__ tx,
-                            const double* __restrict__ ty, const double* __restrict__ tz, long long* pairs,
-                            long long* evals) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntl) return;
-    const int T = tleaves[i];
-    long long np = 0, ne = 0;
-    for (int tg = 0; tg < tcount[T]; tg += 64) {
-        const int ng = min(64, tcount[T] - tg);
-        const int g0 = tfirst[T] + tg;
-        for (int k = off[T]; k < off[T + 1]; ++k) {
-            const int S = src[k];
-            const int cnt = c.count[S];
-            if (leaf_far(c, S, cnt, tx, ty, tz, g0, ng)) ne += ng;
-            else np += (long long)ng * cnt;
-        }
-    }
-    pairs[i] = np;
-    evals[i] = ne;
-}
-
-void near_work(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-               const int* tcount, const double* tx, const double* ty, const double* tz, long long* pairs,
-               long long* evals, hipStream_t s) {
-    if (ntl <= 0) return;
-    k_near_work<<<(unsigned)((ntl + 127) / 128), 128, 0, s>>>(c, tleaves, ntl, off, src, tfirst, tcount, tx, ty,
-                                                              tz, pairs, evals);
+void reduce_items(const WorkItems& w, const int* tfirst, const int* tcount, const uint32_t* tperm, double* psi,
+                  double* defl, int64_t m_out, hipStream_t s) {
+    if (w.nred <= 0) return;
+    k_near_reduce<<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, w.part.data(), psi, defl,
+                                                  m_out);
     SFMM_LAUNCH_CHECK();
 }
 
-void fmm_p2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s) {
-    if (ntl <= 0) return;
-    k_p2p<<<(unsigned)ntl, 64, 0, s>>>(c, tleaves, ntl, off, src, tfirst, tcount, tx, ty, tz, tperm, psi, defl,
-                                       m_out);
+void fmm_p2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
+             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
+             double* defl, int64_t m_out, hipStream_t s) {
+    if (w.n <= 0) return;
+    k_p2p<<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, defl, m_out,
+                                       w.part.data());
     SFMM_LAUNCH_CHECK();
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
 }
 
-void fmm_m2p(const FmmCtx& c, const int* tleaves, int ntl, const int* off, const int* src, const int* tfirst,
-             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s) {
-    if (ntl <= 0 || c.p < kM2PMinOrder) return;
-    k_m2p<<<(unsigned)ntl, 64, 0, s>>>(c, tleaves, ntl, off, src, tfirst, tcount, tx, ty, tz, tperm, psi, defl,
-                                       m_out);
+void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
+             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
+             double* defl, int64_t m_out, hipStream_t s) {
+    if (w.n <= 0 || c.p < kM2PMinOrder) return;
+#define L_(P)                                                                                             \
+    case P:                                                                                               \
+        k_m2p<P><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, \
+                                              defl, m_out, w.part.data());                                \
+        break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
     SFMM_LAUNCH_CHECK();
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
 }
 
 }  // namespace sfmm

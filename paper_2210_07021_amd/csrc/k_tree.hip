@@ -353,21 +353,19 @@ void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hi
     SFMM_LAUNCH_CHECK();
 }
 
-__global__ void k_work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals,
-                                  int* flag) {
+// key = leading zeros of the work (heaviest power-of-two bucket first, 8 bits)
+__global__ void k_work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    const unsigned long long cap = (1ULL << 40) - 1;
-    const unsigned long long v = (unsigned long long)tcount[b] * (unsigned long long)(off[b + 1] - off[b]);
-    keys[b] = (v == 0) ? (1ULL << 40) : cap - (v < cap ? v : cap);
+    const unsigned long long v = (unsigned long long)work[b];
+    keys[b] = (v == 0) ? 255ULL : (uint64_t)__clzll(v);
     vals[b] = (uint32_t)b;
     flag[b] = v > 0 ? 1 : 0;
 }
 
-void work_order_keys(const int* off, const int* tcount, int n, uint64_t* keys, uint32_t* vals, int* flag,
-                     hipStream_t s) {
+void work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s) {
     if (n <= 0) return;
-    k_work_order_keys<<<nblocks(n, 256), 256, 0, s>>>(off, tcount, n, keys, vals, flag);
+    k_work_order_keys<<<nblocks(n, 256), 256, 0, s>>>(work, n, keys, vals, flag);
     SFMM_LAUNCH_CHECK();
 }
 

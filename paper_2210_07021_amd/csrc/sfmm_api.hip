@@ -117,9 +117,12 @@ struct sfmm_plan_impl {
     DVec<double> tx, ty, tz;
     DVec<uint32_t> tperm;
     DVec<uint64_t> tkeys;
-    DVec<int> tleaf, tfirst, tcount, tleaves;
-    int ntl = 0;
-    mutable long long n_p2p_pairs = -1, n_m2p_evals = -1;  // computed on the first stats request
+    DVec<int> tleaf, tfirst, tcount;
+    int ntl = 0;  // leaves with targets and direct-sum work
+    // direct-act lists split into direct sums and multipole evaluations
+    NearLists nl;
+    WorkItems near_items, far_items;
+    mutable long long n_p2p_pairs = -1, n_m2p_evals = -1;  // summed on the first stats request
     // expansions
     DVec<double> mult, local;
     bool executed = false;
@@ -320,6 +323,16 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
+// Boxes that have items: the items minus the extra segments of split boxes
+int count_boxes(const WorkItems& w) {
+    if (w.nred == 0) return w.n;
+    std::vector<int4> r(w.nred);
+    SFMM_HIP(hipMemcpy(r.data(), w.red.data(), sizeof(int4) * w.nred, hipMemcpyDeviceToHost));
+    int extra = 0;
+    for (const int4& x : r) extra += x.y - 1;
+    return w.n - extra;
+}
+
 void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     sort_points(tgt, nullptr, P.M, P.tx, P.ty, P.tz, nullptr, P.tperm, P.tkeys, P, s, "targets");
     P.tleaf.resize(std::max<int64_t>(P.M, 1));
@@ -329,23 +342,13 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     fill_i32(P.tcount.data(), P.nbox, 0, s);
     locate_targets(P.tkeys.data(), P.M, P.child0.data(), P.level.data(), P.tleaf.data(), s);
     target_ranges(P.tleaf.data(), P.M, P.tfirst.data(), P.tcount.data(), s);
-    // leaves with direct-act work, most work first
-    DVec<uint64_t> keys;
-    DVec<uint32_t> vals;
-    DVec<int> flag, off, tot;
-    keys.resize(P.nbox);
-    vals.resize(P.nbox);
-    flag.resize(P.nbox);
-    off.resize(P.nbox);
-    tot.resize(1);
-    work_order_keys(P.p2p_off.data(), P.tcount.data(), P.nbox, keys.data(), vals.data(), flag.data(), s);
-    scan_excl_i32(flag.data(), off.data(), P.nbox, tot.data(), s);
-    P.ntl = read_int(tot.data(), P, s);
-    radix_sort_u64(keys.data(), vals.data(), P.nbox, 41, s);
-    P.tleaves.resize(std::max(P.ntl, 1));
-    SFMM_HIP(hipMemcpyAsync(P.tleaves.data(), vals.data(), sizeof(int) * std::max(P.ntl, 1),
-                            hipMemcpyDeviceToDevice, s));
-    SFMM_HIP(hipStreamSynchronize(s));
+    near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.nbox, P.n_p2p, P.tfirst.data(), P.tcount.data(),
+               P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
+    build_items(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), P.tcount.data(), P.nbox, kSegNear,
+                P.near_items, s);
+    build_items(P.nl.far_off.data(), P.nl.far_src.data(), nullptr, P.tcount.data(), P.nbox, kSegFar, P.far_items,
+                s);
+    P.ntl = count_boxes(P.near_items);
 }
 
 // Order from a tolerance.  Measured on uniform and clustered skies at the
@@ -504,13 +507,13 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         }
         {
             StageScope st(prof, S_M2P);
-            fmm_m2p(c, P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
-                    P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
+            fmm_m2p(c, P.far_items, P.nl.far_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
+                    P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
         }
         {
             StageScope st(prof, S_P2P);
-            fmm_p2p(c, P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
-                    P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
+            fmm_p2p(c, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
+                    P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
         }
         prof.flush();
         P.executed = true;
@@ -542,14 +545,11 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->n_m2l = P.n_m2l;
         out->n_p2p = P.n_p2p;
         out->n_target_leaves = P.ntl;
-        if (P.n_p2p_pairs < 0 && P.ntl > 0) {
-            DVec<long long> w, tot;
-            w.resize(2 * (size_t)P.ntl);
+        if (P.n_p2p_pairs < 0 && P.nbox > 0) {
+            DVec<long long> tot;
             tot.resize(2);
-            near_work(P.ctx(), P.tleaves.data(), P.ntl, P.p2p_off.data(), P.p2p_src.data(), P.tfirst.data(),
-                      P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), w.data(), w.data() + P.ntl, nullptr);
-            sum_i64(w.data(), P.ntl, tot.data(), nullptr);
-            sum_i64(w.data() + P.ntl, P.ntl, tot.data() + 1, nullptr);
+            sum_i64(P.nl.pairs.data(), P.nbox, tot.data(), nullptr);
+            sum_i64(P.nl.evals.data(), P.nbox, tot.data() + 1, nullptr);
             long long h[2];
             SFMM_HIP(hipMemcpy(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost));
             P.n_p2p_pairs = h[0];
@@ -614,6 +614,20 @@ sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_
         copy_widen(tgt_keys, P.tkeys.data(), P.M);
         copy_widen(tgt_perm, P.tperm.data(), P.M);
         copy_widen(tgt_leaf, P.tleaf.data(), P.M);
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pairs, int64_t* evals) {
+    try {
+        if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
+        const sfmm_plan_impl& P = *plan;
+        if (P.N == 0 || P.nbox == 0) return SFMM_OK;
+        copy_widen(tgt_count, P.tcount.data(), P.nbox);
+        copy_widen(pairs, P.nl.pairs.data(), P.nbox);
+        copy_widen(evals, P.nl.evals.data(), P.nbox);
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);

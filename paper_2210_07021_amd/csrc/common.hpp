@@ -137,6 +137,7 @@ void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int*
 void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild,
                const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p,
                int p2p_base, hipStream_t s);
+// M2L order: longest list first (16-bit keys, ties in table order)
 void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s);
 // pairs (target << 32 | source) sorted by target -> CSR offsets and sources
 void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src, hipStream_t s);
@@ -172,7 +173,6 @@ void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* 
 // by target box, with the work each box gives the two kernels.
 struct NearLists {
     DVec<int> near_off, near_src, far_off, far_src;
-    DVec<long long> pairs, evals;
     int n_near = 0, n_far = 0;
 };
 void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
@@ -191,6 +191,10 @@ constexpr int kSegFar = 128;   // close leaves per expansion item
 // count == nullptr: work counted per entry instead of per particle
 void build_items(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
                  WorkItems& out, hipStream_t s);
+// per box: pairs[b] = targets x particles of the near leaves, evals[b] =
+// targets x far leaves
+void near_work(const int* count, const NearLists& nl, const int* tcount, int nbox, long long* pairs,
+               long long* evals, hipStream_t s);
 void fmm_p2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
              double* defl, int64_t m_out, hipStream_t s);

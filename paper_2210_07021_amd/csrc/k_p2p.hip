@@ -60,11 +60,18 @@ constexpr int kM2PMinOrder = 12;
 constexpr double kM2PRatio = 3.0;  // every target beyond 3 R_S from the leaf centre
 
 // ------------------------------------------------------------ list split
-// Target box of every direct-act entry
-__global__ void k_entry_box(const int* __restrict__ off, int nbox, int* __restrict__ ent_t) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbox) return;
-    for (int k = off[b]; k < off[b + 1]; ++k) ent_t[k] = b;
+// Target box of every direct-act entry: the last box whose list starts at
+// or before it (empty boxes share their start with the next one)
+__global__ void k_entry_box(const int* __restrict__ off, int nbox, int np, int* __restrict__ ent_t) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    int lo = 0, hi = nbox - 1;  // off[lo] <= k always holds (off[0] = 0)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    ent_t[k] = lo;
 }
 
 // 1 in near[k] / far[k] when entry k goes to the direct sum / the multipole
@@ -151,8 +158,6 @@ void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int n
                 hipStream_t s) {
     out.near_off.resize(nbox + 1);
     out.far_off.resize(nbox + 1);
-    out.pairs.resize(std::max(nbox, 1));
-    out.evals.resize(std::max(nbox, 1));
     out.n_near = out.n_far = 0;
     if (nbox <= 0) return;
     DVec<int> ent_t, near, far, npos, fpos, tot;
@@ -165,7 +170,7 @@ void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int n
     tot.resize(2);
     fill_i32(tot.data(), 2, 0, s);
     if (np > 0) {
-        k_entry_box<<<nblk(nbox, 256), 256, 0, s>>>(off, nbox, ent_t.data());
+        k_entry_box<<<nblk(np, 256), 256, 0, s>>>(off, nbox, np, ent_t.data());
         SFMM_LAUNCH_CHECK();
         k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t.data(), src, np, tfirst, tcount, tx, ty, tz,
                                                    near.data(), far.data());
@@ -188,11 +193,15 @@ void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int n
     k_near_offsets<<<nblk(nbox + 1, 256), 256, 0, s>>>(off, nbox, np, npos.data(), tot.data(), fpos.data(),
                                                        tot.data() + 1, out.near_off.data(), out.far_off.data());
     SFMM_LAUNCH_CHECK();
-    k_near_work<<<nblk(nbox, 256), 256, 0, s>>>(c.count, out.near_off.data(), out.near_src.data(),
-                                                out.far_off.data(), tcount, nbox, out.pairs.data(),
-                                                out.evals.data());
-    SFMM_LAUNCH_CHECK();
     SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
+}
+
+void near_work(const int* count, const NearLists& nl, const int* tcount, int nbox, long long* pairs,
+               long long* evals, hipStream_t s) {
+    if (nbox <= 0) return;
+    k_near_work<<<nblk(nbox, 256), 256, 0, s>>>(count, nl.near_off.data(), nl.near_src.data(), nl.far_off.data(),
+                                                tcount, nbox, pairs, evals);
+    SFMM_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------ work items
@@ -209,14 +218,12 @@ __global__ void k_seg_count(const int* __restrict__ off, const int* __restrict__
     multi[b] = ns > 1 ? 1 : 0;
 }
 
-// Items (box, first entry, end entry, partial slot base or -1) with their
-// sort keys (leading zeros of the work: targets x particles, or targets x
-// entries when count is null), and the reduce records (box, nseg, base).
-__global__ void k_seg_emit(const int* __restrict__ off, const int* __restrict__ src, const int* __restrict__ count,
-                           const int* __restrict__ tcount, int nbox, int seg, const int* __restrict__ nseg,
-                           const int* __restrict__ item_off, const int* __restrict__ slot_off,
-                           const int* __restrict__ red_off, int4* __restrict__ items, uint64_t* __restrict__ keys,
-                           uint32_t* __restrict__ vals, int4* __restrict__ red) {
+// Items (box, first entry, end entry, partial slot base or -1) and the
+// reduce records (box, nseg, base) of the boxes cut into several segments
+__global__ void k_seg_emit(const int* __restrict__ off, const int* __restrict__ tcount, int nbox, int seg,
+                           const int* __restrict__ nseg, const int* __restrict__ item_off,
+                           const int* __restrict__ slot_off, const int* __restrict__ red_off,
+                           int4* __restrict__ items, int4* __restrict__ red) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
     const int ns = nseg[b];
@@ -224,19 +231,28 @@ __global__ void k_seg_emit(const int* __restrict__ off, const int* __restrict__ 
     const int nt = tcount[b];
     for (int sg = 0; sg < ns; ++sg) {
         const int kb = off[b] + sg * seg, ke = min(kb + seg, off[b + 1]);
-        long long w = 0;
-        if (count) {
-            for (int k = kb; k < ke; ++k) w += count[src[k]];
-        } else {
-            w = ke - kb;
-        }
-        w *= nt;
-        const int it = item_off[b] + sg;
-        items[it] = make_int4(b, kb, ke, ns > 1 ? slot_off[b] + sg * nt : -1);
-        keys[it] = (w > 0) ? (uint64_t)__clzll((unsigned long long)w) : 255ULL;
-        vals[it] = (uint32_t)it;
+        items[item_off[b] + sg] = make_int4(b, kb, ke, ns > 1 ? slot_off[b] + sg * nt : -1);
     }
     if (ns > 1) red[red_off[b]] = make_int4(b, ns, slot_off[b], 0);
+}
+
+// Sort key of each item: leading zeros of its work, targets x particles (or
+// targets x entries when count is null); heaviest power-of-two bucket first
+__global__ void k_item_keys(const int4* __restrict__ items, int n, const int* __restrict__ src,
+                            const int* __restrict__ count, const int* __restrict__ tcount,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int4 it = items[i];
+    long long w = 0;
+    if (count) {
+        for (int k = it.y; k < it.z; ++k) w += count[src[k]];
+    } else {
+        w = it.z - it.y;
+    }
+    w *= tcount[it.x];
+    keys[i] = (w > 0) ? (uint64_t)__clzll((unsigned long long)w) : 255ULL;
+    vals[i] = (uint32_t)i;
 }
 
 __global__ void k_gather_items(const int4* __restrict__ in, const uint32_t* __restrict__ idx, int n,
@@ -279,9 +295,10 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     raw.resize(out.n);
     keys.resize(out.n);
     vals.resize(out.n);
-    k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, src, count, tcount, nbox, seg, nseg.data(), item_off.data(),
-                                               slot_off.data(), red_off.data(), raw.data(), keys.data(),
-                                               vals.data(), out.red.data());
+    k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), item_off.data(),
+                                               slot_off.data(), red_off.data(), raw.data(), out.red.data());
+    SFMM_LAUNCH_CHECK();
+    k_item_keys<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), out.n, src, count, tcount, keys.data(), vals.data());
     SFMM_LAUNCH_CHECK();
     radix_sort_u64(keys.data(), vals.data(), out.n, 8, s);
     k_gather_items<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), vals.data(), out.n, out.items.data());

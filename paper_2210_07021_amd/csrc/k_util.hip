@@ -96,28 +96,35 @@ void fill_i32(int* p, size_t n, int v, hipStream_t s) {
 
 // ------------------------------------------------------------------ scan
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// block-wide exclusive scan of one value per thread (256 threads)
+// block-wide exclusive scan of one value per thread (256 threads = 4 waves):
+// inclusive scan inside each wave by shuffles, then the wave totals
 __device__ int block_excl_scan(int v, int* sh, int* total) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        int a = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += a;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    const int incl = sh[t];
-    *total = sh[kScanThreads - 1];
+    if (lane == 63) sh[wv] = x;
     __syncthreads();
-    return incl - v;
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const int ws = sh[w];
+        before += (w < wv) ? ws : 0;
+        all += ws;
+    }
+    *total = all;
+    __syncthreads();  // sh may be reused by the caller
+    return before + x - v;
 }
 
 __global__ void k_scan_tiles(const int* in, int* out, int64_t n, int* bsum) {
-    __shared__ int sh[kScanThreads];
+    __shared__ int sh[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
@@ -143,26 +150,26 @@ __global__ void k_scan_add(int* out, int64_t n, const int* boff) {
         if (base + k < n) out[base + k] += add;
 }
 
-__global__ void k_scan_total(const int* in, const int* out, int64_t n, int* total) {
-    *total = (n > 0) ? out[n - 1] + in[n - 1] : 0;
-}
-
+// Tile scans write each tile's sum to bsum; with a single tile that sum is
+// the total.  Otherwise the tile sums are scanned (their total is the total)
+// and added back.  In place (in == out) is allowed.
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s) {
     if (n <= 0) {
         fill_i32(total, 1, 0, s);
         return;
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    int* bsum = (int*)pool_alloc(sizeof(int) * (nb + 1));
-    int* boff = (int*)pool_alloc(sizeof(int) * (nb + 1));
+    if (nb == 1) {
+        k_scan_tiles<<<1, kScanThreads, 0, s>>>(in, out, n, total);
+        SFMM_LAUNCH_CHECK();
+        return;
+    }
+    int* bsum = (int*)pool_alloc(sizeof(int) * nb);
+    int* boff = (int*)pool_alloc(sizeof(int) * nb);
     k_scan_tiles<<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, bsum);
     SFMM_LAUNCH_CHECK();
-    if (nb > 1) {
-        scan_excl_i32(bsum, boff, nb, boff + nb, s);
-        k_scan_add<<<(unsigned)nb, kScanThreads, 0, s>>>(out, n, boff);
-        SFMM_LAUNCH_CHECK();
-    }
-    k_scan_total<<<1, 1, 0, s>>>(in, out, n, total);
+    scan_excl_i32(bsum, boff, nb, total, s);
+    k_scan_add<<<(unsigned)nb, kScanThreads, 0, s>>>(out, n, boff);
     SFMM_LAUNCH_CHECK();
     // freed blocks are only reused by later stream-ordered work on this stream
     pool_free(bsum);

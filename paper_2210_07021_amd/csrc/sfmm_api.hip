@@ -546,10 +546,12 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->n_p2p = P.n_p2p;
         out->n_target_leaves = P.ntl;
         if (P.n_p2p_pairs < 0 && P.nbox > 0) {
-            DVec<long long> tot;
+            DVec<long long> w, tot;
+            w.resize(2 * (size_t)P.nbox);
             tot.resize(2);
-            sum_i64(P.nl.pairs.data(), P.nbox, tot.data(), nullptr);
-            sum_i64(P.nl.evals.data(), P.nbox, tot.data() + 1, nullptr);
+            near_work(P.count.data(), P.nl, P.tcount.data(), P.nbox, w.data(), w.data() + P.nbox, nullptr);
+            sum_i64(w.data(), P.nbox, tot.data(), nullptr);
+            sum_i64(w.data() + P.nbox, P.nbox, tot.data() + 1, nullptr);
             long long h[2];
             SFMM_HIP(hipMemcpy(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost));
             P.n_p2p_pairs = h[0];
@@ -626,8 +628,11 @@ sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pair
         const sfmm_plan_impl& P = *plan;
         if (P.N == 0 || P.nbox == 0) return SFMM_OK;
         copy_widen(tgt_count, P.tcount.data(), P.nbox);
-        copy_widen(pairs, P.nl.pairs.data(), P.nbox);
-        copy_widen(evals, P.nl.evals.data(), P.nbox);
+        DVec<long long> w;
+        w.resize(2 * (size_t)P.nbox);
+        near_work(P.count.data(), P.nl, P.tcount.data(), P.nbox, w.data(), w.data() + P.nbox, nullptr);
+        copy_widen(pairs, w.data(), P.nbox);
+        copy_widen(evals, w.data() + P.nbox, P.nbox);
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);

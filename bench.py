@@ -31,6 +31,44 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_P2P_PAIR = 66
 
 
+# Source files of each timed kernel: the traffic measured by the counters is
+# only used while these files are unchanged.
+KERNEL_SOURCES = {
+    "m2l": ["k_fmm.hip", "expand.hpp", "common.hpp"],
+    "p2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
+    "m2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
+}
+KERNEL_NAMES = {"m2l": "k_m2l", "p2p": "k_p2p", "m2p": "k_m2p"}
+
+
+def source_hash(stage: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[stage]:
+        with open(os.path.join(ROOT, "paper_2210_07021_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, stage: str):
+    """HBM bytes per launch (read + write) of a stage's kernel, from the
+    committed counter summary profiles/traffic_<workload>.md (lines
+    'traffic <stage> read=<bytes> write=<bytes> src=<hash>'), or None when
+    there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 5 and parts[0] == "traffic" and parts[1] == stage:
+                kv = dict(x.split("=", 1) for x in parts[2:])
+                if kv["src"] != source_hash(stage):
+                    return None
+                return float(kv["read"]) + float(kv["write"])
+    return None
+
+
 def m2l_flops(p: int) -> int:
     """Algorithmic flops of one Lemma 3 translation at order p: two
     triangular Taylor-shift factors (p(p+1) complex*real FMAs, 4p^2 + 4p
@@ -143,8 +181,8 @@ def main():
     dom = max(work, key=lambda k: stages_ms[k])
     bound, flops, peak, unit = work[dom]
     achieved = flops / (stages_ms[dom] * 1e-3) / 1e12
-    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None,
+    roofline = {"kernel": KERNEL_NAMES[dom], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
                 "work_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
 
     result = {

@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--leaf-size", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-tier (FP32 mixed) leg")
+    ap.add_argument("--fp32-tolerance", type=float, default=1e-6)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (scale for the traffic counters) and exit")
     args = ap.parse_args()
@@ -140,37 +142,49 @@ def main():
         opts["tolerance"] = args.tolerance
     torch.cuda.synchronize()
 
-    def step():
-        plan = sf.Plan(src, q, tgt, **opts)
-        plan.execute(psi, defl)
-        return plan
+    def run(opts, out_psi, out_defl, label):
+        """W untimed steps, then K timed ones; returns (seconds, stage ms, stats)."""
+        def step():
+            plan = sf.Plan(src, q, tgt, **opts)
+            plan.execute(out_psi, out_defl)
+            return plan
 
-    for w in range(args.warmup):
-        t = time.time()
-        plan = step()
+        for w in range(args.warmup):
+            t = time.time()
+            plan = step()
+            torch.cuda.synchronize()
+            stats = plan.stats()
+            plan.close()
+            log(f"[bench] {label} warmup {w}: {time.time() - t:.3f}s")
+        if args.warmup == 0:
+            plan = step()
+            stats = plan.stats()
+            plan.close()
+        sf.profile_reset()
+        sf.profile_enable(True)
         torch.cuda.synchronize()
-        stats = plan.stats()
-        plan.close()
-        log(f"[bench] warmup {w}: {time.time() - t:.3f}s")
-    if args.warmup == 0:
-        plan = step()
-        stats = plan.stats()
-        plan.close()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            plan = step()
+            plan.close()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sf.profile_enable(False)
+        prof = sf.profile_read()
+        log(f"[bench] {label}: {args.steps} steps in {t1 - t0:.3f}s")
+        return t1 - t0, {k: v[0] / args.steps for k, v in prof.items()}, stats
 
-    sf.profile_reset()
-    sf.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        plan = step()
-        plan.close()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sf.profile_enable(False)
-    prof = sf.profile_read()
-    elapsed = t1 - t0
-    log(f"[bench] {args.steps} steps in {elapsed:.3f}s")
-    stages_ms = {k: v[0] / args.steps for k, v in prof.items()}
+    elapsed, stages_ms, stats = run(opts, psi, defl, "fp64")
+    fp32 = None
+    if not args.no_fp32:
+        # the precision tier at its own tolerance, same workload
+        psi32 = torch.empty_like(psi)
+        defl32 = torch.empty_like(defl)
+        e32, st32, s32 = run(dict(leaf_size=args.leaf_size, tolerance=args.fp32_tolerance,
+                                  precision=sf.SFMM_FP32_MIXED), psi32, defl32, "fp32-mixed")
+        fp32 = {"value": M * args.steps / e32, "unit": "targets/s", "ms_per_step": 1e3 * e32 / args.steps,
+                "tolerance": args.fp32_tolerance, "order": s32["order"], "dtype": "f32+f64",
+                "stages_ms": {k: round(v, 4) for k, v in st32.items()}}
 
     p = stats["order"]
     work = {
@@ -206,6 +220,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
         "roofline": roofline,
     }
+    if fp32 is not None:
+        result["fp32_mixed"] = fp32
 
     if not args.no_cpu_baseline:
         import oracle
@@ -234,6 +250,13 @@ def main():
             "psi_rel_l2": float(np.linalg.norm(psi_h[idx] - ref_p) / np.linalg.norm(ref_p)),
             "alpha_rel_l2": float(np.linalg.norm(defl_h[:, idx] - ref_a) / np.linalg.norm(ref_a)),
             "targets": k}
+        if fp32 is not None:
+            p32 = psi32.cpu().numpy()
+            d32 = defl32.cpu().numpy()
+            fp32["accuracy"] = {
+                "psi_rel_l2": float(np.linalg.norm(p32[idx] - ref_p) / np.linalg.norm(ref_p)),
+                "alpha_rel_l2": float(np.linalg.norm(d32[:, idx] - ref_a) / np.linalg.norm(ref_a)),
+                "targets": k}
     print(json.dumps(result), flush=True)
 
 

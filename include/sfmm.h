@@ -53,7 +53,12 @@ typedef enum {
 } sfmm_status;
 
 enum { SFMM_GAUGE_ZERO_MEAN = 0, SFMM_GAUGE_RAW = 1 };
-enum { SFMM_FP64 = 0 };
+/* SFMM_FP64: every step in FP64.  SFMM_FP32_MIXED: the precision tier -- the
+ * pair sums of the near field and the M2L coefficient arithmetic in FP32
+ * (two-float coordinates, per-tile FP64 sums), everything else (keys, tree,
+ * P2M, M2M, L2L, L2P, C and Q of every expansion, the final sums) in FP64.
+ * Meant for tolerances of 1e-6 and above; outputs are FP64 in both modes. */
+enum { SFMM_FP64 = 0, SFMM_FP32_MIXED = 1 };
 
 typedef struct {
     int32_t order;      /* truncation order p of Eq. MUL_ERR, 1..48; 0 = pick p
@@ -65,7 +70,7 @@ typedef struct {
     double c_s;         /* MAC1 constant of Sec. 3.5 (default 2)              */
     double c_t;         /* MAC2 constant of Sec. 3.5 (default 0.5)            */
     int32_t max_level;  /* maximum depth r_max of Sec. 3.1, 0..29 (default 29) */
-    int32_t precision;  /* SFMM_FP64                                          */
+    int32_t precision;  /* SFMM_FP64 (default) or SFMM_FP32_MIXED              */
     int32_t psi_gauge;  /* SFMM_GAUGE_ZERO_MEAN (default) or SFMM_GAUGE_RAW   */
     int32_t reserved[9];
 } sfmm_options;

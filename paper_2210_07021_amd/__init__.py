@@ -22,6 +22,7 @@ SFMM_OK = 0
 SFMM_GAUGE_ZERO_MEAN = 0
 SFMM_GAUGE_RAW = 1
 SFMM_FP64 = 0
+SFMM_FP32_MIXED = 1
 
 
 class SfmmError(RuntimeError):

@@ -137,8 +137,14 @@ void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int*
 void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild,
                const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p,
                int p2p_base, hipStream_t s);
-// M2L order: longest list first (16-bit keys, ties in table order)
-void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s);
+// M2L order: boxes of levels <= lc first, then the others; longest list
+// first within each part (16-bit keys, ties in table order)
+void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
+                    hipStream_t s);
+// precision tier: M2L into boxes of levels <= kFp32CoarseLevel stays FP64
+// (the large contributions of coarse boxes nearly cancel on smooth skies,
+// which FP32 rounding would show)
+constexpr int kFp32CoarseLevel = 6;
 // pairs (target << 32 | source) sorted by target -> CSR offsets and sources
 void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src, hipStream_t s);
 // sort keys (8 bits) putting the boxes with the most work first, in
@@ -164,6 +170,10 @@ struct FmmCtx {
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s);
 void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s);
 void fmm_m2l(const FmmCtx& c, const int* order, int n, const int* off, const int* src, hipStream_t s);
+// precision tier M2L over the n boxes order[0..n): multf receives the FP32
+// A-blocks of all nbox multipoles first ([nbox][2p])
+void fmm_m2l_f32(const FmmCtx& c, float* multf, int nbox, const int* order, int n, const int* off,
+                 const int* src, hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
              const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
@@ -195,9 +205,11 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
 // targets x far leaves
 void near_work(const int* count, const NearLists& nl, const int* tcount, int nbox, long long* pairs,
                long long* evals, hipStream_t s);
-void fmm_p2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
-             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s);
+// fp32: the precision tier's pair arithmetic (two-float coordinates, FP32
+// log / reciprocal, FP64 sums per tile)
+void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
+             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
+             double* psi, double* defl, int64_t m_out, hipStream_t s);
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
              double* defl, int64_t m_out, hipStream_t s);

@@ -251,6 +251,71 @@ SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
 
 // Lemma 1 for a set of particles about centre f with scale rho; C carries the
 // zero-mean gauge's share sum q / (4 pi) (Eq. STAND_CONDITION).
+// The precision tier's Lemma 3 translation: the A-block (scaled, FP32, A[2l-2]
+// = Re A_l, A[2l-1] = Im A_l) goes through the same factorised map in FP32
+// and is added to the FP32 accumulator acc[2P]; C and Q stay FP64 (accCQ).
+// The pair geometry G is computed in FP64 and rounded once.
+struct cplxf {
+    float re, im;
+};
+SFMM_HD cplxf cmulf(cplxf a, cplxf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+template <int P>
+SFMM_HD void translate_add_f32(const float* __restrict__ A, double C, double Q, const TransGeom& G, float* acc,
+                               double* accCQ) {
+    float ar[P + 1], ai[P + 1];
+    ar[0] = 0.0f;
+    ai[0] = 0.0f;
+    const cplxf ph1 = {(float)G.ph1.re, (float)G.ph1.im}, ph2 = {(float)G.ph2.re, (float)G.ph2.im};
+    const float a = (float)G.a, b = (float)G.b, g = (float)G.g;
+    cplxf pw = ph1;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplxf v = cmulf(pw, cplxf{A[2 * l - 2], A[2 * l - 1]});
+        ar[l] = v.re;
+        ai[l] = v.im;
+        pw = cmulf(pw, ph1);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int j = P - 1; j >= i; --j) {
+            ar[j] = fmaf(b, ar[j + 1], ar[j]);
+            ai[j] = fmaf(b, ai[j + 1], ai[j]);
+        }
+    }
+    const double u0 = (double)ar[0];
+    float gn = g;
+#pragma unroll
+    for (int n = 1; n <= P; ++n) {
+        ar[n] *= gn;
+        ai[n] *= gn;
+        gn *= g;
+    }
+#pragma unroll
+    for (int i = P - 2; i >= 0; --i) {
+#pragma unroll
+        for (int j = i; j <= P - 2; ++j) {
+            ar[j + 2] = fmaf(a, ar[j + 1], ar[j + 2]);
+            ai[j + 2] = fmaf(a, ai[j + 1], ai[j + 2]);
+        }
+    }
+    const float qf = (float)Q;
+    cplxf pw2 = ph2;
+    float an = a;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplxf v = {ar[l] - qf * (1.0f / l) * an, ai[l]};
+        const cplxf o = cmulf(pw2, v);
+        acc[2 * l - 2] += o.re;
+        acc[2 * l - 1] += o.im;
+        pw2 = cmulf(pw2, ph2);
+        an *= a;
+    }
+    accCQ[0] += C + Q * G.clog + 2.0 * u0;
+    accCQ[1] += Q;
+}
+
 template <int P>
 struct P2MAcc {
     double sre[P], sim[P];

@@ -353,13 +353,81 @@ __device__ __forceinline__ void emit_target(int slot, int64_t o, double ps, doub
 }
 
 // ------------------------------------------------------------ direct sums
+// Pair terms of one lane over one LDS tile.  FP64: coordinates as stored.
+// FP32 (precision tier): every coordinate is a two-float pair hi + lo
+// (hi = float(x), lo = float(x - hi)), so d = (t_hi - s_hi) + (t_lo - s_lo)
+// keeps ~1e-7 relative accuracy for close points where plain FP32 positions
+// would lose all digits of d; log and reciprocal are the hardware FP32
+// instructions, and each tile's FP32 partial sums (at most 256 terms) are
+// added to FP64 running sums.
+struct TileF64 {
+    double4 p[kTile];
+};
+struct TileF32 {
+    float4 hi[kTile];  // x, y, z, q
+    float4 lo[kTile];  // x, y, z low parts
+};
+
+__device__ __forceinline__ void tile_store(TileF64& t, int k, double x, double y, double z, double q) {
+    t.p[k] = make_double4(x, y, z, q);
+}
+__device__ __forceinline__ void tile_store(TileF32& t, int k, double x, double y, double z, double q) {
+    const float xh = (float)x, yh = (float)y, zh = (float)z;
+    t.hi[k] = make_float4(xh, yh, zh, (float)q);
+    t.lo[k] = make_float4((float)(x - (double)xh), (float)(y - (double)yh), (float)(z - (double)zh), 0.0f);
+}
+
+__device__ __forceinline__ void tile_pairs(const TileF64& t, int r, int L, int tn, double ax, double ay, double az,
+                                           double& p0, double& p1, double& p2, double& p3) {
+    for (int j = r; j < tn; j += L) {
+        const double4 sp = t.p[j];
+        const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
+        const bool coinc = (dx == 0.0) & (dy == 0.0) & (dz == 0.0);
+        const double r2 = coinc ? 1.0 : dx * dx + dy * dy + dz * dz;
+        const double lg = coinc ? kLog4 : log_f64(r2);
+        const double wi = sp.w * recip(r2);
+        p0 = fma(sp.w, lg, p0);
+        p1 = fma(wi, dx, p1);
+        p2 = fma(wi, dy, p2);
+        p3 = fma(wi, dz, p3);
+    }
+}
+
+__device__ __forceinline__ void tile_pairs(const TileF32& t, int r, int L, int tn, double ax, double ay, double az,
+                                           double& p0, double& p1, double& p2, double& p3) {
+    const float axh = (float)ax, ayh = (float)ay, azh = (float)az;
+    const float axl = (float)(ax - (double)axh), ayl = (float)(ay - (double)ayh), azl = (float)(az - (double)azh);
+    constexpr float kLn2f = 0.693147180559945309f, kLog4f = 1.38629436111989061f;
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
+    for (int j = r; j < tn; j += L) {
+        const float4 h = t.hi[j], l = t.lo[j];
+        const float dx = (axh - h.x) + (axl - l.x);
+        const float dy = (ayh - h.y) + (ayl - l.y);
+        const float dz = (azh - h.z) + (azl - l.z);
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const bool coinc = d2 == 0.0f;
+        const float r2 = coinc ? 1.0f : d2;
+        const float lg = coinc ? kLog4f : __builtin_amdgcn_logf(r2) * kLn2f;
+        const float wi = h.w * __builtin_amdgcn_rcpf(r2);
+        f0 = fmaf(h.w, lg, f0);
+        f1 = fmaf(wi, dx, f1);
+        f2 = fmaf(wi, dy, f2);
+        f3 = fmaf(wi, dz, f3);
+    }
+    p0 += (double)f0;
+    p1 += (double)f1;
+    p2 += (double)f2;
+    p3 += (double)f3;
+}
+
+template <class Tile>
 __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ items,
                                            const int* __restrict__ src, const int* __restrict__ tfirst,
                                            const int* __restrict__ tcount, const double* __restrict__ tx,
                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
                                            double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
-    __shared__ double4 tile[kTile];
+    __shared__ Tile tile;
     __shared__ double red[4][64];
     const int lane = threadIdx.x;
     const int4 item = items[blockIdx.x];
@@ -417,24 +485,11 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                     const int base = __shfl(fst, e, 64) - __shfl(excl, e, 64);
                     if (f < total) {
                         const int i = base + f;
-                        tile[j * 64 + lane] = make_double4(sx[i], sy[i], sz[i], sq[i]);
+                        tile_store(tile, j * 64 + lane, sx[i], sy[i], sz[i], sq[i]);
                     }
                 }
                 __syncthreads();
-                if (active) {
-                    for (int j = r; j < tn; j += L) {
-                        const double4 sp = tile[j];
-                        const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
-                        const bool coinc = (dx == 0.0) & (dy == 0.0) & (dz == 0.0);
-                        const double r2 = coinc ? 1.0 : dx * dx + dy * dy + dz * dz;
-                        const double lg = coinc ? kLog4 : log_f64(r2);
-                        const double wi = sp.w * recip(r2);
-                        p0 = fma(sp.w, lg, p0);
-                        p1 = fma(wi, dx, p1);
-                        p2 = fma(wi, dy, p2);
-                        p3 = fma(wi, dz, p3);
-                    }
-                }
+                if (active) tile_pairs(tile, r, L, tn, ax, ay, az, p0, p1, p2, p3);
             }
         }
         const double qn = wave_sum(qnear);
@@ -564,12 +619,16 @@ void reduce_items(const WorkItems& w, const int* tfirst, const int* tcount, cons
     SFMM_LAUNCH_CHECK();
 }
 
-void fmm_p2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
-             const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s) {
+void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
+             const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
+             double* psi, double* defl, int64_t m_out, hipStream_t s) {
     if (w.n <= 0) return;
-    k_p2p<<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, defl, m_out,
-                                       w.part.data());
+    if (fp32)
+        k_p2p<TileF32><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
+                                                    defl, m_out, w.part.data());
+    else
+        k_p2p<TileF64><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
+                                                    defl, m_out, w.part.data());
     SFMM_LAUNCH_CHECK();
     reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
 }

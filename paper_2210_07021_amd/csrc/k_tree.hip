@@ -339,21 +339,25 @@ void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* s
     }
 }
 
-__global__ void k_m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals) {
+// M2L order keys: boxes of levels <= lc first (bit 15 clear), then the rest;
+// longest list first within each part (lengths beyond 2^15 - 1 tie)
+__global__ void k_m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys,
+                                 uint32_t* vals) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
     const uint32_t len = (uint32_t)(off[b + 1] - off[b]);
-    keys[b] = (uint64_t)(0xffffu - (len < 0xffffu ? len : 0xffffu));  // longest lists first
+    const uint64_t fine = level[b] > lc ? 1 : 0;
+    keys[b] = (fine << 15) | (uint64_t)(0x7fffu - (len < 0x7fffu ? len : 0x7fffu));
     vals[b] = (uint32_t)b;
 }
 
-void m2l_order_keys(const int* off, int nbox, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
+                    hipStream_t s) {
     if (nbox <= 0) return;
-    k_m2l_order_keys<<<nblocks(nbox, 256), 256, 0, s>>>(off, nbox, keys, vals);
+    k_m2l_order_keys<<<nblocks(nbox, 256), 256, 0, s>>>(off, level, lc, nbox, keys, vals);
     SFMM_LAUNCH_CHECK();
 }
 
-// key = leading zeros of the work (heaviest power-of-two bucket first, 8 bits)
 __global__ void k_work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;

@@ -113,6 +113,7 @@ struct sfmm_plan_impl {
     // interaction lists in CSR form by target box
     int n_m2l = 0, n_p2p = 0;
     DVec<int> m2l_off, m2l_src, p2p_off, p2p_src, m2l_order;
+    int n_m2l_fp64 = 0;  // the first n_m2l_fp64 boxes of m2l_order take the FP64 M2L
     // targets, sorted by key
     DVec<double> tx, ty, tz;
     DVec<uint32_t> tperm;
@@ -125,6 +126,7 @@ struct sfmm_plan_impl {
     mutable long long n_p2p_pairs = -1, n_m2p_evals = -1;  // summed on the first stats request
     // expansions
     DVec<double> mult, local;
+    DVec<float> multf;  // precision tier: FP32 A-blocks of the multipoles
     bool executed = false;
     std::unique_ptr<Pinned> pin;
 
@@ -164,7 +166,7 @@ void validate(const sfmm_options& o) {
     if (!(o.c_s > 0.0) || !std::isfinite(o.c_s)) bad("c_s must be positive");
     if (!(o.c_t > 0.0 && o.c_t < 1.0)) bad("c_t must be in (0, 1)");
     if (o.max_level < 0 || o.max_level > 29) bad("max_level must be in [0, 29]");
-    if (o.precision != SFMM_FP64) bad("unknown precision");
+    if (o.precision != SFMM_FP64 && o.precision != SFMM_FP32_MIXED) bad("unknown precision");
     if (o.psi_gauge != SFMM_GAUGE_ZERO_MEAN && o.psi_gauge != SFMM_GAUGE_RAW) bad("unknown psi_gauge");
 }
 
@@ -316,8 +318,13 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     DVec<uint32_t> v;
     k.resize(P.nbox);
     v.resize(P.nbox);
-    m2l_order_keys(P.m2l_off.data(), P.nbox, k.data(), v.data(), s);
+    // precision tier: boxes of the coarse levels first (they stay FP64)
+    const bool tier = P.opt.precision == SFMM_FP32_MIXED;
+    const int lc = tier ? kFp32CoarseLevel : 29;
+    m2l_order_keys(P.m2l_off.data(), P.level.data(), lc, P.nbox, k.data(), v.data(), s);
     radix_sort_u64(k.data(), v.data(), P.nbox, 16, s);
+    const int nlev = (int)P.lvl_start.size() - 1;
+    P.n_m2l_fp64 = tier ? P.lvl_start[std::min(lc + 1, nlev)] : P.nbox;
     P.m2l_order.resize(P.nbox);
     SFMM_HIP(hipMemcpyAsync(P.m2l_order.data(), v.data(), sizeof(int) * P.nbox, hipMemcpyDeviceToDevice, s));
     SFMM_HIP(hipStreamSynchronize(s));
@@ -492,7 +499,12 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         // FMM acts: Lemma 3
         {
             StageScope st(prof, S_M2L);
-            fmm_m2l(c, P.m2l_order.data(), P.nbox, P.m2l_off.data(), P.m2l_src.data(), s);
+            fmm_m2l(c, P.m2l_order.data(), P.n_m2l_fp64, P.m2l_off.data(), P.m2l_src.data(), s);
+            if (P.n_m2l_fp64 < P.nbox) {
+                P.multf.resize((size_t)P.nbox * 2 * P.p);
+                fmm_m2l_f32(c, P.multf.data(), P.nbox, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
+                            P.m2l_off.data(), P.m2l_src.data(), s);
+            }
         }
         // down-pass: Lemma 4 from level 1 down
         {
@@ -512,7 +524,7 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         }
         {
             StageScope st(prof, S_P2P);
-            fmm_p2p(c, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
+            fmm_p2p(c, P.opt.precision == SFMM_FP32_MIXED, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
                     P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
         }
         prof.flush();

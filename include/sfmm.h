@@ -60,6 +60,32 @@ enum { SFMM_GAUGE_ZERO_MEAN = 0, SFMM_GAUGE_RAW = 1 };
  * Meant for tolerances of 1e-6 and above; outputs are FP64 in both modes. */
 enum { SFMM_FP64 = 0, SFMM_FP32_MIXED = 1 };
 
+/* Order of each FMM act (Lemma 3 pair).  FIXED: every pair at the plan order
+ * p.  Otherwise a pair at order p' < p translates its multipole part at p'
+ * (A_1..A_p' of the source in, local coefficients 1..p' out) and its
+ * monopole part at p.  BOUND: p' = the smallest multiple of 4 (<= p) with
+ * x^(p'+1) (p'+1) / (1 - x) <= SFMM_ORDER_KAPPA tolerance (the form of
+ * Eq. MUL_ERR for the pair's convergence ratio x, relative to the source's
+ * multipole strength W_S = sum_l |A_l| rho_S^-l).  LEARNED: p' predicted by
+ * the order network (weights in sfmm_options.mlp_weights) for the same
+ * criterion measured exactly; see sfmm_order_samples / sfmm_mlp_train.  With
+ * BOUND and LEARNED the plan order is rounded up to a multiple of 4. */
+enum { SFMM_ORDER_FIXED = 0, SFMM_ORDER_BOUND = 1, SFMM_ORDER_LEARNED = 2 };
+#define SFMM_ORDER_KAPPA 0.1
+
+/* The order network: kMlpIn = 8 features -> 64 ReLU -> 64 ReLU -> 1.  Weight
+ * array of SFMM_MLP_WEIGHTS floats, in this order: W1 [64][8] (row = hidden
+ * unit), b1 [64], W2 [64][64], b2 [64], w3 [64], b3.  Features of a pair
+ * (target box T, source box S; a, b the shift parameters of the factorised
+ * Lemma 3 translation, g its diagonal ratio, x = max(a + b, sqrt g)): x,
+ * a/(a + b) (1/2 when a + b = 0), log10(kappa tol)/16, then
+ * log10(|A_l| / |Q|)/8 of S's scaled multipole at l = 1, 4, 8, 16, and
+ * level(T)/29.  The output y predicts (order - 16) / 8; the learned policy
+ * uses the order ceil(16 + 8 y + 2) rounded up to a multiple of 4, at most p. */
+#define SFMM_MLP_IN 8
+#define SFMM_MLP_HIDDEN 64
+#define SFMM_MLP_WEIGHTS (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
+
 typedef struct {
     int32_t order;      /* truncation order p of Eq. MUL_ERR, 1..48; 0 = pick p
                            from `tolerance`                                   */
@@ -72,7 +98,10 @@ typedef struct {
     int32_t max_level;  /* maximum depth r_max of Sec. 3.1, 0..29 (default 29) */
     int32_t precision;  /* SFMM_FP64 (default) or SFMM_FP32_MIXED              */
     int32_t psi_gauge;  /* SFMM_GAUGE_ZERO_MEAN (default) or SFMM_GAUGE_RAW   */
-    int32_t reserved[9];
+    int32_t order_policy;      /* SFMM_ORDER_FIXED (default), _BOUND, _LEARNED */
+    const float* mlp_weights;  /* host, SFMM_MLP_WEIGHTS floats; read (copied)
+                                  by sfmm_plan when order_policy is LEARNED  */
+    int32_t reserved[6];
 } sfmm_options;
 
 typedef struct {
@@ -85,6 +114,9 @@ typedef struct {
                                        the leaf's multipole expansion instead  */
     int32_t order, leaf_size;
     double q_total;                 /* sum of the masses                        */
+    int64_t m2l_order_sq;           /* sum over the FMM acts of (their order)^2
+                                       in the last sfmm_execute (the M2L work
+                                       relative to one order-1 act); 0 before */
 } sfmm_stats;
 
 /* Fill *opt with the defaults: order 0 with tolerance 1e-10, leaf_size 64,
@@ -144,6 +176,35 @@ sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pair
  * multipole and local are [n_boxes][2p+2] = (C, Q, Re A_1, Im A_1, ...,
  * Re A_p, Im A_p).  C is reported without the zero-mean gauge share. */
 sfmm_status sfmm_export_expansions(sfmm_plan_t plan, double* multipole, double* local);
+
+/* Training data for the order network, from an executed plan: n FMM-act
+ * pairs drawn with the seed (uniformly, with replacement), their features
+ * [n][SFMM_MLP_IN] and their labels [n]: the smallest multiple of 4 (<= the
+ * plan order p) for which the pair's Lemma 3 translation truncated at that
+ * order (multipole part; monopole part kept at p) differs from the order-p
+ * translation by sum_l l |dA'_l| <= SFMM_ORDER_KAPPA tolerance W_S (scaled
+ * local coefficients, FP64).  Host buffers.  Errors: plan not executed, n < 0,
+ * NULL buffers with n > 0. */
+sfmm_status sfmm_order_samples(sfmm_plan_t plan, int64_t n, uint64_t seed, float* features, float* labels,
+                               int64_t* pairs /* [n][2] (target box, source box), may be NULL */);
+
+/* Order network, all host buffers.
+ * sfmm_mlp_init: He-initialised weights from the seed.
+ * sfmm_mlp_train: Adam (lr), `epochs` passes over the n samples in shuffled
+ *   minibatches of `batch`, loss per sample w r^2 (r = prediction - label,
+ *   w = 4 for r < 0, else 1); weights are read and overwritten; epoch_loss
+ *   [epochs] (may be NULL) receives the mean loss of each epoch.
+ * sfmm_mlp_forward: y [n] = network(features); bf16 != 0 rounds weights and
+ *   activations to bfloat16 as the learned policy does, else FP32.
+ * sfmm_mlp_grad: gradient [SFMM_MLP_WEIGHTS] and value of the mean loss over
+ *   the n samples (FP32 network).
+ * Errors: n < 0 or NULL buffers with n > 0, batch < 1, epochs < 0. */
+void sfmm_mlp_init(uint64_t seed, float* weights);
+sfmm_status sfmm_mlp_train(const float* features, const float* labels, int64_t n, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float* weights, float* epoch_loss);
+sfmm_status sfmm_mlp_forward(const float* weights, const float* features, int64_t n, int32_t bf16, float* y);
+sfmm_status sfmm_mlp_grad(const float* weights, const float* features, const float* labels, int64_t n,
+                          float* grad, float* loss);
 
 void sfmm_destroy(sfmm_plan_t plan);
 const char* sfmm_status_string(sfmm_status s);

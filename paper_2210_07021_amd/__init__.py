@@ -23,6 +23,12 @@ SFMM_GAUGE_ZERO_MEAN = 0
 SFMM_GAUGE_RAW = 1
 SFMM_FP64 = 0
 SFMM_FP32_MIXED = 1
+SFMM_ORDER_FIXED = 0
+SFMM_ORDER_BOUND = 1
+SFMM_ORDER_LEARNED = 2
+MLP_IN = 8
+MLP_HIDDEN = 64
+MLP_WEIGHTS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 
 class SfmmError(RuntimeError):
@@ -41,7 +47,9 @@ class Options(ctypes.Structure):
         ("max_level", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("psi_gauge", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 9),
+        ("order_policy", ctypes.c_int32),
+        ("mlp_weights", ctypes.c_void_p),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -60,6 +68,7 @@ class Stats(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("leaf_size", ctypes.c_int32),
         ("q_total", ctypes.c_double),
+        ("m2l_order_sq", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -79,6 +88,12 @@ SIGNATURES = {
     "sfmm_export_keys": (ctypes.c_int, [_P] * 6),
     "sfmm_export_work": (ctypes.c_int, [_P] * 4),
     "sfmm_export_expansions": (ctypes.c_int, [_P] * 3),
+    "sfmm_order_samples": (ctypes.c_int, [_P, _I64, ctypes.c_uint64, _P, _P, _P]),
+    "sfmm_mlp_init": (None, [ctypes.c_uint64, _P]),
+    "sfmm_mlp_train": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                      ctypes.c_uint64, _P, _P]),
+    "sfmm_mlp_forward": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int32, _P]),
+    "sfmm_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P]),
     "sfmm_destroy": (None, [_P]),
     "sfmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sfmm_last_error": (ctypes.c_char_p, []),
@@ -99,6 +114,14 @@ def load_library(path: str = LIB_PATH):
     """Load libsfmm.so and declare its signatures.  Raises if it is missing."""
     global _lib
     if _lib is None:
+        # torch carries its own HIP runtime; the two share the device only when
+        # torch's is up first (device tensors are passed to this library)
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         if not os.path.exists(path):
             raise RuntimeError(f"libsfmm.so not found at {path}: build it with "
                                "`python -m paper_2210_07021_amd.build` (no fallback exists)")
@@ -125,6 +148,57 @@ def default_options(**overrides) -> Options:
             raise TypeError(f"unknown option {k!r}")
         setattr(opt, k, v)
     return opt
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """He-initialised order-network weights (sfmm_mlp_init)."""
+    w = np.zeros(MLP_WEIGHTS, np.float32)
+    load_library().sfmm_mlp_init(ctypes.c_uint64(seed), w.ctypes.data_as(_P))
+    return w
+
+
+def mlp_train(features, labels, weights, epochs=20, batch=1024, lr=1e-3, seed=0):
+    """Train the order network on the GPU (sfmm_mlp_train); returns (weights,
+    mean loss per epoch)."""
+    f = _f32(features)
+    l = _f32(labels)
+    n = l.shape[0]
+    if f.shape != (n, MLP_IN):
+        raise ValueError("features must be [n][8]")
+    w = _f32(weights, (MLP_WEIGHTS,)).copy()
+    loss = np.zeros(max(epochs, 1), np.float32)
+    _check(load_library().sfmm_mlp_train(f.ctypes.data_as(_P), l.ctypes.data_as(_P), n, epochs, batch,
+                                         ctypes.c_float(lr), ctypes.c_uint64(seed), w.ctypes.data_as(_P),
+                                         loss.ctypes.data_as(_P)))
+    return w, loss[:epochs]
+
+
+def mlp_forward(weights, features, bf16=False) -> np.ndarray:
+    f = _f32(features)
+    w = _f32(weights, (MLP_WEIGHTS,))
+    y = np.zeros(f.shape[0], np.float32)
+    _check(load_library().sfmm_mlp_forward(w.ctypes.data_as(_P), f.ctypes.data_as(_P), f.shape[0],
+                                           1 if bf16 else 0, y.ctypes.data_as(_P)))
+    return y
+
+
+def mlp_grad(weights, features, labels):
+    """Gradient of the mean training loss and the loss (sfmm_mlp_grad)."""
+    f = _f32(features)
+    l = _f32(labels)
+    w = _f32(weights, (MLP_WEIGHTS,))
+    g = np.zeros(MLP_WEIGHTS, np.float32)
+    loss = ctypes.c_float()
+    _check(load_library().sfmm_mlp_grad(w.ctypes.data_as(_P), f.ctypes.data_as(_P), l.ctypes.data_as(_P),
+                                        l.shape[0], g.ctypes.data_as(_P), ctypes.byref(loss)))
+    return g, float(loss.value)
 
 
 def order_for_tolerance(tol: float) -> int:
@@ -180,7 +254,12 @@ class Plan:
             raise ValueError("q must have shape (N,)")
         self.N = int(self.src.shape[1])
         self.M = int(self.tgt.shape[1])
+        weights = options.pop("mlp_weights", None)
         self.options = default_options(**options)
+        if weights is not None:
+            # read by sfmm_plan only; kept alive until then
+            self._mlp_weights = _f32(weights, (MLP_WEIGHTS,))
+            self.options.mlp_weights = self._mlp_weights.ctypes.data
         self._stream = stream
         self._h = ctypes.c_void_p()
         _check(self._lib.sfmm_plan(
@@ -229,6 +308,17 @@ class Plan:
                    tgt_leaf=np.zeros(self.M, np.int64))
         _check(self._lib.sfmm_export_keys(self._h, *[a.ctypes.data_as(_P) for a in out.values()]))
         return out
+
+    def order_samples(self, n: int, seed: int = 0, with_pairs: bool = False):
+        """Features [n][8] and exact order labels [n] of n sampled FMM acts of
+        this executed plan (sfmm_order_samples), and their (target, source)
+        boxes [n][2] if asked."""
+        f = np.zeros((n, MLP_IN), np.float32)
+        l = np.zeros(n, np.float32)
+        pr = np.zeros((n, 2), np.int64)
+        _check(self._lib.sfmm_order_samples(self._h, n, ctypes.c_uint64(seed), f.ctypes.data_as(_P),
+                                            l.ctypes.data_as(_P), pr.ctypes.data_as(_P) if with_pairs else None))
+        return (f, l, pr) if with_pairs else (f, l)
 
     def export_work(self) -> dict:
         nb = self.stats()["n_boxes"]

@@ -76,6 +76,15 @@ struct DVec {
 };
 
 constexpr int kMaxOrder = 48;
+// per-pair order policies: orders are multiples of kOrderStep; the order
+// network maps kMlpIn features through two kMlpHidden ReLU layers to one
+// output (kMlpWeights floats: W1, b1, W2, b2, w3, b3)
+constexpr int kOrderStep = 4;
+// the network predicts (order - kOrderCenter) / kOrderScale; kOrderMargin
+// orders are added before rounding up
+constexpr float kOrderCenter = 16.0f, kOrderScale = 8.0f, kOrderMargin = 2.0f;
+constexpr int kMlpIn = 8, kMlpHidden = 64;
+constexpr int kMlpWeights = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
 
 // every order 1..kMaxOrder is a template instance; SFMM_DISPATCH(p, X) runs
 // X(P) for the runtime order p
@@ -92,6 +101,7 @@ constexpr int kMaxOrder = 48;
 
 // ---------------------------------------------------------------- utilities
 void fill_f64(double* p, size_t n, double v, hipStream_t s);
+void fill_f32(float* p, size_t n, float v, hipStream_t s);
 void fill_i32(int* p, size_t n, int v, hipStream_t s);
 // exclusive scan of n ints; the total goes to *total (device)
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s);
@@ -169,10 +179,14 @@ struct FmmCtx {
 };
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s);
 void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s);
-void fmm_m2l(const FmmCtx& c, const int* order, int n, const int* off, const int* src, hipStream_t s);
-// precision tier M2L over the n boxes order[0..n): multf receives the FP32
-// A-blocks of all nbox multipoles first ([nbox][2p])
-void fmm_m2l_f32(const FmmCtx& c, float* multf, int nbox, const int* order, int n, const int* off,
+// M2L at order p <= c.p over the boxes order[0..n) (order may be null: box
+// i); acc_in adds to the local records instead of overwriting them
+void fmm_m2l(const FmmCtx& c, int p, bool acc_in, const int* order, int n, const int* off, const int* src,
+             hipStream_t s);
+// precision tier: FP32 copy of the multipole A-blocks ([nbox][2 c.p]), and
+// M2L with FP32 A-block arithmetic (p, acc_in, order as fmm_m2l)
+void mult_to_f32(const FmmCtx& c, int nbox, float* multf, hipStream_t s);
+void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n, const int* off,
                  const int* src, hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
@@ -213,5 +227,30 @@ void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, con
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
              double* defl, int64_t m_out, hipStream_t s);
+
+// ---------------------------------------------------------------- order policies
+void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s);
+void order_box_decay(const FmmCtx& c, int nbox, float4* decay, hipStream_t s);
+void order_features(const FmmCtx& c, const int* ent_t, const int* src, const int* idx, int64_t n,
+                    const float4* decay, double kappa_tol, float* feat, hipStream_t s);
+void order_bound(const FmmCtx& c, const int* ent_t, const int* src, int np, double kappa_tol, uint8_t* ord,
+                 hipStream_t s);
+// feat null: the features of pairs 0..n) are computed in place from (c, ent_t, src, decay, kappa_tol)
+void order_mlp(const FmmCtx& c, const int* ent_t, const int* src, const float4* decay, double kappa_tol,
+               const float* feat, int64_t n, const float* w, int pmax, float margin, uint8_t* ord, float* y,
+               hipStream_t s);
+// monopole part of the local coefficients above each pair's order (pairs in
+// the full CSR off/src with their orders ord)
+void m2l_qtail(const FmmCtx& c, const int* off, const int* src, const uint8_t* ord, int nbox, hipStream_t s);
+void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* idx, int n, double kappa_tol,
+                  float* label, hipStream_t s);
+// split pairs by order into CSR lists boff + q nbox (q = order / kOrderStep - 1)
+// over bsrc; returns the sum of the orders squared
+long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
+                      DVec<int>& boff, DVec<int>& bsrc, hipStream_t s);
+void mlp_grad(const float* w, const float* feat, const float* label, int n, float* rec, float* grad, hipStream_t s);
+void mlp_adam(float* w, float* m, float* v, const float* grad, float lr, int step, hipStream_t s);
+void mlp_forward_f32(const float* w, const float* feat, int n, float* y, hipStream_t s);
+size_t mlp_record_floats();
 
 }  // namespace sfmm

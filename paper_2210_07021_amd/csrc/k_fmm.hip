@@ -58,52 +58,59 @@ __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
 }
 
 // Lemma 3: each target box sums its FMM-act list (boxes taken longest list
-// first so the lanes of a wave carry similar work)
+// first so the lanes of a wave carry similar work).  P is the order of the
+// translation, c.p that of the records (P <= c.p: a per-pair order policy
+// runs one pass per order with the pairs of that order, adding to the
+// record's first 2P+2 entries, acc = true).
 template <int P>
-__global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, const int* off, const int* src) {
+__global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, const int* off, const int* src,
+                                            bool acc_in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
     if (k0 == k1) return;
+    const size_t ew = 2 * (size_t)c.p + 2;
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
+    double* out = c.local + (size_t)t * ew;
     double acc[2 * P + 2];
 #pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = acc_in ? out[k] : 0.0;
     for (int k = k0; k < k1; ++k) {
         const int s = src[k];
         double rho_s;
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
-        translate_add<P>(c.mult + (size_t)s * (2 * P + 2), G, acc);
+        translate_add<P>(c.mult + (size_t)s * ew, G, acc);
     }
-    double* out = c.local + (size_t)t * (2 * P + 2);
 #pragma unroll
     for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
 }
 
-// Precision tier: FP32 copy of every multipole A-block, [nb][2P]
-template <int P>
-__global__ void k_mult_to_f32(const double* __restrict__ mult, int nb, float* __restrict__ out) {
+// Precision tier: FP32 copy of every multipole A-block, [nb][2p]
+__global__ void k_mult_to_f32(const double* __restrict__ mult, int p, int nb, float* __restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= (int64_t)nb * 2 * P) return;
-    const int64_t b = i / (2 * P), k = i - b * (2 * P);
-    out[i] = (float)mult[b * (2 * P + 2) + 2 + k];
+    if (i >= (int64_t)nb * 2 * p) return;
+    const int64_t b = i / (2 * p), k = i - b * (2 * p);
+    out[i] = (float)mult[b * (2 * p + 2) + 2 + k];
 }
 
-// Precision tier Lemma 3: the lists as in k_m2l, FP32 A-blocks and FP32
-// translation arithmetic, FP64 C and Q; the local record is written in FP64
+// Precision tier Lemma 3: the lists as in k_m2l, FP32 A-blocks (multf,
+// [nb][2 c.p]) and FP32 translation arithmetic, FP64 C and Q; the local
+// record is written in FP64.  P and acc_in as in k_m2l.
 template <int P>
 __global__ void __launch_bounds__(128) k_m2l_f32(FmmCtx c, const float* __restrict__ multf, const int* order, int n,
-                                                const int* off, const int* src) {
+                                                const int* off, const int* src, bool acc_in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
     if (k0 == k1) return;
+    const size_t ew = 2 * (size_t)c.p + 2, fw = 2 * (size_t)c.p;
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
+    double* out = c.local + (size_t)t * ew;
     float acc[2 * P];
 #pragma unroll
     for (int k = 0; k < 2 * P; ++k) acc[k] = 0.0f;
@@ -113,14 +120,20 @@ __global__ void __launch_bounds__(128) k_m2l_f32(FmmCtx c, const float* __restri
         double rho_s;
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
-        const double* e = c.mult + (size_t)s * (2 * P + 2);
-        translate_add_f32<P>(multf + (size_t)s * (2 * P), e[0], e[1], G, acc, cq);
+        const double* e = c.mult + (size_t)s * ew;
+        translate_add_f32<P>(multf + (size_t)s * fw, e[0], e[1], G, acc, cq);
     }
-    double* out = c.local + (size_t)t * (2 * P + 2);
-    out[0] = cq[0];
-    out[1] = cq[1];
+    if (acc_in) {
+        out[0] += cq[0];
+        out[1] += cq[1];
 #pragma unroll
-    for (int k = 0; k < 2 * P; ++k) out[2 + k] = (double)acc[k];
+        for (int k = 0; k < 2 * P; ++k) out[2 + k] += (double)acc[k];
+    } else {
+        out[0] = cq[0];
+        out[1] = cq[1];
+#pragma unroll
+        for (int k = 0; k < 2 * P; ++k) out[2 + k] = (double)acc[k];
+    }
 }
 
 // Lemma 4: every box of one level takes its parent's local expansion
@@ -179,23 +192,28 @@ void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s) {
     SFMM_LAUNCH_CHECK();
 }
 
-void fmm_m2l(const FmmCtx& c, const int* order, int n, const int* off, const int* src, hipStream_t s) {
+void fmm_m2l(const FmmCtx& c, int p, bool acc_in, const int* order, int n, const int* off, const int* src,
+             hipStream_t s) {
     if (n <= 0) return;
-#define L_(P) case P: k_m2l<P><<<nblk(n, 128), 128, 0, s>>>(c, order, n, off, src); break;
-    SFMM_DISPATCH(c.p, L_)
+    if (p < 1 || p > c.p) throw Error(ST_INTERNAL, "M2L order above the record order");
+#define L_(P) case P: k_m2l<P><<<nblk(n, 128), 128, 0, s>>>(c, order, n, off, src, acc_in); break;
+    SFMM_DISPATCH(p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
 }
 
-void fmm_m2l_f32(const FmmCtx& c, float* multf, int nbox, const int* order, int n, const int* off,
+void mult_to_f32(const FmmCtx& c, int nbox, float* multf, hipStream_t s) {
+    if (nbox <= 0) return;
+    k_mult_to_f32<<<nblk((int64_t)nbox * 2 * c.p, 256), 256, 0, s>>>(c.mult, c.p, nbox, multf);
+    SFMM_LAUNCH_CHECK();
+}
+
+void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n, const int* off,
                  const int* src, hipStream_t s) {
-    if (n <= 0 || nbox <= 0) return;
-#define L_(P)                                                                                         \
-    case P:                                                                                           \
-        k_mult_to_f32<P><<<nblk((int64_t)nbox * 2 * P, 256), 256, 0, s>>>(c.mult, nbox, multf);        \
-        k_m2l_f32<P><<<nblk(n, 128), 128, 0, s>>>(c, multf, order, n, off, src);                       \
-        break;
-    SFMM_DISPATCH(c.p, L_)
+    if (n <= 0) return;
+    if (p < 1 || p > c.p) throw Error(ST_INTERNAL, "M2L order above the record order");
+#define L_(P) case P: k_m2l_f32<P><<<nblk(n, 128), 128, 0, s>>>(c, multf, order, n, off, src, acc_in); break;
+    SFMM_DISPATCH(p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
 }

@@ -1,0 +1,496 @@
+// Per-interaction truncation order for the FMM acts (Lemma 3).
+//
+// The plan order p (from the tolerance) is what the worst pair needs.  A
+// pair whose boxes are well separated converges faster: with the factorised
+// translation of k_m2l its terms fall like x^n, x = a + b (a = rho_T cot(T/2),
+// b = rho_S cot(T/2); exactly antipodal centres, where a = b = 0, converge
+// like g^n, g = rho_T rho_S: x = max(a + b, sqrt g)).  A pair at order p' < p
+// keeps its monopole part exact
+// (the -(Q/l) a^l terms of the local coefficients for every l <= p, added by
+// k_m2l_qtail: on smooth skies these large terms cancel between pairs, so
+// they must not be cut) and truncates the multipole part: the source's
+// A_1..A_p' in, the local coefficients up to p' out.  Its error is of the
+// order of
+//     W_S x^(p'+1) (p'+1) / (1 - x),   W_S = sum_l |Ah_l| (scaled multipole),
+// the shape of Eq. MUL_ERR with W_S in place of Q~ and the extra p'+1 of a
+// gradient.  Two policies pick p' per pair from the criterion
+// e(p') <= kappa tol W_S:
+//   * bound:   the smallest p' (multiple of kOrderStep) whose bound above
+//              meets it;
+//   * learned: a 3 x 64 MLP that maps per-pair features to p', trained on
+//              labels that the FP64 translation itself produces: the exact
+//              e(p') = sum_l l |A'_l(p) - A'_l(p')| over the local
+//              coefficients (scaled by rho_T^l) of the pair.
+// Pairs are then split per target box into one list per order (a stable
+// counting split), and the M2L runs once per order over its lists, adding
+// into the local records.
+#include "common.hpp"
+#include "expand.hpp"
+
+namespace sfmm {
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
+
+// ------------------------------------------------------------ features
+// log10 |A_l| / |Q| of a source multipole at l = 1, 4, 8, 16 (scaled
+// coefficients; orders above p repeat the last one), clamped to [-40, 5]
+__global__ void k_box_decay(const double* __restrict__ mult, int p, int nb, float4* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double* e = mult + (size_t)b * (2 * p + 2);
+    const double q = fabs(e[1]) + 1e-300;
+    float v[4];
+    const int ls[4] = {1, 4, 8, 16};
+    for (int k = 0; k < 4; ++k) {
+        const int l = ls[k] < p ? ls[k] : p;
+        const double m = sqrt(e[2 * l] * e[2 * l] + e[2 * l + 1] * e[2 * l + 1]);
+        double lg = log10(m / q + 1e-40);
+        lg = lg < -40.0 ? -40.0 : (lg > 5.0 ? 5.0 : lg);
+        v[k] = (float)lg;
+    }
+    out[b] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// Shift parameters a, b of the pair's factorised Lemma 3 and its convergence
+// ratio x = max(a + b, sqrt(g)): the terms of the translated coefficients
+// fall like (a + b)^n, and like g^n through the diagonal, which alone is
+// left for exactly antipodal centres (a = b = 0, g = rho_T rho_S); for any
+// other pair sqrt(g) <= (a + b) / 2.
+__device__ __forceinline__ double pair_ratio(const FmmCtx& c, int t, int s, double* a, double* b) {
+    const double* ct = c.cen + 4 * (size_t)t;
+    const double* cs = c.cen + 4 * (size_t)s;
+    const Frame ft = make_frame(ct[0], ct[1], ct[2]);
+    const Frame fs = make_frame(cs[0], cs[1], cs[2]);
+    const TransGeom G = trans_geom<kM2L>(fs, cs[3], ft, ct[3]);
+    *a = G.a;
+    *b = G.b;
+    return fmax(G.a + G.b, sqrt(G.g));
+}
+
+// Features of pair k (target ent_t[k], source src[k]), kMlpIn floats:
+// x, a/x, log10(kappa tol)/16, the source's four decay values / 8, level_T / 29
+__device__ __forceinline__ void pair_feature_vec(const FmmCtx& c, int t, int s, const float4* __restrict__ decay,
+                                                 float ltol, float* f) {
+    double a, b;
+    const double x = pair_ratio(c, t, s, &a, &b);
+    const float4 d = decay[s];
+    f[0] = (float)x;
+    f[1] = a + b > 0.0 ? (float)(a / (a + b)) : 0.5f;  // a + b = 0: exactly antipodal base pixels
+    f[2] = ltol / 16.0f;
+    f[3] = d.x / 8.0f;
+    f[4] = d.y / 8.0f;
+    f[5] = d.z / 8.0f;
+    f[6] = d.w / 8.0f;
+    f[7] = (float)c.level[t] / 29.0f;
+}
+
+__global__ void k_pair_features(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src,
+                                const int* __restrict__ idx, int64_t n, const float4* __restrict__ decay,
+                                float ltol, float* __restrict__ feat) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k = idx ? idx[i] : i;
+    pair_feature_vec(c, ent_t[k], src[k], decay, ltol, feat + i * kMlpIn);
+}
+
+// ------------------------------------------------------------ bound policy
+__device__ __forceinline__ int round_order(int p, int pmax) {
+    int q = ((p + kOrderStep - 1) / kOrderStep) * kOrderStep;
+    q = q < kOrderStep ? kOrderStep : q;
+    return q > pmax ? pmax : q;
+}
+
+__global__ void k_order_bound(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src, int np,
+                              double eps, int pmax, uint8_t* __restrict__ ord) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    double a, b;
+    const double x = pair_ratio(c, ent_t[k], src[k], &a, &b);
+    int p = pmax;
+    if (x < 1.0) {
+        double xp = x;  // x^(q+1) for q = 0, 1, ...
+        for (int q = 1; q <= pmax; ++q) {
+            xp *= x;
+            if (xp * (q + 1) / (1.0 - x) <= eps) {
+                p = q;
+                break;
+            }
+        }
+    }
+    ord[k] = (uint8_t)round_order(p, pmax);
+}
+
+// ------------------------------------------------------------ learned policy
+// MLP: h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3, with
+// the weights in one array (layout in sfmm.h).  Inference rounds weights,
+// inputs and hidden activations to bfloat16 (the network's storage format)
+// and accumulates in FP32.
+__device__ __forceinline__ float bf16_round(float v) {
+    // round to nearest even on the upper 16 bits (finite inputs)
+    unsigned u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// The network runs on the bf16 matrix cores (v_mfma_f32_32x32x8bf16_1k,
+// D[32x32] += A[32x8] B[8x32], FP32 accumulate), one wave per tile of 32
+// pairs, activations kept transposed ([hidden unit][pair]):
+//   * A operands are weights (rows = output units, k = input units): lane l
+//     holds A[l % 32][4 (l / 32) + r], r = 0..3;
+//   * B operands are activations (k = input units, columns = pairs): lane l
+//     holds B[4 (l / 32) + r][l % 32];
+//   * D: lane l holds D[8 g + 4 (l / 32) + r][l % 32] in element 4 g + r.
+// So the D fragment of a 32-unit block of layer 1 is, group g by group g,
+// exactly the B operand of layer 2's k-step covering units 8 g .. 8 g + 7 of
+// that block: no data moves between the layers.  Layer 3 is a dot product
+// over the 32 units a lane holds, completed with its partner lane l ^ 32.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float v) { return (short)(__float_as_uint(bf16_round(v)) >> 16); }
+
+__global__ void __launch_bounds__(256) k_order_mlp(FmmCtx c, const int* __restrict__ ent_t,
+                                                   const int* __restrict__ src, const float4* __restrict__ decay,
+                                                   float ltol, const float* __restrict__ feat, int64_t n,
+                                                   const float* __restrict__ w, int pmax, float margin,
+                                                   uint8_t* __restrict__ ord, float* __restrict__ yout) {
+    constexpr int H = kMlpHidden, I = kMlpIn;
+    const float* W1 = w;
+    const float* B1 = W1 + H * I;
+    const float* W2 = B1 + H;
+    const float* B2 = W2 + H * H;
+    const float* W3 = B2 + H;
+    __shared__ float sb1[H], sb2[H], sw3[H + 1];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+        sb1[i] = bf16_round(B1[i]);
+        sb2[i] = bf16_round(B2[i]);
+        sw3[i] = bf16_round(W3[i]);
+    }
+    if (threadIdx.x == 0) sw3[H] = bf16_round(W3[H]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
+    // weight fragments, held for every tile of this wave
+    bf16x4 a1[2], a2[2][8];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a1[rb][r] = bf16_bits(W1[(32 * rb + col) * I + 4 * half + r]);
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int st = 0; st < 8; ++st)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a2[ob][st][r] = bf16_bits(W2[(32 * ob + col) * H + 8 * st + 4 * half + r]);
+    const int64_t ntiles = (n + 31) / 32;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        const int64_t k = tile * 32 + col;
+        float f[I];
+        if (k < n) {
+            if (feat) {
+#pragma unroll
+                for (int j = 0; j < I; ++j) f[j] = feat[k * I + j];
+            } else {
+                pair_feature_vec(c, ent_t[k], src[k], decay, ltol, f);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < I; ++j) f[j] = 0.0f;
+        }
+        bf16x4 b0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b0[r] = bf16_bits(half ? f[4 + r] : f[r]);
+        // layer 1 -> layer 2 operands
+        bf16x4 b1[8];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            f32x16 d = {};
+            d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[rb], b0, d, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float v = d[4 * g + r] + sb1[32 * rb + 8 * g + 4 * half + r];
+                    b1[4 * rb + g][r] = bf16_bits(v > 0.0f ? v : 0.0f);
+                }
+        }
+        // layer 2, layer 3
+        float y = 0.0f;
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            f32x16 d = {};
+#pragma unroll
+            for (int st = 0; st < 8; ++st) d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][st], b1[st], d, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int u = 32 * ob + 8 * g + 4 * half + r;
+                    const float v = d[4 * g + r] + sb2[u];
+                    y = fmaf(sw3[u], bf16_round(v > 0.0f ? v : 0.0f), y);
+                }
+        }
+        y += __shfl_xor(y, 32, 64);
+        y += sw3[H];
+        if (half == 0 && k < n) {
+            if (yout) yout[k] = y;
+            if (ord) {
+                const float pf = kOrderCenter + kOrderScale * y + margin;
+                const int p = pf >= (float)pmax ? pmax : (pf <= 1.0f ? 1 : (int)ceilf(pf));
+                ord[k] = (uint8_t)round_order(p, pmax);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ labels
+// Lemma 3 at a run-time order pc: the multipole part from A_1..A_pc into
+// the local coefficients 1..pc, the monopole part into all coefficients up
+// to pmax (what the per-order passes plus k_m2l_qtail compute), in the same
+// factorised arithmetic as translate_add; out has 2 pmax + 2 entries.
+__device__ void translate_rt(const double* in, const TransGeom& G, int pc, int pmax, double* out) {
+    double ar[kMaxOrder + 1], ai[kMaxOrder + 1];
+    const double C = in[0], Q = in[1];
+    ar[0] = ai[0] = 0.0;
+    cplx pw = G.ph1;
+    for (int l = 1; l <= pc; ++l) {
+        const cplx v = cmul(pw, cplx{in[2 * l], in[2 * l + 1]});
+        ar[l] = v.re;
+        ai[l] = v.im;
+        pw = cmul(pw, G.ph1);
+    }
+    for (int i = 0; i < pc; ++i)
+        for (int j = pc - 1; j >= i; --j) {
+            ar[j] = fma(G.b, ar[j + 1], ar[j]);
+            ai[j] = fma(G.b, ai[j + 1], ai[j]);
+        }
+    const double u0 = ar[0];
+    double gn = G.g;
+    for (int l = 1; l <= pc; ++l) {
+        ar[l] *= gn;
+        ai[l] *= gn;
+        gn *= G.g;
+    }
+    for (int i = pc - 2; i >= 0; --i)
+        for (int j = i; j <= pc - 2; ++j) {
+            ar[j + 2] = fma(G.a, ar[j + 1], ar[j + 2]);
+            ai[j + 2] = fma(G.a, ai[j + 1], ai[j + 2]);
+        }
+    cplx pw2 = G.ph2;
+    double an = G.a;
+    for (int l = 1; l <= pmax; ++l) {
+        const cplx v = {(l <= pc ? ar[l] : 0.0) - Q * (1.0 / l) * an, l <= pc ? ai[l] : 0.0};
+        const cplx o = cmul(pw2, v);
+        out[2 * l] = o.re;
+        out[2 * l + 1] = o.im;
+        pw2 = cmul(pw2, G.ph2);
+        an *= G.a;
+    }
+    out[0] = C + Q * G.clog + 2.0 * u0;
+    out[1] = Q;
+}
+
+// label[i] = smallest p' (multiple of kOrderStep, at most p) with
+// sum_l l |A'_l(p) - A'_l(p')| <= eps W_S for pair idx[i]; scratch holds
+// 2 (2p + 2) doubles per lane
+__global__ void k_order_labels(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src,
+                               const int* __restrict__ idx, int n, double eps, double* __restrict__ scratch,
+                               float* __restrict__ label) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = idx[i];
+    const int t = ent_t[k], s = src[k];
+    const int p = c.p;
+    const size_t ew = 2 * (size_t)p + 2;
+    const double* ct = c.cen + 4 * (size_t)t;
+    const double* cs = c.cen + 4 * (size_t)s;
+    const Frame ft = make_frame(ct[0], ct[1], ct[2]);
+    const Frame fs = make_frame(cs[0], cs[1], cs[2]);
+    const TransGeom G = trans_geom<kM2L>(fs, cs[3], ft, ct[3]);
+    const double* in = c.mult + (size_t)s * ew;
+    double ws = 0.0;
+    for (int l = 1; l <= p; ++l) ws += sqrt(in[2 * l] * in[2 * l] + in[2 * l + 1] * in[2 * l + 1]);
+    double* full = scratch + (size_t)i * 2 * ew;
+    double* tr = full + ew;
+    translate_rt(in, G, p, p, full);
+    const double lim = eps * ws;
+    int best = p;
+    for (int pc = kOrderStep; pc < p; pc += kOrderStep) {
+        translate_rt(in, G, pc, p, tr);
+        double e = 0.0;
+        for (int l = 1; l <= p; ++l) {
+            const double dr = full[2 * l] - tr[2 * l], di = full[2 * l + 1] - tr[2 * l + 1];
+            e += l * sqrt(dr * dr + di * di);
+        }
+        if (e <= lim) {
+            best = pc;
+            break;
+        }
+    }
+    label[i] = (float)best;
+}
+
+// The monopole part of the local coefficients above each pair's order:
+// A'_l += e^(-i l phi_S^(T)) (-(Q/l) a^l) for ord < l <= p (c.p), one lane per
+// target box over its whole list, added to the record once.
+template <int P>
+__global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restrict__ off,
+                                                  const int* __restrict__ src, const uint8_t* __restrict__ ord,
+                                                  int nbox) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbox) return;
+    const int k0 = off[t], k1 = off[t + 1];
+    bool any = false;
+    for (int k = k0; k < k1; ++k) any |= ord[k] < P;
+    if (!any) return;
+    const double* ct = c.cen + 4 * (size_t)t;
+    const Frame ft = make_frame(ct[0], ct[1], ct[2]);
+    double acc[2 * P];
+#pragma unroll
+    for (int l = 0; l < 2 * P; ++l) acc[l] = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int lo = ord[k];
+        if (lo >= P) continue;
+        const int s = src[k];
+        const double* cs = c.cen + 4 * (size_t)s;
+        const Frame fs = make_frame(cs[0], cs[1], cs[2]);
+        const TransGeom G = trans_geom<kM2L>(fs, cs[3], ft, ct[3]);
+        const double Q = c.mult[(size_t)s * (2 * P + 2) + 1];
+        cplx pw2 = G.ph2;
+        double an = G.a;
+#pragma unroll
+        for (int l = 1; l <= P; ++l) {
+            if (l > lo) {
+                const double v = -Q * (1.0 / l) * an;
+                acc[2 * l - 2] = fma(pw2.re, v, acc[2 * l - 2]);
+                acc[2 * l - 1] = fma(pw2.im, v, acc[2 * l - 1]);
+            }
+            pw2 = cmul(pw2, G.ph2);
+            an *= G.a;
+        }
+    }
+    double* out = c.local + (size_t)t * (2 * P + 2);
+#pragma unroll
+    for (int l = 0; l < 2 * P; ++l) out[2 + l] += acc[l];
+}
+
+// ------------------------------------------------------------ split by order
+// cnt[q * nbox + T] = pairs of T with order (q + 1) kOrderStep
+__global__ void k_order_count(const int* __restrict__ off, const uint8_t* __restrict__ ord, int nbox, int nq,
+                              int* __restrict__ cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbox) return;
+    int c[kMaxOrder / kOrderStep];
+    for (int q = 0; q < nq; ++q) c[q] = 0;
+    for (int k = off[t]; k < off[t + 1]; ++k) ++c[ord[k] / kOrderStep - 1];
+    for (int q = 0; q < nq; ++q) cnt[(size_t)q * nbox + t] = c[q];
+}
+
+// stable scatter of each box's entries into the list of their order; boff
+// is the exclusive scan of cnt (so the lists of order q are the CSR boff +
+// q nbox, with absolute offsets into bsrc)
+__global__ void k_order_scatter(const int* __restrict__ off, const int* __restrict__ src,
+                                const uint8_t* __restrict__ ord, int nbox, int nq, const int* __restrict__ boff,
+                                int* __restrict__ bsrc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbox) return;
+    int pos[kMaxOrder / kOrderStep];
+    for (int q = 0; q < nq; ++q) pos[q] = boff[(size_t)q * nbox + t];
+    for (int k = off[t]; k < off[t + 1]; ++k) {
+        const int q = ord[k] / kOrderStep - 1;
+        bsrc[pos[q]++] = src[k];
+    }
+}
+
+// sum of p'^2 over the pairs (work of the bucketed M2L relative to p^2)
+__global__ void k_order_sq(const uint8_t* __restrict__ ord, int np, long long* __restrict__ part) {
+    __shared__ long long sh[256];
+    long long v = 0;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < np; k += gridDim.x * 256) v += (long long)ord[k] * ord[k];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// ------------------------------------------------------------ host side
+void order_box_decay(const FmmCtx& c, int nbox, float4* decay, hipStream_t s) {
+    if (nbox <= 0) return;
+    k_box_decay<<<nblk(nbox, 256), 256, 0, s>>>(c.mult, c.p, nbox, decay);
+    SFMM_LAUNCH_CHECK();
+}
+
+void order_features(const FmmCtx& c, const int* ent_t, const int* src, const int* idx, int64_t n,
+                    const float4* decay, double kappa_tol, float* feat, hipStream_t s) {
+    if (n <= 0) return;
+    k_pair_features<<<nblk(n, 256), 256, 0, s>>>(c, ent_t, src, idx, n, decay, (float)log10(kappa_tol), feat);
+    SFMM_LAUNCH_CHECK();
+}
+
+void order_bound(const FmmCtx& c, const int* ent_t, const int* src, int np, double kappa_tol, uint8_t* ord,
+                 hipStream_t s) {
+    if (np <= 0) return;
+    k_order_bound<<<nblk(np, 256), 256, 0, s>>>(c, ent_t, src, np, kappa_tol, c.p, ord);
+    SFMM_LAUNCH_CHECK();
+}
+
+void order_mlp(const FmmCtx& c, const int* ent_t, const int* src, const float4* decay, double kappa_tol,
+               const float* feat, int64_t n, const float* w, int pmax, float margin, uint8_t* ord, float* y,
+               hipStream_t s) {
+    if (n <= 0) return;
+    // one wave per 32 pairs, a few tiles per wave
+    const int64_t waves = std::min<int64_t>((n + 31) / 32, 4096 * 4);
+    k_order_mlp<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(c, ent_t, src, decay, (float)log10(kappa_tol), feat, n,
+                                                            w, pmax, margin, ord, y);
+    SFMM_LAUNCH_CHECK();
+}
+
+void m2l_qtail(const FmmCtx& c, const int* off, const int* src, const uint8_t* ord, int nbox, hipStream_t s) {
+    if (nbox <= 0) return;
+#define L_(P) case P: k_m2l_qtail<P><<<nblk(nbox, 128), 128, 0, s>>>(c, off, src, ord, nbox); break;
+    SFMM_DISPATCH(c.p, L_)
+#undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* idx, int n, double kappa_tol,
+                  float* label, hipStream_t s) {
+    if (n <= 0) return;
+    DVec<double> scratch;
+    scratch.resize((size_t)n * 2 * (2 * c.p + 2));
+    k_order_labels<<<nblk(n, 64), 64, 0, s>>>(c, ent_t, src, idx, n, kappa_tol, scratch.data(), label);
+    SFMM_LAUNCH_CHECK();
+    SFMM_HIP(hipStreamSynchronize(s));
+}
+
+long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
+                      DVec<int>& boff, DVec<int>& bsrc, hipStream_t s) {
+    const int nq = pmax / kOrderStep;
+    DVec<int> cnt, tot;
+    cnt.resize((size_t)nq * nbox);
+    boff.resize((size_t)nq * nbox + 1);
+    bsrc.resize(std::max(np, 1));
+    tot.resize(1);
+    k_order_count<<<nblk(nbox, 256), 256, 0, s>>>(off, ord, nbox, nq, cnt.data());
+    SFMM_LAUNCH_CHECK();
+    scan_excl_i32(cnt.data(), boff.data(), (int64_t)nq * nbox, boff.data() + (size_t)nq * nbox, s);
+    k_order_scatter<<<nblk(nbox, 256), 256, 0, s>>>(off, src, ord, nbox, nq, boff.data(), bsrc.data());
+    SFMM_LAUNCH_CHECK();
+    DVec<long long> part, sum;
+    const int nb = 256;
+    part.resize(nb);
+    sum.resize(1);
+    k_order_sq<<<nb, 256, 0, s>>>(ord, np, part.data());
+    SFMM_LAUNCH_CHECK();
+    sum_i64(part.data(), nb, sum.data(), s);
+    long long h = 0;
+    SFMM_HIP(hipMemcpyAsync(&h, sum.data(), sizeof(h), hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+}  // namespace sfmm

@@ -153,6 +153,12 @@ __global__ void k_near_work(const int* __restrict__ count, const int* __restrict
     evals[b] = (long long)(far_off[b + 1] - far_off[b]) * (long long)tcount[b];
 }
 
+void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s) {
+    if (np <= 0 || nbox <= 0) return;
+    k_entry_box<<<nblk(np, 256), 256, 0, s>>>(off, nbox, np, ent_t);
+    SFMM_LAUNCH_CHECK();
+}
+
 void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
                 const int* tcount, const double* tx, const double* ty, const double* tz, NearLists& out,
                 hipStream_t s) {

@@ -88,6 +88,12 @@ void fill_f64(double* p, size_t n, double v, hipStream_t s) {
     SFMM_LAUNCH_CHECK();
 }
 
+void fill_f32(float* p, size_t n, float v, hipStream_t s) {
+    if (!n) return;
+    k_fill<float><<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+    SFMM_LAUNCH_CHECK();
+}
+
 void fill_i32(int* p, size_t n, int v, hipStream_t s) {
     if (!n) return;
     k_fill<int><<<grid_for(n, 256), 256, 0, s>>>(p, n, v);

@@ -127,6 +127,13 @@ struct sfmm_plan_impl {
     // expansions
     DVec<double> mult, local;
     DVec<float> multf;  // precision tier: FP32 A-blocks of the multipoles
+    // per-pair order policies
+    DVec<int> m2l_ent;        // target box of every FMM-act entry
+    DVec<float> mlp_w;        // order network (learned policy)
+    DVec<float4> decay;       // per-box multipole decay features
+    DVec<uint8_t> m2l_ord;    // order of every FMM act (last execute)
+    DVec<int> ord_off, ord_src;  // FMM acts split by order
+    long long m2l_order_sq = 0;
     bool executed = false;
     std::unique_ptr<Pinned> pin;
 
@@ -168,6 +175,10 @@ void validate(const sfmm_options& o) {
     if (o.max_level < 0 || o.max_level > 29) bad("max_level must be in [0, 29]");
     if (o.precision != SFMM_FP64 && o.precision != SFMM_FP32_MIXED) bad("unknown precision");
     if (o.psi_gauge != SFMM_GAUGE_ZERO_MEAN && o.psi_gauge != SFMM_GAUGE_RAW) bad("unknown psi_gauge");
+    if (o.order_policy != SFMM_ORDER_FIXED && o.order_policy != SFMM_ORDER_BOUND &&
+        o.order_policy != SFMM_ORDER_LEARNED)
+        bad("unknown order_policy");
+    if (o.order_policy == SFMM_ORDER_LEARNED && !o.mlp_weights) bad("the learned order policy needs mlp_weights");
 }
 
 // Sort points by key and keep the permutation; outputs resized here.
@@ -396,6 +407,11 @@ void export_csr(const DVec<int>& off, const DVec<int>& src, int nbox, int np, in
     }
 }
 
+void check_finite(const float* a, int64_t n, const char* what) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) throw Error(ST_INVALID_ARG, std::string(what) + " holds a non-finite value");
+}
+
 }  // namespace
 
 extern "C" {
@@ -433,6 +449,8 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         P->pin.reset(new Pinned());
         P->opt = o;
         P->p = o.order > 0 ? o.order : order_for_tolerance(o.tolerance);
+        if (o.order_policy != SFMM_ORDER_FIXED)
+            P->p = std::min(kMaxOrder, ((P->p + kOrderStep - 1) / kOrderStep) * kOrderStep);
         P->N = N;
         P->M = M;
         Profiler prof(s);
@@ -452,6 +470,16 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
             StageScope st(prof, S_TGT);
             build_targets(*P, tgt, s);
         }
+        if (o.order_policy != SFMM_ORDER_FIXED && P->n_m2l > 0) {
+            P->m2l_ent.resize(P->n_m2l);
+            entry_box(P->m2l_off.data(), P->nbox, P->n_m2l, P->m2l_ent.data(), s);
+        }
+        if (o.order_policy == SFMM_ORDER_LEARNED) {
+            P->mlp_w.resize(kMlpWeights);
+            SFMM_HIP(hipMemcpyAsync(P->mlp_w.data(), o.mlp_weights, sizeof(float) * kMlpWeights,
+                                    hipMemcpyHostToDevice, s));
+        }
+        P->opt.mlp_weights = nullptr;  // not kept: the caller owns it
         prof.flush();
         const size_t ne = (size_t)P->nbox * (2 * P->p + 2);
         P->mult.resize(ne);
@@ -499,11 +527,38 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         // FMM acts: Lemma 3
         {
             StageScope st(prof, S_M2L);
-            fmm_m2l(c, P.m2l_order.data(), P.n_m2l_fp64, P.m2l_off.data(), P.m2l_src.data(), s);
-            if (P.n_m2l_fp64 < P.nbox) {
+            const bool tier = P.n_m2l_fp64 < P.nbox;
+            if (tier) {
                 P.multf.resize((size_t)P.nbox * 2 * P.p);
-                fmm_m2l_f32(c, P.multf.data(), P.nbox, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
-                            P.m2l_off.data(), P.m2l_src.data(), s);
+                mult_to_f32(c, P.nbox, P.multf.data(), s);
+            }
+            // one pass per order: (order, CSR offsets, sources); the first pass
+            // writes the local records, later ones add to them
+            auto m2l_pass = [&](int p, bool acc, const int* off, const int* src) {
+                fmm_m2l(c, p, acc, P.m2l_order.data(), P.n_m2l_fp64, off, src, s);
+                if (tier)
+                    fmm_m2l_f32(c, p, acc, P.multf.data(), P.m2l_order.data() + P.n_m2l_fp64,
+                                P.nbox - P.n_m2l_fp64, off, src, s);
+            };
+            if (P.opt.order_policy == SFMM_ORDER_FIXED || P.n_m2l == 0) {
+                m2l_pass(P.p, false, P.m2l_off.data(), P.m2l_src.data());
+                P.m2l_order_sq = (long long)P.n_m2l * P.p * P.p;
+            } else {
+                const double kt = SFMM_ORDER_KAPPA * P.opt.tolerance;
+                P.m2l_ord.resize(P.n_m2l);
+                if (P.opt.order_policy == SFMM_ORDER_BOUND) {
+                    order_bound(c, P.m2l_ent.data(), P.m2l_src.data(), P.n_m2l, kt, P.m2l_ord.data(), s);
+                } else {
+                    P.decay.resize(P.nbox);
+                    order_box_decay(c, P.nbox, P.decay.data(), s);
+                    order_mlp(c, P.m2l_ent.data(), P.m2l_src.data(), P.decay.data(), kt, nullptr, P.n_m2l,
+                              P.mlp_w.data(), P.p, kOrderMargin, P.m2l_ord.data(), nullptr, s);
+                }
+                P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
+                                             P.p, P.ord_off, P.ord_src, s);
+                for (int q = 0; q < P.p / kOrderStep; ++q)
+                    m2l_pass((q + 1) * kOrderStep, q > 0, P.ord_off.data() + (size_t)q * P.nbox, P.ord_src.data());
+                m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
             }
         }
         // down-pass: Lemma 4 from level 1 down
@@ -571,6 +626,7 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         }
         out->n_p2p_pairs = P.n_p2p_pairs < 0 ? 0 : P.n_p2p_pairs;
         out->n_m2p_evals = P.n_m2p_evals < 0 ? 0 : P.n_m2p_evals;
+        out->m2l_order_sq = P.executed ? P.m2l_order_sq : 0;
         out->order = P.p;
         out->leaf_size = P.opt.leaf_size;
         out->q_total = P.q_total;
@@ -678,6 +734,202 @@ sfmm_status sfmm_export_expansions(sfmm_plan_t plan, double* multipole, double* 
         };
         unscale(P.mult, multipole, false);
         unscale(P.local, local, true);
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+sfmm_status sfmm_order_samples(sfmm_plan_t plan, int64_t n, uint64_t seed, float* features, float* labels,
+                               int64_t* pairs) {
+    try {
+        if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
+        if (n < 0 || n > 0x7fffffff) throw Error(ST_INVALID_ARG, "n must be in [0, 2^31 - 1]");
+        if (n > 0 && (!features || !labels)) throw Error(ST_INVALID_ARG, "features or labels is NULL");
+        sfmm_plan_impl& P = *plan;
+        if (!P.executed) throw Error(ST_INVALID_ARG, "plan has not been executed");
+        if (n == 0) return SFMM_OK;
+        if (P.n_m2l == 0) throw Error(ST_INVALID_ARG, "plan has no FMM acts");
+        hipStream_t s = nullptr;
+        if (P.m2l_ent.n < (size_t)P.n_m2l) {
+            P.m2l_ent.resize(P.n_m2l);
+            entry_box(P.m2l_off.data(), P.nbox, P.n_m2l, P.m2l_ent.data(), s);
+        }
+        // pairs drawn with a counter-based generator (splitmix64)
+        std::vector<int> idx(n);
+        for (int64_t i = 0; i < n; ++i) {
+            uint64_t z = seed + 0x9e3779b97f4a7c15ULL * (uint64_t)(i + 1);
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+            z ^= z >> 31;
+            idx[i] = (int)(z % (uint64_t)P.n_m2l);
+        }
+        DVec<int> didx;
+        DVec<float> feat, lab;
+        didx.resize(n);
+        feat.resize((size_t)n * kMlpIn);
+        lab.resize(n);
+        SFMM_HIP(hipMemcpy(didx.data(), idx.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+        const FmmCtx c = P.ctx();
+        const double kt = SFMM_ORDER_KAPPA * P.opt.tolerance;
+        P.decay.resize(P.nbox);
+        order_box_decay(c, P.nbox, P.decay.data(), s);
+        order_features(c, P.m2l_ent.data(), P.m2l_src.data(), didx.data(), n, P.decay.data(), kt, feat.data(), s);
+        order_labels(c, P.m2l_ent.data(), P.m2l_src.data(), didx.data(), (int)n, kt, lab.data(), s);
+        SFMM_HIP(hipMemcpy(features, feat.data(), sizeof(float) * n * kMlpIn, hipMemcpyDeviceToHost));
+        SFMM_HIP(hipMemcpy(labels, lab.data(), sizeof(float) * n, hipMemcpyDeviceToHost));
+        if (pairs) {
+            std::vector<int> ent(P.n_m2l), src(P.n_m2l);
+            SFMM_HIP(hipMemcpy(ent.data(), P.m2l_ent.data(), sizeof(int) * P.n_m2l, hipMemcpyDeviceToHost));
+            SFMM_HIP(hipMemcpy(src.data(), P.m2l_src.data(), sizeof(int) * P.n_m2l, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) {
+                pairs[2 * i] = ent[idx[i]];
+                pairs[2 * i + 1] = src[idx[i]];
+            }
+        }
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+void sfmm_mlp_init(uint64_t seed, float* weights) {
+    if (!weights) return;
+    // He-normal weights (Box-Muller on splitmix64), zero biases
+    uint64_t st = seed;
+    auto next = [&]() {
+        uint64_t z = (st += 0x9e3779b97f4a7c15ULL);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    auto gauss = [&]() { return std::sqrt(-2.0 * std::log(next())) * std::cos(6.283185307179586 * next()); };
+    float* w = weights;
+    const int H = kMlpHidden, I = kMlpIn;
+    for (int k = 0; k < H * I; ++k) *w++ = (float)(gauss() * std::sqrt(2.0 / I));
+    for (int k = 0; k < H; ++k) *w++ = 0.0f;
+    for (int k = 0; k < H * H; ++k) *w++ = (float)(gauss() * std::sqrt(2.0 / H));
+    for (int k = 0; k < H; ++k) *w++ = 0.0f;
+    for (int k = 0; k < H; ++k) *w++ = (float)(gauss() * std::sqrt(1.0 / H));
+    *w++ = 0.0f;
+}
+
+sfmm_status sfmm_mlp_grad(const float* weights, const float* features, const float* labels, int64_t n,
+                          float* grad, float* loss) {
+    try {
+        if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
+        if (!weights || !grad || (n > 0 && (!features || !labels)))
+            throw Error(ST_INVALID_ARG, "NULL buffer");
+        check_finite(weights, kMlpWeights, "weights");
+        check_finite(features, n * kMlpIn, "features");
+        check_finite(labels, n, "labels");
+        DVec<float> w, f, l, rec, g;
+        w.resize(kMlpWeights);
+        g.resize(kMlpWeights + 1);
+        f.resize(std::max<int64_t>(n, 1) * kMlpIn);
+        l.resize(std::max<int64_t>(n, 1));
+        rec.resize(std::max<int64_t>(n, 1) * mlp_record_floats());
+        SFMM_HIP(hipMemcpy(w.data(), weights, sizeof(float) * kMlpWeights, hipMemcpyHostToDevice));
+        fill_f32(g.data(), kMlpWeights + 1, 0.0f, nullptr);
+        if (n > 0) {
+            SFMM_HIP(hipMemcpy(f.data(), features, sizeof(float) * n * kMlpIn, hipMemcpyHostToDevice));
+            SFMM_HIP(hipMemcpy(l.data(), labels, sizeof(float) * n, hipMemcpyHostToDevice));
+            mlp_grad(w.data(), f.data(), l.data(), (int)n, rec.data(), g.data(), nullptr);
+        }
+        std::vector<float> h(kMlpWeights + 1);
+        SFMM_HIP(hipMemcpy(h.data(), g.data(), sizeof(float) * (kMlpWeights + 1), hipMemcpyDeviceToHost));
+        std::memcpy(grad, h.data(), sizeof(float) * kMlpWeights);
+        if (loss) *loss = h[kMlpWeights];
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+sfmm_status sfmm_mlp_train(const float* features, const float* labels, int64_t n, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float* weights, float* epoch_loss) {
+    try {
+        if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
+        if (batch < 1 || epochs < 0 || !(lr > 0.0f)) throw Error(ST_INVALID_ARG, "batch, epochs or lr out of range");
+        if (!weights || (n > 0 && (!features || !labels))) throw Error(ST_INVALID_ARG, "NULL buffer");
+        check_finite(weights, kMlpWeights, "weights");
+        check_finite(features, n * kMlpIn, "features");
+        check_finite(labels, n, "labels");
+        if (n == 0 || epochs == 0) return SFMM_OK;
+        const int B = (int)std::min<int64_t>(batch, n);
+        DVec<float> w, m, v, g, f, l, rec;
+        w.resize(kMlpWeights);
+        m.resize(kMlpWeights);
+        v.resize(kMlpWeights);
+        g.resize(kMlpWeights + 1);
+        f.resize((size_t)n * kMlpIn);
+        l.resize(n);
+        rec.resize((size_t)B * mlp_record_floats());
+        SFMM_HIP(hipMemcpy(w.data(), weights, sizeof(float) * kMlpWeights, hipMemcpyHostToDevice));
+        fill_f32(m.data(), kMlpWeights, 0.0f, nullptr);
+        fill_f32(v.data(), kMlpWeights, 0.0f, nullptr);
+        // shuffled copies per epoch (Fisher-Yates on splitmix64)
+        std::vector<int64_t> perm(n);
+        std::vector<float> fs((size_t)n * kMlpIn), ls(n);
+        uint64_t st = seed ^ 0x5bd1e995ULL;
+        auto next = [&]() {
+            uint64_t z = (st += 0x9e3779b97f4a7c15ULL);
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+            return z ^ (z >> 31);
+        };
+        int step = 0;
+        std::vector<float> hl(kMlpWeights + 1);
+        for (int ep = 0; ep < epochs; ++ep) {
+            for (int64_t i = 0; i < n; ++i) perm[i] = i;
+            for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+            for (int64_t i = 0; i < n; ++i) {
+                std::memcpy(&fs[i * kMlpIn], &features[perm[i] * kMlpIn], sizeof(float) * kMlpIn);
+                ls[i] = labels[perm[i]];
+            }
+            SFMM_HIP(hipMemcpy(f.data(), fs.data(), sizeof(float) * n * kMlpIn, hipMemcpyHostToDevice));
+            SFMM_HIP(hipMemcpy(l.data(), ls.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+            double ep_loss = 0.0;
+            int nb = 0;
+            for (int64_t b0 = 0; b0 + B <= n; b0 += B) {
+                mlp_grad(w.data(), f.data() + b0 * kMlpIn, l.data() + b0, B, rec.data(), g.data(), nullptr);
+                mlp_adam(w.data(), m.data(), v.data(), g.data(), lr, ++step, nullptr);
+                if (epoch_loss) {
+                    float lv;
+                    SFMM_HIP(hipMemcpy(&lv, g.data() + kMlpWeights, sizeof(float), hipMemcpyDeviceToHost));
+                    ep_loss += lv;
+                    ++nb;
+                }
+            }
+            if (epoch_loss) epoch_loss[ep] = nb ? (float)(ep_loss / nb) : 0.0f;
+        }
+        SFMM_HIP(hipMemcpy(weights, w.data(), sizeof(float) * kMlpWeights, hipMemcpyDeviceToHost));
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+sfmm_status sfmm_mlp_forward(const float* weights, const float* features, int64_t n, int32_t bf16, float* y) {
+    try {
+        if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
+        if (!weights || (n > 0 && (!features || !y))) throw Error(ST_INVALID_ARG, "NULL buffer");
+        if (n == 0) return SFMM_OK;
+        DVec<float> w, f, out;
+        w.resize(kMlpWeights);
+        f.resize((size_t)n * kMlpIn);
+        out.resize(n);
+        SFMM_HIP(hipMemcpy(w.data(), weights, sizeof(float) * kMlpWeights, hipMemcpyHostToDevice));
+        SFMM_HIP(hipMemcpy(f.data(), features, sizeof(float) * n * kMlpIn, hipMemcpyHostToDevice));
+        if (bf16) {
+            FmmCtx c{};
+            order_mlp(c, nullptr, nullptr, nullptr, 1.0, f.data(), n, w.data(), kMaxOrder, 0.0f, nullptr, out.data(),
+                      nullptr);
+        } else {
+            mlp_forward_f32(w.data(), f.data(), (int)n, out.data(), nullptr);
+        }
+        SFMM_HIP(hipMemcpy(y, out.data(), sizeof(float) * n, hipMemcpyDeviceToHost));
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);

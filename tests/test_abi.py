@@ -90,3 +90,24 @@ def test_invalid_arguments_rejected_before_any_device_work(lib):
     rc = lib.sfmm_plan(None, None, 10, None, 0, ctypes.byref(sf.default_options()), None, ctypes.byref(h))
     assert rc == 1 and b"NULL" in lib.sfmm_last_error()
     assert h.value is None
+
+
+def test_mlp_init_is_deterministic_he_normal(lib):
+    import numpy as np
+    import paper_2210_07021_amd as sf
+    a, b, c = sf.mlp_init(7), sf.mlp_init(7), sf.mlp_init(8)
+    assert a.shape == (sf.MLP_WEIGHTS,) and np.array_equal(a, b) and not np.array_equal(a, c)
+    W1 = a[:64 * 8]
+    W2 = a[64 * 8 + 64:64 * 8 + 64 + 64 * 64]
+    assert abs(W1.std() - np.sqrt(2 / 8)) < 0.06 and abs(W2.std() - np.sqrt(2 / 64)) < 0.01
+    assert not a[64 * 8:64 * 8 + 64].any()  # biases zero
+
+
+def test_order_policy_options_rejected_without_weights(lib):
+    import numpy as np
+    import paper_2210_07021_amd as sf
+    opt = sf.default_options(order_policy=sf.SFMM_ORDER_LEARNED)
+    st = lib.sfmm_plan(None, None, 0, None, 0, ctypes.byref(opt), None, ctypes.byref(ctypes.c_void_p()))
+    assert st == 1 and b"mlp_weights" in lib.sfmm_last_error()
+    opt = sf.default_options(order_policy=7)
+    assert lib.sfmm_plan(None, None, 0, None, 0, ctypes.byref(opt), None, ctypes.byref(ctypes.c_void_p())) == 1

@@ -1,0 +1,196 @@
+"""GPU tests of the per-interaction order policies and of the order network.
+
+* the network's FP32 gradient and forward pass (sfmm_mlp_grad,
+  sfmm_mlp_forward) against the FP64 oracle (oracle/mlp.py), and its
+  bfloat16 inference against the oracle's bfloat16 emulation;
+* training on the GPU lowers the loss;
+* the order labels the FP64 translation produces (sfmm_order_samples) against
+  labels computed from the oracle's own multipoles with the printed Lemma 3;
+* the bound and learned policies hold the tolerance against the direct sum
+  and do less M2L work than the fixed order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2210_07021_amd import skies
+
+pytestmark = pytest.mark.gpu
+
+
+def _sf():
+    import paper_2210_07021_amd as sf
+    sf.load_library()
+    return sf
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _batch(seed, n):
+    rng = np.random.default_rng(seed)
+    f = rng.normal(0, 1, (n, omlp.IN)).astype(np.float32)
+    lab = rng.uniform(-1.5, 1.0, n).astype(np.float32)
+    return f, lab
+
+
+def test_mlp_gradient_and_forward_match_oracle():
+    sf = _sf()
+    w = sf.mlp_init(11) + np.random.default_rng(1).normal(0, 0.05, sf.MLP_WEIGHTS).astype(np.float32)
+    f, lab = _batch(2, 777)
+    g, loss = sf.mlp_grad(w, f, lab)
+    g_ref = omlp.grad(w.astype(np.float64), f, lab)
+    l_ref = omlp.loss(w.astype(np.float64), f, lab)
+    print(f"[mlp] loss {loss:.6e} oracle {l_ref:.6e}; grad rel err {_rel(g, g_ref):.2e}", flush=True)
+    assert abs(loss - l_ref) <= 1e-5 * l_ref
+    assert _rel(g, g_ref) <= 1e-5
+    assert np.abs(g - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+    y = sf.mlp_forward(w, f)
+    y_ref, _ = omlp.forward(w.astype(np.float64), f)
+    assert np.abs(y - y_ref).max() <= 1e-5 * max(1.0, np.abs(y_ref).max())
+    yb = sf.mlp_forward(w, f, bf16=True)
+    yb_ref = omlp.forward_bf16(w, f)
+    assert np.abs(yb - yb_ref).max() <= 1e-4 * max(1.0, np.abs(yb_ref).max())
+    # bfloat16 rounding matters: the bf16 output differs from the FP32 one
+    assert np.abs(yb - y).max() > 1e-6
+
+
+def test_mlp_training_lowers_the_loss():
+    sf = _sf()
+    rng = np.random.default_rng(5)
+    f = rng.normal(0, 1, (8192, omlp.IN)).astype(np.float32)
+    lab = (np.tanh(f[:, 0] - 0.5 * f[:, 3]) + 0.3 * f[:, 1] * f[:, 2]).astype(np.float32)
+    w0 = sf.mlp_init(3)
+    _, l0 = sf.mlp_grad(w0, f, lab)
+    w, hist = sf.mlp_train(f, lab, w0, epochs=40, batch=256, lr=1e-3, seed=4)
+    _, l1 = sf.mlp_grad(w, f, lab)
+    print(f"[mlp] loss {l0:.4f} -> {l1:.4f}; per epoch {hist[[0, 9, 19, 39]]}", flush=True)
+    assert l1 < 0.1 * l0
+    assert hist[-1] < hist[0]
+
+
+def test_order_labels_match_printed_lemma3(oracle_lib):
+    """Labels from the FP64 GPU translation equal labels computed from the
+    oracle's own multipoles with the printed Lemma 3 (T_ll' triple sum)."""
+    from oracle import lemmas as L
+    sf = _sf()
+    import torch
+    rng = skies.rng_for(110)
+    src = skies.uniform(3000, rng)
+    q = skies.masses_lognormal(3000, rng)
+    tgt = skies.uniform(200, rng)
+    tol, m = 1e-6, 16
+    plan = sf.Plan(src, q, tgt, tolerance=tol, leaf_size=m)
+    plan.execute()
+    torch.cuda.synchronize()
+    p = plan.stats()["order"]
+    f, lab, pairs = plan.order_samples(300, seed=9, with_pairs=True)
+    plan.close()
+    ref = L.sfmm(src, q, tgt, p=p, m=m)
+    t = ref["tree"]
+    kt = 0.1 * tol
+    agree = borderline = 0
+    for (tb, sb), lg in zip(pairs, lab):
+        C, Q, A = ref["multipole"][sb]
+        rho_t = np.tan(t.radius[tb] / 2.0)
+        rho_s = np.tan(t.radius[sb] / 2.0)
+        ws = np.sum(np.abs(A) / rho_s ** np.arange(1, p + 1))
+        full = L.m2l((C, Q, A), t.centre[:, sb], t.centre[:, tb])[2]
+        ls = np.arange(1, p + 1)
+        best, ratio = p, None
+        for pc in range(4, p, 4):
+            part = L.m2l((C, Q, A[:pc]), t.centre[:, sb], t.centre[:, tb])[2]
+            tr = np.zeros(p, complex)
+            tr[:pc] = part
+            # the monopole part of the coefficients above pc stays exact
+            cq = 1.0 / np.tan(_theta(t.centre[:, sb], t.centre[:, tb]) / 2.0)
+            tr[pc:] = full_monopole(Q, cq, rho_t, t.centre[:, sb], t.centre[:, tb], p)[pc:]
+            e = np.sum(ls * np.abs(full - tr) * rho_t ** ls)
+            if e <= kt * ws:
+                best, ratio = pc, e / (kt * ws)
+                break
+        if best == int(lg):
+            agree += 1
+        elif ratio is not None and ratio > 0.98:
+            borderline += 1
+    print(f"[labels] {agree} of {len(lab)} agree, {borderline} borderline", flush=True)
+    assert agree + borderline == len(lab) and agree >= 0.97 * len(lab)
+
+
+def _theta(a, b):
+    return np.arctan2(np.linalg.norm(np.cross(a, b)), np.dot(a, b))
+
+
+def full_monopole(Q, c, rho_t, cS, cT, p):
+    """Monopole part of Lemma 3's local coefficients: -(Q/l) c^l e^(-i l phi_S^(T))."""
+    from oracle import lemmas as L
+    _, _, ph_ST = L._pair_geometry(cS, cT)
+    ls = np.arange(1, p + 1)
+    return -(Q / ls) * c ** ls * np.exp(-1j * ls * ph_ST)
+
+
+def _policy_case(name):
+    if name == "uniform-1e4":
+        return skies.workload("uniform-1e4")
+    rng = skies.rng_for(102)
+    s2 = skies.clustered(50000, rng, n_clumps=100)
+    q2 = skies.masses_lognormal(50000, rng)
+    t2 = np.concatenate([skies.grid(32), s2[:, :2000]], axis=1)
+    return s2, q2, t2
+
+
+def _run(src, q, tgt, **opt):
+    import torch
+    sf = _sf()
+    plan = sf.Plan(src, q, tgt, **opt)
+    psi, defl = plan.execute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    return st, psi.cpu().numpy(), defl.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["uniform-1e4", "clustered-5e4"])
+def test_bound_policy_holds_tolerance(name, oracle_lib):
+    sf = _sf()
+    src, q, tgt = _policy_case(name)
+    ref_p, ref_a = oracle.direct(src, q, tgt)
+    for tol in (1e-6, 1e-9):
+        st, psi, defl = _run(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_BOUND)
+        fx, _, _ = _run(src, q, tgt, tolerance=tol, leaf_size=32)
+        ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
+        print(f"[bound] {name} tol {tol}: psi {ep:.2e} alpha {ea:.2e} work {st['m2l_order_sq'] / fx['m2l_order_sq']:.3f} "
+              f"of fixed", flush=True)
+        assert ep <= tol and ea <= tol
+        assert st["m2l_order_sq"] <= fx["m2l_order_sq"]
+
+
+def test_learned_policy_gain(oracle_lib):
+    """Trained on labels from one clustered sky, the learned policy holds the
+    tolerance on other skies and does less M2L work than both the fixed
+    order and the bound policy (the gain of the network)."""
+    sf = _sf()
+    from paper_2210_07021_amd import learn
+    rng = skies.rng_for(300)
+    train_sky = (skies.clustered(200000, rng, n_clumps=300), skies.masses_lognormal(200000, rng), skies.grid(64))
+    tol = 1e-6
+    f, lab = learn.order_training_data([train_sky], tol, samples_per_sky=60000, seed=1)
+    w, hist = learn.train_order_network(f, lab, epochs=30)
+    print(f"[learned] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, mean label {lab.mean():.2f}", flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+    for name in ("uniform-1e4", "clustered-5e4"):
+        src, q, tgt = _policy_case(name)
+        ref_p, ref_a = oracle.direct(src, q, tgt)
+        fx, _, _ = _run(src, q, tgt, tolerance=tol, leaf_size=32)
+        bd, _, _ = _run(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_BOUND)
+        st, psi, defl = _run(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_LEARNED,
+                             mlp_weights=w)
+        ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
+        gain = st["m2l_order_sq"] / fx["m2l_order_sq"]
+        print(f"[learned] {name}: psi {ep:.2e} alpha {ea:.2e}; M2L work {gain:.3f} of fixed, "
+              f"bound {bd['m2l_order_sq'] / fx['m2l_order_sq']:.3f}", flush=True)
+        assert ep <= tol and ea <= tol
+        assert st["m2l_order_sq"] <= 0.95 * fx["m2l_order_sq"]
+        assert st["m2l_order_sq"] < bd["m2l_order_sq"]

@@ -175,16 +175,30 @@ def main():
         return t1 - t0, {k: v[0] / args.steps for k, v in prof.items()}, stats
 
     elapsed, stages_ms, stats = run(opts, psi, defl, "fp64")
-    fp32 = None
+    legs = {}
     if not args.no_fp32:
-        # the precision tier at its own tolerance, same workload
-        psi32 = torch.empty_like(psi)
-        defl32 = torch.empty_like(defl)
-        e32, st32, s32 = run(dict(leaf_size=args.leaf_size, tolerance=args.fp32_tolerance,
-                                  precision=sf.SFMM_FP32_MIXED), psi32, defl32, "fp32-mixed")
-        fp32 = {"value": M * args.steps / e32, "unit": "targets/s", "ms_per_step": 1e3 * e32 / args.steps,
-                "tolerance": args.fp32_tolerance, "order": s32["order"], "dtype": "f32+f64",
-                "stages_ms": {k: round(v, 4) for k, v in st32.items()}}
+        # the precision tier at its own tolerance, same workload; then the same
+        # with the learned per-interaction order (network trained untimed on
+        # labels of the clustered 1e6 sky, a different sky and seed)
+        outs = {}
+        for leg, extra in (("fp32_mixed", {}), ("fp32_learned", "learned")):
+            opts32 = dict(leaf_size=args.leaf_size, tolerance=args.fp32_tolerance, precision=sf.SFMM_FP32_MIXED)
+            if extra == "learned":
+                from paper_2210_07021_amd import learn
+                t = time.time()
+                f_tr, l_tr = learn.order_training_data([skies.workload("clustered-1e6")], args.fp32_tolerance,
+                                                       leaf_size=args.leaf_size, samples_per_sky=60000, seed=1)
+                w_net, _ = learn.train_order_network(f_tr, l_tr, epochs=30)
+                log(f"[bench] order network trained in {time.time() - t:.1f}s (untimed)")
+                opts32.update(order_policy=sf.SFMM_ORDER_LEARNED, mlp_weights=w_net)
+            p32 = torch.empty_like(psi)
+            d32 = torch.empty_like(defl)
+            e32, st32, s32 = run(opts32, p32, d32, leg)
+            outs[leg] = (p32, d32)
+            legs[leg] = {"value": M * args.steps / e32, "unit": "targets/s", "ms_per_step": 1e3 * e32 / args.steps,
+                         "tolerance": args.fp32_tolerance, "order": s32["order"], "dtype": "f32+f64",
+                         "m2l_work_vs_fixed": s32["m2l_order_sq"] / max(1, s32["n_m2l"] * s32["order"] ** 2),
+                         "stages_ms": {k: round(v, 4) for k, v in st32.items()}}
 
     p = stats["order"]
     work = {
@@ -220,8 +234,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
         "roofline": roofline,
     }
-    if fp32 is not None:
-        result["fp32_mixed"] = fp32
+    result.update(legs)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -250,10 +263,10 @@ def main():
             "psi_rel_l2": float(np.linalg.norm(psi_h[idx] - ref_p) / np.linalg.norm(ref_p)),
             "alpha_rel_l2": float(np.linalg.norm(defl_h[:, idx] - ref_a) / np.linalg.norm(ref_a)),
             "targets": k}
-        if fp32 is not None:
-            p32 = psi32.cpu().numpy()
-            d32 = defl32.cpu().numpy()
-            fp32["accuracy"] = {
+        for leg, (p32, d32) in (outs.items() if legs else []):
+            p32 = p32.cpu().numpy()
+            d32 = d32.cpu().numpy()
+            legs[leg]["accuracy"] = {
                 "psi_rel_l2": float(np.linalg.norm(p32[idx] - ref_p) / np.linalg.norm(ref_p)),
                 "alpha_rel_l2": float(np.linalg.norm(d32[:, idx] - ref_a) / np.linalg.norm(ref_a)),
                 "targets": k}

@@ -55,16 +55,19 @@ __global__ void k_box_decay(const double* __restrict__ mult, int p, int nb, floa
 // ratio x = max(a + b, sqrt(g)): the terms of the translated coefficients
 // fall like (a + b)^n, and like g^n through the diagonal, which alone is
 // left for exactly antipodal centres (a = b = 0, g = rho_T rho_S); for any
-// other pair sqrt(g) <= (a + b) / 2.
+// other pair sqrt(g) <= (a + b) / 2.  Same formulas as trans_geom<kM2L>,
+// without the phases and the log.
 __device__ __forceinline__ double pair_ratio(const FmmCtx& c, int t, int s, double* a, double* b) {
     const double* ct = c.cen + 4 * (size_t)t;
     const double* cs = c.cen + 4 * (size_t)s;
-    const Frame ft = make_frame(ct[0], ct[1], ct[2]);
-    const Frame fs = make_frame(cs[0], cs[1], cs[2]);
-    const TransGeom G = trans_geom<kM2L>(fs, cs[3], ft, ct[3]);
-    *a = G.a;
-    *b = G.b;
-    return fmax(G.a + G.b, sqrt(G.g));
+    const double dx = ct[0] - cs[0], dy = ct[1] - cs[1], dz = ct[2] - cs[2];
+    const double sx = ct[0] + cs[0], sy = ct[1] + cs[1], sz = ct[2] + cs[2];
+    const double dif2 = dx * dx + dy * dy + dz * dz, sum2 = sx * sx + sy * sy + sz * sz;
+    const double cc = sum2 < 1e-24 ? 0.0 : sqrt(sum2 / dif2);  // cot(T/2); 0 for antipodes
+    *a = cc * ct[3];
+    *b = cc * cs[3];
+    const double g = ct[3] * cs[3] * (1.0 + cc * cc);
+    return fmax(*a + *b, sqrt(g));
 }
 
 // Features of pair k (target ent_t[k], source src[k]), kMlpIn floats:
@@ -354,11 +357,25 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
         if (lo >= P) continue;
         const int s = src[k];
         const double* cs = c.cen + 4 * (size_t)s;
-        const Frame fs = make_frame(cs[0], cs[1], cs[2]);
-        const TransGeom G = trans_geom<kM2L>(fs, cs[3], ft, ct[3]);
+        // a = rho_T cot(T/2) and the output phase conj(e2) of trans_geom<kM2L>
+        const double dx = ft.c[0] - cs[0], dy = ft.c[1] - cs[1], dz = ft.c[2] - cs[2];
+        const double sx = ft.c[0] + cs[0], sy = ft.c[1] + cs[1], sz = ft.c[2] + cs[2];
+        const double dif2 = dx * dx + dy * dy + dz * dz, sum2 = sx * sx + sy * sy + sz * sz;
+        double u2, v2;
+        if (sum2 < 1e-24) {
+            const Frame fs = make_frame(cs[0], cs[1], cs[2]);
+            u2 = fs.et[0] * ft.et[0] + fs.et[1] * ft.et[1] + fs.et[2] * ft.et[2];
+            v2 = fs.et[0] * ft.ep[0] + fs.et[1] * ft.ep[1] + fs.et[2] * ft.ep[2];
+        } else {
+            u2 = -(dx * ft.et[0] + dy * ft.et[1] + dz * ft.et[2]);
+            v2 = -(dx * ft.ep[0] + dy * ft.ep[1] + dz * ft.ep[2]);
+        }
+        const double r2 = 1.0 / sqrt(u2 * u2 + v2 * v2);
+        const cplx ph2 = {u2 * r2, -v2 * r2};
+        const double a = (sum2 < 1e-24 ? 0.0 : sqrt(sum2 / dif2)) * ct[3];
         const double Q = c.mult[(size_t)s * (2 * P + 2) + 1];
-        cplx pw2 = G.ph2;
-        double an = G.a;
+        cplx pw2 = ph2;
+        double an = a;
 #pragma unroll
         for (int l = 1; l <= P; ++l) {
             if (l > lo) {
@@ -366,8 +383,8 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
                 acc[2 * l - 2] = fma(pw2.re, v, acc[2 * l - 2]);
                 acc[2 * l - 1] = fma(pw2.im, v, acc[2 * l - 1]);
             }
-            pw2 = cmul(pw2, G.ph2);
-            an *= G.a;
+            pw2 = cmul(pw2, ph2);
+            an *= a;
         }
     }
     double* out = c.local + (size_t)t * (2 * P + 2);
@@ -376,30 +393,32 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
 }
 
 // ------------------------------------------------------------ split by order
-// cnt[q * nbox + T] = pairs of T with order (q + 1) kOrderStep
-__global__ void k_order_count(const int* __restrict__ off, const uint8_t* __restrict__ ord, int nbox, int nq,
-                              int* __restrict__ cnt) {
+// cnt[q * nbox + T] = pairs of T with order (q + 1) kOrderStep; the
+// per-order counters of each lane live in LDS ([q][lane]), not in scratch
+constexpr int kMaxQ = kMaxOrder / kOrderStep;
+__global__ void __launch_bounds__(256) k_order_count(const int* __restrict__ off, const uint8_t* __restrict__ ord,
+                                                     int nbox, int nq, int* __restrict__ cnt) {
+    __shared__ int c[kMaxQ][256];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int q = 0; q < nq; ++q) c[q][threadIdx.x] = 0;
     if (t >= nbox) return;
-    int c[kMaxOrder / kOrderStep];
-    for (int q = 0; q < nq; ++q) c[q] = 0;
-    for (int k = off[t]; k < off[t + 1]; ++k) ++c[ord[k] / kOrderStep - 1];
-    for (int q = 0; q < nq; ++q) cnt[(size_t)q * nbox + t] = c[q];
+    for (int k = off[t]; k < off[t + 1]; ++k) ++c[ord[k] / kOrderStep - 1][threadIdx.x];
+    for (int q = 0; q < nq; ++q) cnt[(size_t)q * nbox + t] = c[q][threadIdx.x];
 }
 
 // stable scatter of each box's entries into the list of their order; boff
 // is the exclusive scan of cnt (so the lists of order q are the CSR boff +
 // q nbox, with absolute offsets into bsrc)
-__global__ void k_order_scatter(const int* __restrict__ off, const int* __restrict__ src,
-                                const uint8_t* __restrict__ ord, int nbox, int nq, const int* __restrict__ boff,
-                                int* __restrict__ bsrc) {
+__global__ void __launch_bounds__(256) k_order_scatter(const int* __restrict__ off, const int* __restrict__ src,
+                                                       const uint8_t* __restrict__ ord, int nbox, int nq,
+                                                       const int* __restrict__ boff, int* __restrict__ bsrc) {
+    __shared__ int pos[kMaxQ][256];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nbox) return;
-    int pos[kMaxOrder / kOrderStep];
-    for (int q = 0; q < nq; ++q) pos[q] = boff[(size_t)q * nbox + t];
+    for (int q = 0; q < nq; ++q) pos[q][threadIdx.x] = boff[(size_t)q * nbox + t];
     for (int k = off[t]; k < off[t + 1]; ++k) {
         const int q = ord[k] / kOrderStep - 1;
-        bsrc[pos[q]++] = src[k];
+        bsrc[pos[q][threadIdx.x]++] = src[k];
     }
 }
 

@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct sfmm_plan_impl* sfmm_plan_t;
+typedef struct sfmm_batch_impl* sfmm_batch_t;
 
 typedef enum {
     SFMM_OK = 0,
@@ -101,7 +102,10 @@ typedef struct {
     int32_t order_policy;      /* SFMM_ORDER_FIXED (default), _BOUND, _LEARNED */
     const float* mlp_weights;  /* host, SFMM_MLP_WEIGHTS floats; read (copied)
                                   by sfmm_plan when order_policy is LEARNED  */
-    int32_t reserved[6];
+    int32_t near_segment;      /* close leaves per near-field work item: direct
+                                  sums (0 = 128); 8..4096                     */
+    int32_t far_segment;       /* the same for the multipole evaluations     */
+    int32_t reserved[4];
 } sfmm_options;
 
 typedef struct {
@@ -139,6 +143,30 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
 /* Run the five stages of Sec. 3.7 for a plan: psi [M] and defl [3][M]
  * (device, caller-owned, caller's target order) are overwritten. */
 sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stream);
+
+/* Batches: several independent spheres (lensing shells, Sec. 2.1: one
+ * Poisson problem per layer) planned together and executed as one unit.
+ * sfmm_batch_plan: sfmm_plan on each of the nshell (src[i], q[i], N[i],
+ *   tgt[i], M[i]) with the same options, in order, on `stream`; the batch owns
+ *   the plans.  With the null stream the batch creates a stream of its own
+ *   for sfmm_batch_execute.
+ * sfmm_batch_execute: psi[i] [M[i]] and defl[i] [3][M[i]] for every shell.
+ *   The first call (and any call with other output pointers or another
+ *   stream) runs every shell once directly, records the same work in a HIP
+ *   graph and launches it; later calls replay the graph: one launch for all
+ *   shells.  Batches with the bound or learned order policy are run directly
+ *   every time (their per-order split reads sizes on the host).  With the
+ *   null stream the call returns when the work is done.
+ * sfmm_batch_plan_at: the plan of shell i (owned by the batch: for stats and
+ *   exports, not to be destroyed or executed by the caller while a graph
+ *   holds it).
+ * Errors: as sfmm_plan / sfmm_execute; nshell outside [1, 4096]. */
+sfmm_status sfmm_batch_plan(int32_t nshell, const double* const* src, const double* const* q, const int64_t* N,
+                            const double* const* tgt, const int64_t* M, const sfmm_options* opt, void* stream,
+                            sfmm_batch_t* out);
+sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* const* defl, void* stream);
+sfmm_status sfmm_batch_plan_at(sfmm_batch_t batch, int32_t i, sfmm_plan_t* out);
+void sfmm_batch_destroy(sfmm_batch_t batch);
 
 /* Sizes of a plan. */
 sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out);

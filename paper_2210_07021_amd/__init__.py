@@ -49,7 +49,9 @@ class Options(ctypes.Structure):
         ("psi_gauge", ctypes.c_int32),
         ("order_policy", ctypes.c_int32),
         ("mlp_weights", ctypes.c_void_p),
-        ("reserved", ctypes.c_int32 * 6),
+        ("near_segment", ctypes.c_int32),
+        ("far_segment", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -88,6 +90,11 @@ SIGNATURES = {
     "sfmm_export_keys": (ctypes.c_int, [_P] * 6),
     "sfmm_export_work": (ctypes.c_int, [_P] * 4),
     "sfmm_export_expansions": (ctypes.c_int, [_P] * 3),
+    "sfmm_batch_plan": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(Options), _P,
+                                       ctypes.POINTER(_P)]),
+    "sfmm_batch_execute": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sfmm_batch_plan_at": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "sfmm_batch_destroy": (None, [_P]),
     "sfmm_order_samples": (ctypes.c_int, [_P, _I64, ctypes.c_uint64, _P, _P, _P]),
     "sfmm_mlp_init": (None, [ctypes.c_uint64, _P]),
     "sfmm_mlp_train": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
@@ -353,3 +360,78 @@ def sfmm(src, q, tgt, **options):
         return p.execute()
     finally:
         p.close()
+
+
+class _PlanView(Plan):
+    """A plan owned by a Batch (stats and exports only)."""
+
+    def __init__(self, batch, i):
+        self._lib = batch._lib
+        self._h = ctypes.c_void_p()
+        _check(self._lib.sfmm_batch_plan_at(batch._h, i, ctypes.byref(self._h)))
+        self.N, self.M = batch.N[i], batch.M[i]
+        self._torch = batch._torch
+
+    def close(self):
+        self._h = ctypes.c_void_p()  # the batch owns it
+
+
+class Batch:
+    """Several independent spheres (shells) planned together; execute() runs
+    all of them, replaying a recorded HIP graph after the first call
+    (sfmm_batch_plan / sfmm_batch_execute)."""
+
+    def __init__(self, srcs, qs, tgts, **options):
+        import torch
+        self._lib = load_library()
+        self._torch = torch
+        n = len(srcs)
+        if not (len(qs) == len(tgts) == n) or n == 0:
+            raise ValueError("need as many masses and target sets as source sets (>= 1)")
+        self.src = [_dev_planes(x, "src") for x in srcs]
+        self.q = [_dev_planes(x, "q") for x in qs]
+        self.tgt = [_dev_planes(x, "tgt") for x in tgts]
+        self.N = [int(x.shape[1]) for x in self.src]
+        self.M = [int(x.shape[1]) for x in self.tgt]
+        weights = options.pop("mlp_weights", None)
+        self.options = default_options(**options)
+        if weights is not None:
+            self._mlp_weights = _f32(weights, (MLP_WEIGHTS,))
+            self.options.mlp_weights = self._mlp_weights.ctypes.data
+        arr = lambda xs: (ctypes.c_void_p * n)(*[x.data_ptr() if x.numel() else 0 for x in xs])
+        self._ptrs = (arr(self.src), arr(self.q), arr(self.tgt))
+        Ns = (ctypes.c_int64 * n)(*self.N)
+        Ms = (ctypes.c_int64 * n)(*self.M)
+        self._h = ctypes.c_void_p()
+        _check(self._lib.sfmm_batch_plan(n, self._ptrs[0], self._ptrs[1], Ns, self._ptrs[2], Ms,
+                                         ctypes.byref(self.options), None, ctypes.byref(self._h)))
+        self.n = n
+
+    def execute(self, psi=None, defl=None):
+        """Returns lists of psi (M_i,) and defl (3, M_i) CUDA float64 tensors;
+        pass the same output tensors again to replay the recorded graph."""
+        t = self._torch
+        if psi is None:
+            psi = [t.empty(m, dtype=t.float64, device="cuda") for m in self.M]
+        if defl is None:
+            defl = [t.empty((3, m), dtype=t.float64, device="cuda") for m in self.M]
+        pp = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in psi])
+        dp = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in defl])
+        t.cuda.synchronize()  # inputs written by torch are visible to the batch's stream
+        _check(self._lib.sfmm_batch_execute(self._h, pp, dp, None))
+        return psi, defl
+
+    def plan(self, i: int) -> Plan:
+        return _PlanView(self, i)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.sfmm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -32,6 +32,7 @@ enum Stage {
     S_SRC = 0, S_TREE, S_GEOM, S_WALK, S_LISTS, S_TGT, S_P2M, S_M2M, S_M2L, S_L2L, S_L2P, S_P2P, S_M2P, S_COUNT
 };
 std::atomic<int> g_prof_on{0};
+thread_local bool g_capturing = false;  // no stage timing while a graph is recorded
 std::mutex g_prof_mu;
 double g_prof_ms[S_COUNT];
 long long g_prof_calls[S_COUNT];
@@ -46,7 +47,7 @@ struct Profiler {
         hipEvent_t a, b;
     };
     std::vector<Rec> recs;
-    explicit Profiler(hipStream_t st) : s(st), on(g_prof_on.load() != 0) {}
+    explicit Profiler(hipStream_t st) : s(st), on(g_prof_on.load() != 0 && !g_capturing) {}
     int begin(int stage) {
         if (!on) return -1;
         Rec r{stage, nullptr, nullptr};
@@ -179,6 +180,8 @@ void validate(const sfmm_options& o) {
         o.order_policy != SFMM_ORDER_LEARNED)
         bad("unknown order_policy");
     if (o.order_policy == SFMM_ORDER_LEARNED && !o.mlp_weights) bad("the learned order policy needs mlp_weights");
+    if (o.near_segment != 0 && (o.near_segment < 8 || o.near_segment > 4096)) bad("near_segment must be 0 or in [8, 4096]");
+    if (o.far_segment != 0 && (o.far_segment < 8 || o.far_segment > 4096)) bad("far_segment must be 0 or in [8, 4096]");
 }
 
 // Sort points by key and keep the permutation; outputs resized here.
@@ -362,9 +365,11 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     target_ranges(P.tleaf.data(), P.M, P.tfirst.data(), P.tcount.data(), s);
     near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.nbox, P.n_p2p, P.tfirst.data(), P.tcount.data(),
                P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
-    build_items(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), P.tcount.data(), P.nbox, kSegNear,
+    const int segn = P.opt.near_segment > 0 ? P.opt.near_segment : kSegNear;
+    const int segf = P.opt.far_segment > 0 ? P.opt.far_segment : kSegFar;
+    build_items(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), P.tcount.data(), P.nbox, segn,
                 P.near_items, s);
-    build_items(P.nl.far_off.data(), P.nl.far_src.data(), nullptr, P.tcount.data(), P.nbox, kSegFar, P.far_items,
+    build_items(P.nl.far_off.data(), P.nl.far_src.data(), nullptr, P.tcount.data(), P.nbox, segf, P.far_items,
                 s);
     P.ntl = count_boxes(P.near_items);
 }
@@ -413,6 +418,29 @@ void check_finite(const float* a, int64_t n, const char* what) {
 }
 
 }  // namespace
+
+// A batch of plans (shells) executed together; the work of sfmm_execute on
+// all of them is recorded once in a HIP graph and replayed as one launch.
+struct sfmm_batch_impl {
+    std::vector<sfmm_plan_impl*> plans;
+    hipStream_t own = nullptr;  // used when the caller passes the null stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double*> g_psi, g_defl;  // outputs the graph was recorded with
+    hipStream_t g_stream = nullptr;
+    bool capturable = true;
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~sfmm_batch_impl() {
+        drop_graph();
+        for (auto* p : plans) delete p;
+        if (own) hipStreamDestroy(own);
+    }
+};
 
 extern "C" {
 
@@ -935,6 +963,101 @@ sfmm_status sfmm_mlp_forward(const float* weights, const float* features, int64_
         return fail(e);
     }
 }
+
+sfmm_status sfmm_batch_plan(int32_t nshell, const double* const* src, const double* const* q, const int64_t* N,
+                            const double* const* tgt, const int64_t* M, const sfmm_options* opt, void* stream,
+                            sfmm_batch_t* out) {
+    if (out) *out = nullptr;
+    try {
+        if (!out) throw Error(ST_INVALID_ARG, "out is NULL");
+        if (nshell < 1 || nshell > 4096) throw Error(ST_INVALID_ARG, "nshell must be in [1, 4096]");
+        if (!src || !q || !N || !tgt || !M) throw Error(ST_INVALID_ARG, "NULL array");
+        std::unique_ptr<sfmm_batch_impl> B(new sfmm_batch_impl());
+        hipStream_t s = (hipStream_t)stream;
+        if (!s) SFMM_HIP(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
+        for (int i = 0; i < nshell; ++i) {
+            sfmm_plan_t p = nullptr;
+            const sfmm_status st = sfmm_plan(src[i], q[i], N[i], tgt[i], M[i], opt, stream, &p);
+            if (st != SFMM_OK) return st;
+            B->plans.push_back(p);
+        }
+        // the per-order split of the bound and learned policies reads sizes
+        // on the host between kernels: those batches run without a graph
+        B->capturable = !opt || opt->order_policy == SFMM_ORDER_FIXED;
+        *out = B.release();
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SFMM_ERR_INTERNAL;
+    }
+}
+
+sfmm_status sfmm_batch_plan_at(sfmm_batch_t batch, int32_t i, sfmm_plan_t* out) {
+    if (!batch || !out || i < 0 || i >= (int32_t)batch->plans.size()) {
+        g_last_error = "batch, out or index out of range";
+        return SFMM_ERR_INVALID_ARG;
+    }
+    *out = batch->plans[i];
+    return SFMM_OK;
+}
+
+sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* const* defl, void* stream) {
+    try {
+        if (!batch || !psi || !defl) throw Error(ST_INVALID_ARG, "batch, psi or defl is NULL");
+        sfmm_batch_impl& B = *batch;
+        const size_t n = B.plans.size();
+        hipStream_t caller = (hipStream_t)stream;
+        hipStream_t s = caller ? caller : B.own;
+        if (!s) throw Error(ST_INVALID_ARG, "the batch was planned with a stream: pass a stream");
+        auto run_all = [&]() {
+            for (size_t i = 0; i < n; ++i) {
+                const sfmm_status st = sfmm_execute(B.plans[i], psi[i], defl[i], s);
+                if (st != SFMM_OK) throw Error(st, g_last_error);
+            }
+        };
+        bool same = B.exec && B.g_stream == s;
+        for (size_t i = 0; same && i < n; ++i) same = B.g_psi[i] == psi[i] && B.g_defl[i] == defl[i];
+        if (same) {
+            SFMM_HIP(hipGraphLaunch(B.exec, s));
+        } else if (!B.capturable) {
+            run_all();
+        } else {
+            B.drop_graph();
+            // one direct pass (sizes every buffer a pass needs), then the same
+            // pass recorded in a graph, which this call also launches
+            run_all();
+            SFMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            g_capturing = true;
+            try {
+                run_all();
+            } catch (...) {
+                g_capturing = false;
+                hipGraph_t g = nullptr;
+                hipStreamEndCapture(s, &g);
+                if (g) hipGraphDestroy(g);
+                throw;
+            }
+            g_capturing = false;
+            SFMM_HIP(hipStreamEndCapture(s, &B.graph));
+            SFMM_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+            B.g_psi.assign(psi, psi + n);
+            B.g_defl.assign(defl, defl + n);
+            B.g_stream = s;
+            SFMM_HIP(hipGraphLaunch(B.exec, s));
+        }
+        if (!caller) SFMM_HIP(hipStreamSynchronize(s));
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SFMM_ERR_INTERNAL;
+    }
+}
+
+void sfmm_batch_destroy(sfmm_batch_t batch) { delete batch; }
 
 void sfmm_destroy(sfmm_plan_t plan) { delete plan; }
 

@@ -159,3 +159,21 @@ def workload(name: str, scale: float = 1.0):
         n = int(round(1e7 * scale))
         return clustered(n, rng), masses_lognormal(n, rng), grid(512)
     raise ValueError(f"unknown workload {name!r}")
+
+
+def shells(n_shell: int = 40, n_min: float = 1e5, n_max: float = 5e6, nside: int = 256, scale: float = 1.0,
+           base: int = 3):
+    """Lensing shells of one light cone: shell s has N_s = round(exp U(ln n_min,
+    ln n_max)) particles (times scale) on the clustered recipe, seeded with
+    generator base + 100 s; every shell has the same HEALPix grid of targets.
+    Returns lists (src, q, tgt) per shell."""
+    out = []
+    tgt = grid(nside)
+    for s_ in range(n_shell):
+        rng = rng_for(base + 100 * s_)
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max))) * scale))
+        src = clustered(n, rng)
+        q = masses_lognormal(n, rng)
+        out.append((src, q, tgt))
+    return out
+

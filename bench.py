@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-tier (FP32 mixed) leg")
     ap.add_argument("--fp32-tolerance", type=float, default=1e-6)
+    ap.add_argument("--shells", type=int, default=0,
+                    help="measure the batched form instead: this many lensing shells (N_s log-uniform in "
+                         "[1e5, 5e6], 786,432 grid targets each) in one recorded graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (scale for the traffic counters) and exit")
     args = ap.parse_args()
@@ -124,6 +127,8 @@ def main():
     from paper_2210_07021_amd import skies
 
     sf.load_library()
+    if args.shells > 0:
+        return bench_shells(args, sf, skies, torch)
     torch.cuda.set_device(0)
     log(f"[bench] generating {args.workload} (scale {args.scale})")
     t = time.time()
@@ -271,6 +276,56 @@ def main():
                 "alpha_rel_l2": float(np.linalg.norm(d32[:, idx] - ref_a) / np.linalg.norm(ref_a)),
                 "targets": k}
     print(json.dumps(result), flush=True)
+
+
+def bench_shells(args, sf, skies, torch):
+    """Batched shells: autotune on the median shell (untimed), plan the batch,
+    record the graph (untimed warm-up), then time K graph replays and K
+    direct per-shell executes; report both and the plan time."""
+    from paper_2210_07021_amd import tune
+    t = time.time()
+    sh = skies.shells(args.shells, scale=args.scale)
+    ntot = sum(x[0].shape[1] for x in sh)
+    mtot = sum(x[2].shape[1] for x in sh)
+    log(f"[bench] {args.shells} shells, N = {ntot}, M = {mtot}, generated in {time.time() - t:.1f}s")
+    srcs = [torch.from_numpy(x[0]).cuda() for x in sh]
+    qs = [torch.from_numpy(x[1]).cuda() for x in sh]
+    tgts = [torch.from_numpy(x[2]).cuda() for x in sh]
+    med = sorted(range(len(sh)), key=lambda i: sh[i][0].shape[1])[len(sh) // 2]
+    best, t_best, _ = tune.autotune(srcs[med], qs[med], tgts[med], tolerance=args.tolerance, repeats=1)
+    log(f"[bench] autotuned on shell {med}: {best}")
+    opts = {k: v for k, v in best.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = sf.Batch(srcs, qs, tgts, **opts)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    psi, defl = b.execute()  # direct pass + recording + first launch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.execute(psi, defl)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    plans = [b.plan(i) for i in range(len(sh))]
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for i, p in enumerate(plans):
+            p.execute(psi[i], defl[i])
+    torch.cuda.synchronize()
+    t_direct = (time.perf_counter() - t0) / args.steps
+    result = {
+        "metric": "targets/s (psi+deflection), batched lensing shells, plan + execute",
+        "value": mtot / (t_plan + t_graph), "unit": "targets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": 1e3 * (t_plan + t_graph), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"shells-{args.shells}", "N": ntot, "M": mtot, "tolerance": args.tolerance,
+                   "options": {k: v for k, v in opts.items() if k != "tolerance"}},
+        "plan_ms": 1e3 * t_plan, "execute_graph_ms": 1e3 * t_graph, "execute_direct_ms": 1e3 * t_direct,
+        "execute_targets_per_s_graph": mtot / t_graph,
+    }
+    print(json.dumps(result), flush=True)
+    b.close()
 
 
 if __name__ == "__main__":

@@ -157,9 +157,9 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
  *   shells.  Batches with the bound or learned order policy are run directly
  *   every time (their per-order split reads sizes on the host).  With the
  *   null stream the call returns when the work is done.
- * sfmm_batch_plan_at: the plan of shell i (owned by the batch: for stats and
- *   exports, not to be destroyed or executed by the caller while a graph
- *   holds it).
+ * sfmm_batch_plan_at: the plan of shell i, owned by the batch (never to be
+ *   destroyed by the caller; it may be executed directly, ordered with the
+ *   batch's own calls).
  * Errors: as sfmm_plan / sfmm_execute; nshell outside [1, 4096]. */
 sfmm_status sfmm_batch_plan(int32_t nshell, const double* const* src, const double* const* q, const int64_t* N,
                             const double* const* tgt, const int64_t* M, const sfmm_options* opt, void* stream,

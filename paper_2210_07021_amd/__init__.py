@@ -371,6 +371,7 @@ class _PlanView(Plan):
         _check(self._lib.sfmm_batch_plan_at(batch._h, i, ctypes.byref(self._h)))
         self.N, self.M = batch.N[i], batch.M[i]
         self._torch = batch._torch
+        self._stream = None
 
     def close(self):
         self._h = ctypes.c_void_p()  # the batch owns it

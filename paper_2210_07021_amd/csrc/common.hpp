@@ -142,13 +142,16 @@ struct WalkCtx {
     const double* gdd;
     double c_s, c_t;
 };
-void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* nchild, int* nm2l, int* np2p,
-                   hipStream_t s);
-void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild,
-               const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p,
-               int p2p_base, hipStream_t s);
 // M2L order: boxes of levels <= lc first, then the others; longest list
 // first within each part (16-bit keys, ties in table order)
+// one walk round in three launches: classify + per-block scans, scan of the
+// block totals (tot[3]: children pairs, M2L pairs, P2P pairs), emit
+void walk_round_sizes(int n, int* nthr_total, int* nblk);
+void walk_round_scan(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* toff, int* btot, int* boff,
+                     int* tot, hipStream_t s);
+void walk_round_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* toff,
+                     const int* boff, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
+                     hipStream_t s);
 void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
                     hipStream_t s);
 // precision tier: M2L into boxes of levels <= kFp32CoarseLevel stays FP64

@@ -235,79 +235,178 @@ __device__ bool box_far(const WalkCtx& w, int s, int t) {
     return mac_far(cs, ct, gs[6], gt[6], csd, ctd, dd{gs[6], gs[7]}, dd{gt[6], gt[7]}, w.c_s, w.c_t);
 }
 
-__global__ void k_walk_classify(const int2* F, int n, WalkCtx w, uint8_t* action, int* nchild, int* nm2l,
-                                int* np2p) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int s = F[k].x, t = F[k].y;
-    uint8_t a;
-    if (w.count[s] == 0) {
-        a = A_NONE;
-    } else if (s == t) {
-        a = (w.child0[s] < 0) ? A_P2P : A_SPLIT_SELF;
-    } else if (box_far(w, s, t)) {
-        a = A_M2L;
-    } else {
-        const bool sl = w.child0[s] < 0, tl = w.child0[t] < 0;
-        if (!sl && !tl) {
-            const double* gs = w.gdd + 8 * s;
-            const double* gt = w.gdd + 8 * t;
-            a = radius_greater(gs[6], gt[6], dd{gs[6], gs[7]}, dd{gt[6], gt[7]}) ? A_SPLIT_S : A_SPLIT_T;
-        } else if (!sl) {
-            a = A_SPLIT_S;
-        } else if (!tl) {
-            a = A_SPLIT_T;
-        } else {
-            a = A_P2P;
-        }
+// One round of the walk in three launches.  Thread g of k_walk_round_scan
+// classifies pairs 4g .. 4g+3 and the block scans the three counts of its
+// threads (children pairs, M2L pairs, P2P pairs); k_walk_block_scan scans
+// the block totals; k_walk_round_emit writes each thread's outputs from its
+// base offsets, in pair order (so the lists come out in the same order as a
+// scan over single pairs).
+constexpr int kWalkItems = 4, kWalkThreads = 256;
+
+__device__ __forceinline__ uint8_t walk_action(const WalkCtx& w, int s, int t) {
+    if (w.count[s] == 0) return A_NONE;
+    if (s == t) return (w.child0[s] < 0) ? A_P2P : A_SPLIT_SELF;
+    if (box_far(w, s, t)) return A_M2L;
+    const bool sl = w.child0[s] < 0, tl = w.child0[t] < 0;
+    if (!sl && !tl) {
+        const double* gs = w.gdd + 8 * s;
+        const double* gt = w.gdd + 8 * t;
+        return radius_greater(gs[6], gt[6], dd{gs[6], gs[7]}, dd{gt[6], gt[7]}) ? A_SPLIT_S : A_SPLIT_T;
     }
-    action[k] = a;
-    nchild[k] = (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
-    nm2l[k] = (a == A_M2L) ? 1 : 0;
-    np2p[k] = (a == A_P2P) ? 1 : 0;
+    if (!sl) return A_SPLIT_S;
+    if (!tl) return A_SPLIT_T;
+    return A_P2P;
 }
 
-void walk_classify(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* nchild, int* nm2l, int* np2p,
-                   hipStream_t s) {
-    if (n <= 0) return;
-    k_walk_classify<<<nblocks(n, 128), 128, 0, s>>>(F, n, w, action, nchild, nm2l, np2p);
-    SFMM_LAUNCH_CHECK();
+__device__ __forceinline__ int walk_nchild(uint8_t a) {
+    return (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
+}
+
+__global__ void __launch_bounds__(kWalkThreads) k_walk_round_scan(const int2* __restrict__ F, int n, WalkCtx w,
+                                                                  uint8_t* __restrict__ action,
+                                                                  int* __restrict__ toff, int nthr,
+                                                                  int* __restrict__ btot, int nblk) {
+    __shared__ int sh[3][kWalkThreads / 64];
+    const int g = blockIdx.x * kWalkThreads + threadIdx.x;
+    int c[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < kWalkItems; ++i) {
+        const int k = g * kWalkItems + i;
+        if (k < n) {
+            const uint8_t a = walk_action(w, F[k].x, F[k].y);
+            action[k] = a;
+            c[0] += walk_nchild(a);
+            c[1] += a == A_M2L;
+            c[2] += a == A_P2P;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int x = c[j];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) sh[j][wv] = x;
+        c[j] = x - c[j];  // exclusive within the wave
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int before = 0, all = 0;
+#pragma unroll
+        for (int v = 0; v < kWalkThreads / 64; ++v) {
+            before += v < wv ? sh[j][v] : 0;
+            all += sh[j][v];
+        }
+        toff[(size_t)j * nthr + g] = before + c[j];
+        if (threadIdx.x == 0) btot[(size_t)j * nblk + blockIdx.x] = all;
+    }
+}
+
+// exclusive scans of the three block-total arrays (one workgroup each, in
+// chunks with a running carry); tot[j] = the total of array j
+__global__ void __launch_bounds__(256) k_walk_block_scan(const int* __restrict__ btot, int nblk,
+                                                         int* __restrict__ boff, int* __restrict__ tot) {
+    __shared__ int sh[256 / 64];
+    const int j = blockIdx.x;
+    const int* in = btot + (size_t)j * nblk;
+    int* out = boff + (size_t)j * nblk;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < nblk; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nblk ? in[i] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) sh[wv] = x;
+        __syncthreads();
+        int before = 0, all = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            before += q < wv ? sh[q] : 0;
+            all += sh[q];
+        }
+        if (i < nblk) out[i] = carry + before + x - v;
+        carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[j] = carry;
 }
 
 __device__ uint64_t pair_key(int s, int t) { return ((uint64_t)(uint32_t)t << 32) | (uint32_t)s; }
 
-__global__ void k_walk_emit(const int2* F, int n, WalkCtx w, const uint8_t* action, const int* ochild,
-                            const int* om2l, const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base,
-                            uint64_t* p2p, int p2p_base) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int s = F[k].x, t = F[k].y;
-    const uint8_t a = action[k];
-    int2* out = Fnext + ochild[k];
-    switch (a) {
-        case A_M2L: m2l[m2l_base + om2l[k]] = pair_key(s, t); break;
-        case A_P2P: p2p[p2p_base + op2p[k]] = pair_key(s, t); break;
-        case A_SPLIT_S:
-            for (int i = 0; i < 4; ++i) out[i] = make_int2(w.child0[s] + i, t);
-            break;
-        case A_SPLIT_T:
-            for (int j = 0; j < 4; ++j) out[j] = make_int2(s, w.child0[t] + j);
-            break;
-        case A_SPLIT_SELF:
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) out[4 * i + j] = make_int2(w.child0[s] + i, w.child0[s] + j);
-            break;
-        default: break;
+__global__ void __launch_bounds__(kWalkThreads) k_walk_round_emit(const int2* __restrict__ F, int n, WalkCtx w,
+                                                                  const uint8_t* __restrict__ action,
+                                                                  const int* __restrict__ toff, int nthr,
+                                                                  const int* __restrict__ boff, int nblk,
+                                                                  int2* __restrict__ Fnext, uint64_t* __restrict__ m2l,
+                                                                  int m2l_base, uint64_t* __restrict__ p2p,
+                                                                  int p2p_base) {
+    const int g = blockIdx.x * kWalkThreads + threadIdx.x;
+    if (g * kWalkItems >= n) return;
+    int oc = boff[blockIdx.x] + toff[g];
+    int om = boff[(size_t)nblk + blockIdx.x] + toff[(size_t)nthr + g];
+    int op = boff[2 * (size_t)nblk + blockIdx.x] + toff[2 * (size_t)nthr + g];
+#pragma unroll
+    for (int i = 0; i < kWalkItems; ++i) {
+        const int k = g * kWalkItems + i;
+        if (k >= n) break;
+        const int s = F[k].x, t = F[k].y;
+        const uint8_t a = action[k];
+        int2* out = Fnext + oc;
+        switch (a) {
+            case A_M2L: m2l[m2l_base + om++] = pair_key(s, t); break;
+            case A_P2P: p2p[p2p_base + op++] = pair_key(s, t); break;
+            case A_SPLIT_S:
+                for (int q = 0; q < 4; ++q) out[q] = make_int2(w.child0[s] + q, t);
+                break;
+            case A_SPLIT_T:
+                for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.child0[t] + q);
+                break;
+            case A_SPLIT_SELF:
+                for (int q = 0; q < 4; ++q)
+                    for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.child0[s] + q, w.child0[s] + r);
+                break;
+            default: break;
+        }
+        oc += walk_nchild(a);
     }
 }
 
-void walk_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* ochild, const int* om2l,
-               const int* op2p, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
-               hipStream_t s) {
+void walk_round_scan(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* toff, int* btot, int* boff,
+                     int* tot, hipStream_t s) {
     if (n <= 0) return;
-    k_walk_emit<<<nblocks(n, 128), 128, 0, s>>>(F, n, w, action, ochild, om2l, op2p, Fnext, m2l, m2l_base, p2p,
-                                                p2p_base);
+    const int nthr = (n + kWalkItems - 1) / kWalkItems;
+    const int nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
+    k_walk_round_scan<<<nblk, kWalkThreads, 0, s>>>(F, n, w, action, toff, nblk * kWalkThreads, btot, nblk);
     SFMM_LAUNCH_CHECK();
+    k_walk_block_scan<<<3, 256, 0, s>>>(btot, nblk, boff, tot);
+    SFMM_LAUNCH_CHECK();
+}
+
+void walk_round_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* toff,
+                     const int* boff, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    const int nthr = (n + kWalkItems - 1) / kWalkItems;
+    const int nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
+    k_walk_round_emit<<<nblk, kWalkThreads, 0, s>>>(F, n, w, action, toff, nblk * kWalkThreads, boff, nblk, Fnext,
+                                                    m2l, m2l_base, p2p, p2p_base);
+    SFMM_LAUNCH_CHECK();
+}
+
+// sizes of the per-round scratch of walk_round_scan for n pairs
+void walk_round_sizes(int n, int* nthr_total, int* nblk) {
+    const int nthr = (n + kWalkItems - 1) / kWalkItems;
+    *nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
+    *nthr_total = *nblk * kWalkThreads;
 }
 
 // ------------------------------------------------------------------ lists

@@ -285,22 +285,18 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     F.resize(f0.size());
     SFMM_HIP(hipMemcpyAsync(F.data(), f0.data(), f0.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     DVec<uint8_t> action;
-    DVec<int> nchild, nm2l, np2p, ochild, om2l, op2p, tots;
+    DVec<int> toff, btot, boff, tots;
     tots.resize(3);
     DVec<uint64_t> m2l, p2p;
     int n = (int)f0.size(), n_m2l = 0, n_p2p = 0;
     while (n > 0) {
+        int nthr, nblk;
+        walk_round_sizes(n, &nthr, &nblk);
         action.resize(n);
-        nchild.resize(n);
-        nm2l.resize(n);
-        np2p.resize(n);
-        ochild.resize(n);
-        om2l.resize(n);
-        op2p.resize(n);
-        walk_classify(F.data(), n, w, action.data(), nchild.data(), nm2l.data(), np2p.data(), s);
-        scan_excl_i32(nchild.data(), ochild.data(), n, tots.data(), s);
-        scan_excl_i32(nm2l.data(), om2l.data(), n, tots.data() + 1, s);
-        scan_excl_i32(np2p.data(), op2p.data(), n, tots.data() + 2, s);
+        toff.resize(3 * (size_t)nthr);
+        btot.resize(3 * (size_t)nblk);
+        boff.resize(3 * (size_t)nblk);
+        walk_round_scan(F.data(), n, w, action.data(), toff.data(), btot.data(), boff.data(), tots.data(), s);
         SFMM_HIP(hipMemcpyAsync(P.pin->p, tots.data(), 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         SFMM_HIP(hipStreamSynchronize(s));
         const int nc = P.pin->p[0], am = P.pin->p[1], ap = P.pin->p[2];
@@ -309,8 +305,8 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
         m2l.grow((size_t)n_m2l + am, s);
         p2p.grow((size_t)n_p2p + ap, s);
         G.resize(std::max(nc, 1));
-        walk_emit(F.data(), n, w, action.data(), ochild.data(), om2l.data(), op2p.data(), G.data(), m2l.data(),
-                  n_m2l, p2p.data(), n_p2p, s);
+        walk_round_emit(F.data(), n, w, action.data(), toff.data(), boff.data(), G.data(), m2l.data(), n_m2l,
+                        p2p.data(), n_p2p, s);
         n_m2l += am;
         n_p2p += ap;
         std::swap(F.p, G.p);

@@ -31,30 +31,39 @@ __global__ void __launch_bounds__(128) k_p2m(FmmCtx c, int nb) {
     p2m_finish<P>(a, c.mult + (size_t)b * (2 * P + 2));
 }
 
-// Lemma 2: every split box of one level gathers its 4 children
+// Lemma 2: every split box of one level gathers its 4 children.  Four
+// consecutive lanes per box, lane 4i + k translating child k; the four
+// translated records are summed by two lane exchanges, (c0 + c1) + (c2 + c3),
+// and lane 4i writes the box's record.
 template <int P>
 __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid >> 2, kc = gid & 3;
+    if (i >= nb) return;  // the four lanes of a box leave together
     const int b = b0 + i;
     const int ch0 = c.child0[b];
     if (ch0 < 0) return;
-    double rho_t;
-    const Frame ft = box_frame(c.cen, b, &rho_t);
     double acc[2 * P + 2];
 #pragma unroll
     for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        const int ch = ch0 + k;
-        if (c.count[ch] == 0) continue;
-        double rho_s;
+    const int ch = ch0 + kc;
+    if (c.count[ch] > 0) {
+        double rho_t, rho_s;
+        const Frame ft = box_frame(c.cen, b, &rho_t);
         const Frame fs = box_frame(c.cen, ch, &rho_s);
         const TransGeom G = trans_geom<kM2M>(fs, rho_s, ft, rho_t);
         translate_add<P>(c.mult + (size_t)ch * (2 * P + 2), G, acc);
     }
-    double* out = c.mult + (size_t)b * (2 * P + 2);
 #pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
+    for (int k = 0; k < 2 * P + 2; ++k) {
+        acc[k] += __shfl_xor(acc[k], 1, 64);
+        acc[k] += __shfl_xor(acc[k], 2, 64);
+    }
+    if (kc == 0) {
+        double* out = c.mult + (size_t)b * (2 * P + 2);
+#pragma unroll
+        for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
+    }
 }
 
 // Lemma 3: each target box sums its FMM-act list (boxes taken longest list
@@ -186,7 +195,7 @@ void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s) {
 
 void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s) {
     if (nb <= 0) return;
-#define L_(P) case P: k_m2m<P><<<nblk(nb, 128), 128, 0, s>>>(c, b0, nb); break;
+#define L_(P) case P: k_m2m<P><<<nblk(4 * (int64_t)nb, 128), 128, 0, s>>>(c, b0, nb); break;
     SFMM_DISPATCH(c.p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();

@@ -262,8 +262,7 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
     int* tot = (int*)pool_alloc(sizeof(int));
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
-    int npass = (bits - begin_bit + 7) / 8;
-    if (npass & 1) ++npass;  // even number of passes: result lands in the caller's buffers
+    const int npass = (bits - begin_bit + 7) / 8;
     if (begin_bit + 8 * npass > 64) begin_bit = 64 - 8 * npass;
     for (int pass = 0; pass < npass; ++pass) {
         const int shift = begin_bit + 8 * pass;
@@ -274,6 +273,10 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
+    }
+    if (npass & 1) {  // an odd number of passes leaves the result in the scratch buffers
+        SFMM_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        if (vals) SFMM_HIP(hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     }
     SFMM_HIP(hipStreamSynchronize(s));
     pool_free(k2);

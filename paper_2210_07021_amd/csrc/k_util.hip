@@ -205,13 +205,41 @@ __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, 
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
-                             int shift, int nblk, const int* offs) {
-    __shared__ int base[256];
+// Stable scatter of one tile.  The ranks give every key its position in the
+// tile sorted by digit (the tile's digit counts come from the histogram
+// pass: same tiles); the keys are staged there in LDS and then written out
+// in that order, so consecutive lanes write consecutive addresses within each
+// digit's run.
+__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                           uint32_t* vout, int64_t n, int shift, int nblk,
+                                                           const int* offs, const int* hist) {
+    __shared__ int gbase[256];  // global start of each digit's run of this tile
+    __shared__ int lbase[256];  // start of each digit's run inside the tile
+    __shared__ int run[256];    // keys of each digit placed so far
     __shared__ int wcnt[kRsWaves][256];
+    __shared__ int wsum[kRsWaves];
+    __shared__ uint64_t sk[kRsTile];
+    __shared__ uint32_t sv[kRsTile];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    base[t] = offs[t * nblk + blockIdx.x];
+    gbase[t] = offs[t * nblk + blockIdx.x];
+    run[t] = 0;
+    // exclusive scan of this tile's digit counts
+    {
+        const int c = hist[t * nblk + blockIdx.x];
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int before = 0;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) before += w < wave ? wsum[w] : 0;
+        lbase[t] = before + x - c;
+    }
     const uint64_t lt_mask = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
     const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
     for (int r = 0; r < kRsRounds; ++r) {
@@ -238,17 +266,25 @@ __global__ void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t*
         if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            int pos = base[d] + rank;
+            int pos = lbase[d] + run[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            if (vout) vout[pos] = val;
+            sk[pos] = key;
+            sv[pos] = val;
         }
         __syncthreads();
         int add = 0;
 #pragma unroll
         for (int w = 0; w < kRsWaves; ++w) add += wcnt[w][t];
-        base[t] += add;
-        __syncthreads();
+        run[t] += add;
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kRsTile, n - tile0);
+    for (int p = t; p < cnt; p += kRsThreads) {
+        const uint64_t key = sk[p];
+        const int d = (int)((key >> shift) & 255);
+        const int pos = gbase[d] + (p - lbase[d]);
+        kout[pos] = key;
+        if (vout) vout[pos] = sv[p];
     }
 }
 
@@ -269,7 +305,7 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
         k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, nblk, hist);
         SFMM_LAUNCH_CHECK();
         scan_excl_i32(hist, offs, 256 * (int64_t)nblk, tot, s);
-        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs);
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, hist);
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);

@@ -114,10 +114,10 @@ void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 // Copy [3][n] planes, check they are unit vectors (err bit 1: non-finite,
 // bit 2: off the sphere by more than 1e-6), renormalise ones off by more
 // than 1e-14, and compute their order-29 keys.
-void prepare_points(const double* in, int64_t n, double* x, double* y, double* z, uint64_t* keys,
-                    uint32_t* idx, int* err, hipStream_t s);
-void gather_points(const uint32_t* idx, int64_t n, const double* x, const double* y, const double* z,
-                   const double* q_in, double* ox, double* oy, double* oz, double* oq, hipStream_t s);
+void prepare_points(const double* in, const double* q /*nullable*/, int64_t n, double4* u /*[n] x,y,z,q*/,
+                    uint64_t* keys, uint32_t* idx, int* err, hipStream_t s);
+void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
+                   double* oq /*nullable*/, hipStream_t s);
 void tree_base_level(const uint64_t* keys, int64_t n, int* level, uint64_t* pixel, int* first, int* count,
                      int* parent, int* child0, hipStream_t s);
 void tree_split_flags(int b0, int nb, const int* level, const int* count, int m, int max_level, int* flag,

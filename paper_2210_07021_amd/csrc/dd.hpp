@@ -96,6 +96,50 @@ SFMM_HD dd dd_quarter_pi() { return {0.78539816339744830962, 3.06161699786838301
 
 // sin and cos of a double-double argument: reduce by multiples of pi/2 to
 // |r| <= pi/4, then Taylor series to the 29th power (|r|^31/31! < 1e-34).
+// 1/n! to double-double precision, n = 0..31: hi is 1/n! rounded to the
+// nearest double and lo the nearest double to the remainder.
+SFMM_HD dd inv_factorial(int n) {
+    constexpr double t[32][2] = {
+        {0x1.0000000000000p+0, 0x0.0p+0},
+        {0x1.0000000000000p+0, 0x0.0p+0},
+        {0x1.0000000000000p-1, 0x0.0p+0},
+        {0x1.5555555555555p-3, 0x1.5555555555555p-57},
+        {0x1.5555555555555p-5, 0x1.5555555555555p-59},
+        {0x1.1111111111111p-7, 0x1.1111111111111p-63},
+        {0x1.6c16c16c16c17p-10, -0x1.f49f49f49f49fp-65},
+        {0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-73},
+        {0x1.a01a01a01a01ap-16, 0x1.a01a01a01a01ap-76},
+        {0x1.71de3a556c734p-19, -0x1.c154f8ddc6c00p-73},
+        {0x1.27e4fb7789f5cp-22, 0x1.cbbc05b4fa99ap-76},
+        {0x1.ae64567f544e4p-26, -0x1.c062e06d1f209p-80},
+        {0x1.1eed8eff8d898p-29, -0x1.2aec959e14c06p-83},
+        {0x1.6124613a86d09p-33, 0x1.f28e0cc748ebep-87},
+        {0x1.93974a8c07c9dp-37, 0x1.05d6f8a2efd1fp-92},
+        {0x1.ae7f3e733b81fp-41, 0x1.1d8656b0ee8cbp-97},
+        {0x1.ae7f3e733b81fp-45, 0x1.1d8656b0ee8cbp-101},
+        {0x1.952c77030ad4ap-49, 0x1.ac981465ddc6cp-103},
+        {0x1.6827863b97d97p-53, 0x1.eec01221a8b0bp-107},
+        {0x1.2f49b46814157p-57, 0x1.2650f61dbdcb4p-112},
+        {0x1.e542ba4020225p-62, 0x1.ea72b4afe3c2fp-120},
+        {0x1.71b8ef6dcf572p-66, -0x1.d043ae40c4647p-120},
+        {0x1.0ce396db7f853p-70, -0x1.aebcdbd20331cp-124},
+        {0x1.761b41316381ap-75, -0x1.3423c7d91404fp-130},
+        {0x1.f2cf01972f578p-80, -0x1.9ada5fcc1ab14p-135},
+        {0x1.3f3ccdd165fa9p-84, -0x1.58ddadf344487p-139},
+        {0x1.88e85fc6a4e5ap-89, -0x1.71c37ebd16540p-143},
+        {0x1.d1ab1c2dccea3p-94, 0x1.054d0c78aea14p-149},
+        {0x1.0a18a2635085dp-98, 0x1.b9e2e28e1aa54p-153},
+        {0x1.259f98b4358adp-103, 0x1.eaf8c39dd9bc5p-157},
+        {0x1.3932c5047d60ep-108, 0x1.832b7b530a627p-162},
+        {0x1.434d2e783f5bcp-113, 0x1.0b87b91be9affp-167},
+    };
+    return {t[n][0], t[n][1]};
+}
+
+// sin and cos of a double-double angle: reduction by multiples of pi/2 to
+// |r| <= pi/4, then the two Taylor series in r^2 by Horner's rule with the
+// tabulated 1/n! (terms through r^31/31! and r^30/30!, whose successors are
+// below 1e-33 on that range).
 SFMM_HD void dd_sincos(dd x, dd* s_out, dd* c_out) {
 #pragma clang fp contract(off)
     const double kf = nearbyint(x.hi * 0.63661977236758138243);
@@ -104,12 +148,12 @@ SFMM_HD void dd_sincos(dd x, dd* s_out, dd* c_out) {
     dd r = dd_sub(x, dd_mul_d(dd_half_pi(), kf));
     r = dd_sub(r, dd_from(kf * -1.4973849048591698e-33));
     const dd r2 = dd_mul(r, r);
-    // sin r = r (1 - r^2/(2*3) (1 - r^2/(4*5) (1 - ...)))  Horner from the top
-    dd s = dd_from(1.0), c = dd_from(1.0);
-    for (int n = 30; n >= 2; n -= 2) {
-        // sin: factor r^2 / ((n)(n+1)) with n even -> terms r^{n+1}/(n+1)!
-        s = dd_sub(dd_from(1.0), dd_mul(s, dd_div(r2, dd_from((double)(n * (n + 1))))));
-        c = dd_sub(dd_from(1.0), dd_mul(c, dd_div(r2, dd_from((double)((n - 1) * n)))));
+    // s = sum_j (-1)^j r^2j / (2j+1)!, c = sum_j (-1)^j r^2j / (2j)!
+    dd s = inv_factorial(31), c = inv_factorial(30);
+#pragma unroll
+    for (int j = 14; j >= 0; --j) {
+        s = dd_sub(inv_factorial(2 * j + 1), dd_mul(r2, s));
+        c = dd_sub(inv_factorial(2 * j), dd_mul(r2, c));
     }
     s = dd_mul(s, r);
     dd so, co;

@@ -223,14 +223,26 @@ struct BoxGeomDD {
 SFMM_HD BoxGeomDD box_geometry(int level, uint64_t pix) {
     BoxGeomDD g;
     pix_point_dd(level, pix, 0.5, 0.5, g.c);
-    g.r = dd_from(0.0);
+    // the farthest vertex is the one of largest chord |v - c| (the angle is
+    // 2 asin(chord / 2), increasing in the chord); one angular distance then
     const double cf[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    dd far[3], best = dd_from(-1.0);
     for (int k = 0; k < 4; ++k) {
         dd v[3];
         pix_point_dd(level, pix, cf[k][0], cf[k][1], v);
-        const dd d = angdist_dd(g.c, v);
-        if (dd_lt(g.r, d)) g.r = d;
+        dd ch = dd_from(0.0);
+        for (int i = 0; i < 3; ++i) {
+            const dd e = dd_sub(v[i], g.c[i]);
+            ch = dd_add(ch, dd_mul(e, e));
+        }
+        if (dd_lt(best, ch)) {
+            best = ch;
+            far[0] = v[0];
+            far[1] = v[1];
+            far[2] = v[2];
+        }
     }
+    g.r = angdist_dd(g.c, far);
     return g;
 }
 

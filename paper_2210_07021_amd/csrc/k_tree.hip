@@ -9,7 +9,11 @@ namespace sfmm {
 static unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
 // ------------------------------------------------------------------ points
-__global__ void k_prepare_points(const double* in, int64_t n, double* x, double* y, double* z, uint64_t* keys,
+// Unit vectors, keys and identity permutation of n points given as [3][n];
+// each point is written as one 32-byte record (x, y, z, q) so that the
+// gather after the key sort moves one aligned record per point (q = 0 when
+// the points carry no charge).
+__global__ void k_prepare_points(const double* in, const double* q, int64_t n, double4* u, uint64_t* keys,
                                  uint32_t* idx, int* err) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -25,35 +29,33 @@ __global__ void k_prepare_points(const double* in, int64_t n, double* x, double*
         const double inv = 1.0 / sqrt(r2);
         a *= inv; b *= inv; c *= inv;
     }
-    x[i] = a;
-    y[i] = b;
-    z[i] = c;
+    u[i] = make_double4(a, b, c, q ? q[i] : 0.0);
     keys[i] = key29(a, b, c);
     idx[i] = (uint32_t)i;
 }
 
-void prepare_points(const double* in, int64_t n, double* x, double* y, double* z, uint64_t* keys,
-                    uint32_t* idx, int* err, hipStream_t s) {
+void prepare_points(const double* in, const double* q, int64_t n, double4* u, uint64_t* keys, uint32_t* idx,
+                    int* err, hipStream_t s) {
     if (n <= 0) return;
-    k_prepare_points<<<nblocks(n, 256), 256, 0, s>>>(in, n, x, y, z, keys, idx, err);
+    k_prepare_points<<<nblocks(n, 256), 256, 0, s>>>(in, q, n, u, keys, idx, err);
     SFMM_LAUNCH_CHECK();
 }
 
-__global__ void k_gather_points(const uint32_t* idx, int64_t n, const double* x, const double* y,
-                                const double* z, const double* q, double* ox, double* oy, double* oz, double* oq) {
+__global__ void k_gather_points(const uint32_t* idx, int64_t n, const double4* __restrict__ u, double* ox,
+                                double* oy, double* oz, double* oq) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t j = idx[i];
-    ox[i] = x[j];
-    oy[i] = y[j];
-    oz[i] = z[j];
-    if (q) oq[i] = q[j];
+    const double4 v = u[idx[i]];
+    ox[i] = v.x;
+    oy[i] = v.y;
+    oz[i] = v.z;
+    if (oq) oq[i] = v.w;
 }
 
-void gather_points(const uint32_t* idx, int64_t n, const double* x, const double* y, const double* z,
-                   const double* q, double* ox, double* oy, double* oz, double* oq, hipStream_t s) {
+void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
+                   double* oq, hipStream_t s) {
     if (n <= 0) return;
-    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, x, y, z, q, ox, oy, oz, oq);
+    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, u, ox, oy, oz, oq);
     SFMM_LAUNCH_CHECK();
 }
 
@@ -158,7 +160,7 @@ __global__ void k_box_geometry(int nb, const int* level, const uint64_t* pixel, 
 void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen, double* rad, double* gdd,
                   hipStream_t s) {
     if (nb <= 0) return;
-    k_box_geometry<<<nblocks(nb, 64), 64, 0, s>>>(nb, level, pixel, cen, rad, gdd);
+    k_box_geometry<<<nblocks(nb, 128), 128, 0, s>>>(nb, level, pixel, cen, rad, gdd);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -195,20 +195,17 @@ void sort_points(const double* in, const double* q_in, int64_t n, DVec<double>& 
     perm.resize(n);
     keys.resize(n);
     if (n == 0) return;
-    DVec<double> ux, uy, uz;
-    ux.resize(n);
-    uy.resize(n);
-    uz.resize(n);
+    DVec<double4> u;
+    u.resize(n);
     DVec<int> err;
     err.resize(1);
     fill_i32(err.data(), 1, 0, s);
-    prepare_points(in, n, ux.data(), uy.data(), uz.data(), keys.data(), perm.data(), err.data(), s);
+    prepare_points(in, oq ? q_in : nullptr, n, u.data(), keys.data(), perm.data(), err.data(), s);
     const int e = read_int(err.data(), P, s);
     if (e & 1) throw Error(ST_INVALID_ARG, std::string(what) + ": non-finite coordinates");
     if (e & 2) throw Error(ST_INVALID_ARG, std::string(what) + ": points off the unit sphere by more than 1e-6");
     radix_sort_u64(keys.data(), perm.data(), n, 62, s);
-    gather_points(perm.data(), n, ux.data(), uy.data(), uz.data(), oq ? q_in : nullptr, ox.data(), oy.data(),
-                  oz.data(), oq ? oq->data() : nullptr, s);
+    gather_points(perm.data(), n, u.data(), ox.data(), oy.data(), oz.data(), oq ? oq->data() : nullptr, s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 

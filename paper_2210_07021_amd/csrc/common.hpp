@@ -107,7 +107,7 @@ void fill_i32(int* p, size_t n, int v, hipStream_t s);
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s);
 // stable LSD radix sort of (key, value) pairs on key bits [begin_bit, bits)
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit = 0);
-void sum_f64(const double* x, int64_t n, double* out, hipStream_t s);
+void sum_f64(const double* x, int64_t n, double* out, hipStream_t s, int stride = 1);  // sum of x[i * stride]
 void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 
 // ---------------------------------------------------------------- tree
@@ -117,7 +117,8 @@ void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 void prepare_points(const double* in, const double* q /*nullable*/, int64_t n, double4* u /*[n] x,y,z,q*/,
                     uint64_t* keys, uint32_t* idx, int* err, hipStream_t s);
 void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
-                   double* oq /*nullable*/, hipStream_t s);
+                   hipStream_t s);
+void gather_records(const uint32_t* idx, int64_t n, const double4* u, double4* out, hipStream_t s);
 void tree_base_level(const uint64_t* keys, int64_t n, int* level, uint64_t* pixel, int* first, int* count,
                      int* parent, int* child0, hipStream_t s);
 void tree_split_flags(int b0, int nb, const int* level, const int* count, int m, int max_level, int* flag,
@@ -173,10 +174,7 @@ struct FmmCtx {
     const int* count;
     const int* parent;
     const int* child0;
-    const double* sx;
-    const double* sy;
-    const double* sz;
-    const double* sq;
+    const double4* spt;  // sources sorted by key: x, y, z, q
     double* mult;        // [nb][2p+2]
     double* local;       // [nb][2p+2]
 };

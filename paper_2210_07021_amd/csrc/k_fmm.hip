@@ -27,7 +27,10 @@ __global__ void __launch_bounds__(128) k_p2m(FmmCtx c, int nb) {
     P2MAcc<P> a;
     p2m_init<P>(a);
     const int i0 = c.first[b], i1 = i0 + c.count[b];
-    for (int i = i0; i < i1; ++i) p2m_add<P>(a, f, inv_rho, c.sx[i], c.sy[i], c.sz[i], c.sq[i]);
+    for (int i = i0; i < i1; ++i) {
+        const double4 v = c.spt[i];
+        p2m_add<P>(a, f, inv_rho, v.x, v.y, v.z, v.w);
+    }
     p2m_finish<P>(a, c.mult + (size_t)b * (2 * P + 2));
 }
 

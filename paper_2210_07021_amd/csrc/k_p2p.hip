@@ -46,7 +46,7 @@
 
 namespace sfmm {
 
-constexpr int kTile = 256;  // particles staged in LDS per tile
+constexpr int kTile = 128;  // particles staged in LDS per tile
 
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
@@ -374,13 +374,11 @@ struct TileF32 {
     float4 lo[kTile];  // x, y, z low parts
 };
 
-__device__ __forceinline__ void tile_store(TileF64& t, int k, double x, double y, double z, double q) {
-    t.p[k] = make_double4(x, y, z, q);
-}
-__device__ __forceinline__ void tile_store(TileF32& t, int k, double x, double y, double z, double q) {
-    const float xh = (float)x, yh = (float)y, zh = (float)z;
-    t.hi[k] = make_float4(xh, yh, zh, (float)q);
-    t.lo[k] = make_float4((float)(x - (double)xh), (float)(y - (double)yh), (float)(z - (double)zh), 0.0f);
+__device__ __forceinline__ void tile_store(TileF64& t, int k, double4 v) { t.p[k] = v; }
+__device__ __forceinline__ void tile_store(TileF32& t, int k, double4 v) {
+    const float xh = (float)v.x, yh = (float)v.y, zh = (float)v.z;
+    t.hi[k] = make_float4(xh, yh, zh, (float)v.w);
+    t.lo[k] = make_float4((float)(v.x - (double)xh), (float)(v.y - (double)yh), (float)(v.z - (double)zh), 0.0f);
 }
 
 __device__ __forceinline__ void tile_pairs(const TileF64& t, int r, int L, int tn, double ax, double ay, double az,
@@ -433,18 +431,19 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
                                            double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
-    __shared__ Tile tile;
-    __shared__ double red[4][64];
+    // the tile and the end-of-group reduction share one LDS block (fewer
+    // bytes per wave, more waves per CU)
+    constexpr size_t kSm = sizeof(Tile) > 4 * 64 * sizeof(double) ? sizeof(Tile) : 4 * 64 * sizeof(double);
+    __shared__ __align__(16) unsigned char sm[kSm];
+    Tile& tile = *reinterpret_cast<Tile*>(sm);
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(sm);
     const int lane = threadIdx.x;
     const int4 item = items[blockIdx.x];
     const int T = item.x;
     const int k0 = item.y, K = item.z - item.y;
     const int t0 = tfirst[T], nt = tcount[T];
     const int ew = 2 * c.p + 2;
-    const double* __restrict__ sx = c.sx;
-    const double* __restrict__ sy = c.sy;
-    const double* __restrict__ sz = c.sz;
-    const double* __restrict__ sq = c.sq;
+    const double4* __restrict__ spt = c.spt;
 
     for (int tg = 0; tg < nt; tg += 64) {
         const int ng = min(64, nt - tg);
@@ -491,7 +490,7 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                     const int base = __shfl(fst, e, 64) - __shfl(excl, e, 64);
                     if (f < total) {
                         const int i = base + f;
-                        tile_store(tile, j * 64 + lane, sx[i], sy[i], sz[i], sq[i]);
+                        tile_store(tile, j * 64 + lane, spt[i]);
                     }
                 }
                 __syncthreads();
@@ -499,6 +498,7 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
             }
         }
         const double qn = wave_sum(qnear);
+        __syncthreads();  // the last tile fully consumed before red overwrites it
         red[0][lane] = p0;
         red[1][lane] = p1;
         red[2][lane] = p2;
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
 // lane r of team t evaluates leaves r, r + L, ... of the chunk at target t.
 // The team's partial sums are added in a fixed order at the end of the
 // group.
-constexpr int kChunkF = 32;
+constexpr int kChunkF = 16;
 
 template <int P>
 __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ items,
@@ -543,9 +543,11 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
                                            double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
     constexpr int EW = 2 * P + 2;
-    __shared__ double coef[kChunkF * EW];
+    // the staged records double as the end-of-group reduction buffer
+    static_assert(kChunkF * (2 * kM2PMinOrder + 2) >= 4 * 64, "reduction fits the record buffer");
+    __shared__ __align__(16) double coef[kChunkF * EW];
     __shared__ double frm[kChunkF][10];  // c, e_theta, e_phi, rho
-    __shared__ double red[4][64];
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(coef);
     const int lane = threadIdx.x;
     const int4 item = items[blockIdx.x];
     const int T = item.x;
@@ -563,9 +565,13 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
         for (int kc = 0; kc < K; kc += kChunkF) {
             const int cf = min(kChunkF, K - kc);
             __syncthreads();  // previous chunk fully consumed
-            for (int idx = lane; idx < cf * EW; idx += 64) {
-                const int f = idx / EW, e = idx - f * EW;
-                coef[idx] = c.mult[(size_t)src[k0 + kc + f] * EW + e];
+            // records are EW = 2P + 2 doubles (16-byte aligned): copied as
+            // double2, P + 1 per record
+#pragma unroll 4
+            for (int idx = lane; idx < cf * (P + 1); idx += 64) {
+                const int f = idx / (P + 1), e = idx - f * (P + 1);
+                reinterpret_cast<double2*>(coef)[idx] =
+                    reinterpret_cast<const double2*>(c.mult + (size_t)src[k0 + kc + f] * EW)[e];
             }
             if (lane < cf) {
                 const double* cs = c.cen + 4 * (size_t)src[k0 + kc + lane];
@@ -597,6 +603,7 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
                 }
             }
         }
+        __syncthreads();  // the last chunk fully consumed before red overwrites it
         red[0][lane] = p0;
         red[1][lane] = p1;
         red[2][lane] = p2;

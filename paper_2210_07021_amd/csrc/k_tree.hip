@@ -42,20 +42,30 @@ void prepare_points(const double* in, const double* q, int64_t n, double4* u, ui
 }
 
 __global__ void k_gather_points(const uint32_t* idx, int64_t n, const double4* __restrict__ u, double* ox,
-                                double* oy, double* oz, double* oq) {
+                                double* oy, double* oz) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 v = u[idx[i]];
     ox[i] = v.x;
     oy[i] = v.y;
     oz[i] = v.z;
-    if (oq) oq[i] = v.w;
 }
 
 void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
-                   double* oq, hipStream_t s) {
+                   hipStream_t s) {
     if (n <= 0) return;
-    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, u, ox, oy, oz, oq);
+    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, u, ox, oy, oz);
+    SFMM_LAUNCH_CHECK();
+}
+
+__global__ void k_gather_records(const uint32_t* idx, int64_t n, const double4* __restrict__ u, double4* out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = u[idx[i]];
+}
+
+void gather_records(const uint32_t* idx, int64_t n, const double4* u, double4* out, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_records<<<nblocks(n, 256), 256, 0, s>>>(idx, n, u, out);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -323,10 +323,10 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
 }
 
 // ------------------------------------------------------------------ sum
-__global__ void k_sum_tiles(const double* x, int64_t n, double* part) {
+__global__ void k_sum_tiles(const double* x, int64_t n, int stride, double* part) {
     __shared__ double sh[256];
     double acc = 0.0;
-    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc += x[i];
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc += x[i * stride];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -336,11 +336,11 @@ __global__ void k_sum_tiles(const double* x, int64_t n, double* part) {
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-void sum_f64(const double* x, int64_t n, double* out, hipStream_t s) {
+void sum_f64(const double* x, int64_t n, double* out, hipStream_t s, int stride) {
     double* part = (double*)pool_alloc(sizeof(double) * 1024);
-    k_sum_tiles<<<1024, 256, 0, s>>>(x, n, part);
+    k_sum_tiles<<<1024, 256, 0, s>>>(x, n, stride, part);
     SFMM_LAUNCH_CHECK();
-    k_sum_tiles<<<1, 256, 0, s>>>(part, 1024, out);
+    k_sum_tiles<<<1, 256, 0, s>>>(part, 1024, 1, out);
     SFMM_LAUNCH_CHECK();
     SFMM_HIP(hipStreamSynchronize(s));
     pool_free(part);

@@ -101,8 +101,8 @@ struct sfmm_plan_impl {
     int p = 0;
     int64_t N = 0, M = 0;
     double q_total = 0.0;
-    // sources, sorted by key
-    DVec<double> sx, sy, sz, sq;
+    // sources, sorted by key: (x, y, z, q) records
+    DVec<double4> spt;
     DVec<uint32_t> sperm;
     DVec<uint64_t> skeys;
     // boxes, ordered by (level, pixel)
@@ -148,10 +148,7 @@ struct sfmm_plan_impl {
         c.count = count.data();
         c.parent = parent.data();
         c.child0 = child0.data();
-        c.sx = sx.data();
-        c.sy = sy.data();
-        c.sz = sz.data();
-        c.sq = sq.data();
+        c.spt = spt.data();
         c.mult = mult.data();
         c.local = local.data();
         return c;
@@ -184,14 +181,19 @@ void validate(const sfmm_options& o) {
     if (o.far_segment != 0 && (o.far_segment < 8 || o.far_segment > 4096)) bad("far_segment must be 0 or in [8, 4096]");
 }
 
-// Sort points by key and keep the permutation; outputs resized here.
-void sort_points(const double* in, const double* q_in, int64_t n, DVec<double>& ox, DVec<double>& oy,
-                 DVec<double>& oz, DVec<double>* oq, DVec<uint32_t>& perm, DVec<uint64_t>& keys,
+// Sort points by key and keep the permutation; outputs resized here: the
+// sorted points as (x, y, z, q) records (sources, rec != nullptr) or as three
+// coordinate arrays (targets).
+void sort_points(const double* in, const double* q_in, int64_t n, DVec<double4>* rec, DVec<double>* ox,
+                 DVec<double>* oy, DVec<double>* oz, DVec<uint32_t>& perm, DVec<uint64_t>& keys,
                  sfmm_plan_impl& P, hipStream_t s, const char* what) {
-    ox.resize(n);
-    oy.resize(n);
-    oz.resize(n);
-    if (oq) oq->resize(n);
+    if (rec) {
+        rec->resize(n);
+    } else {
+        ox->resize(n);
+        oy->resize(n);
+        oz->resize(n);
+    }
     perm.resize(n);
     keys.resize(n);
     if (n == 0) return;
@@ -200,12 +202,13 @@ void sort_points(const double* in, const double* q_in, int64_t n, DVec<double>& 
     DVec<int> err;
     err.resize(1);
     fill_i32(err.data(), 1, 0, s);
-    prepare_points(in, oq ? q_in : nullptr, n, u.data(), keys.data(), perm.data(), err.data(), s);
+    prepare_points(in, rec ? q_in : nullptr, n, u.data(), keys.data(), perm.data(), err.data(), s);
     const int e = read_int(err.data(), P, s);
     if (e & 1) throw Error(ST_INVALID_ARG, std::string(what) + ": non-finite coordinates");
     if (e & 2) throw Error(ST_INVALID_ARG, std::string(what) + ": points off the unit sphere by more than 1e-6");
     radix_sort_u64(keys.data(), perm.data(), n, 62, s);
-    gather_points(perm.data(), n, u.data(), ox.data(), oy.data(), oz.data(), oq ? oq->data() : nullptr, s);
+    if (rec) gather_records(perm.data(), n, u.data(), rec->data(), s);
+    else gather_points(perm.data(), n, u.data(), ox->data(), oy->data(), oz->data(), s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -348,7 +351,7 @@ int count_boxes(const WorkItems& w) {
 }
 
 void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
-    sort_points(tgt, nullptr, P.M, P.tx, P.ty, P.tz, nullptr, P.tperm, P.tkeys, P, s, "targets");
+    sort_points(tgt, nullptr, P.M, nullptr, &P.tx, &P.ty, &P.tz, P.tperm, P.tkeys, P, s, "targets");
     P.tleaf.resize(std::max<int64_t>(P.M, 1));
     P.tfirst.resize(P.nbox);
     P.tcount.resize(P.nbox);
@@ -477,12 +480,12 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         Profiler prof(s);
         {
             StageScope st(prof, S_SRC);
-            sort_points(src, q, N, P->sx, P->sy, P->sz, &P->sq, P->sperm, P->skeys, *P, s, "sources");
+            sort_points(src, q, N, &P->spt, nullptr, nullptr, nullptr, P->sperm, P->skeys, *P, s, "sources");
         }
         if (N > 0) {
             DVec<double> qt;
             qt.resize(1);
-            sum_f64(P->sq.data(), N, qt.data(), s);
+            sum_f64(reinterpret_cast<const double*>(P->spt.data()) + 3, N, qt.data(), s, 4);  // the q of every record
             SFMM_HIP(hipMemcpy(&P->q_total, qt.data(), sizeof(double), hipMemcpyDeviceToHost));
         }
         build_tree(*P, s, prof);

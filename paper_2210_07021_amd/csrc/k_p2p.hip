@@ -386,10 +386,14 @@ __device__ __forceinline__ void tile_pairs(const TileF64& t, int r, int L, int t
     for (int j = r; j < tn; j += L) {
         const double4 sp = t.p[j];
         const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
-        const bool coinc = (dx == 0.0) & (dy == 0.0) & (dz == 0.0);
-        const double r2 = coinc ? 1.0 : dx * dx + dy * dy + dz * dz;
-        const double lg = coinc ? kLog4 : log_f64(r2);
-        const double wi = sp.w * recip(r2);
+        // |d|^2 of two distinct unit vectors is >= ~1e-32: zero only for
+        // coincident points (no branch: every lane takes the same path)
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const bool coinc = d2 == 0.0;
+        double l0, i0;
+        log_recip_f64(coinc ? 1.0 : d2, &l0, &i0);
+        const double lg = coinc ? kLog4 : l0;
+        const double wi = sp.w * i0;
         p0 = fma(sp.w, lg, p0);
         p1 = fma(wi, dx, p1);
         p2 = fma(wi, dy, p2);

@@ -145,14 +145,25 @@ struct WalkCtx {
 };
 // M2L order: boxes of levels <= lc first, then the others; longest list
 // first within each part (16-bit keys, ties in table order)
-// one walk round in three launches: classify + per-block scans, scan of the
-// block totals (tot[3]: children pairs, M2L pairs, P2P pairs), emit
-void walk_round_sizes(int n, int* nthr_total, int* nblk);
-void walk_round_scan(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* toff, int* btot, int* boff,
-                     int* tot, hipStream_t s);
-void walk_round_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* toff,
-                     const int* boff, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
-                     hipStream_t s);
+// One walk round in three launches (classify + per-chunk scans, scan of the
+// chunk totals into tot[3]: children pairs, M2L pairs, P2P pairs; emit),
+// sized on the device: st = {frontier size, M2L base, P2P base} of this
+// round, st_next those of the next (written by the emit).  The per-round
+// scratch (action [n], toff [3][tstride], ctot/coff [3][cstride]) must hold
+// the round's n; cap bounds the next frontier and the two lists, and a round
+// whose output would not fit writes nothing, sets *overflow and ends the walk.
+struct WalkCaps {
+    int frontier, m2l, p2p;
+};
+struct WalkScratch {
+    int chunks, threads;  // chunks of a round of n pairs, and threads = chunks x block size
+};
+WalkScratch walk_scratch_sizes(int n);
+void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* toff, int tstride,
+                     int* ctot, int* coff, int cstride, int* tot, int grid, hipStream_t s);
+void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* toff,
+                     int tstride, const int* coff, int cstride, const int* tot, const WalkCaps& cap, int2* Fnext,
+                     uint64_t* m2l, uint64_t* p2p, int* st_next, int* overflow, int grid, hipStream_t s);
 void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
                     hipStream_t s);
 // precision tier: M2L into boxes of levels <= kFp32CoarseLevel stays FP64
@@ -160,7 +171,8 @@ void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t
 // which FP32 rounding would show)
 constexpr int kFp32CoarseLevel = 6;
 // pairs (target << 32 | source) sorted by target -> CSR offsets and sources
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off /*[nbox+1]*/, int* src, hipStream_t s);
+void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* ent /*nullable*/,
+                  hipStream_t s);
 // sort keys (8 bits) putting the boxes with the most work first, in
 // power-of-two buckets; flag the boxes that have any
 void work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s);
@@ -200,9 +212,9 @@ struct NearLists {
     DVec<int> near_off, near_src, far_off, far_src;
     int n_near = 0, n_far = 0;
 };
-void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
-                const int* tcount, const double* tx, const double* ty, const double* tz, NearLists& out,
-                hipStream_t s);
+void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_t, int nbox, int np,
+                const int* tfirst, const int* tcount, const double* tx, const double* ty, const double* tz,
+                NearLists& out, hipStream_t s);
 // Near-field work items: segment [y, z) of box x's list, results to the
 // outputs (w < 0) or to partial slots w .. w + tcount[x] - 1; reduce records
 // (box, segments, first slot) for the boxes cut into several segments.

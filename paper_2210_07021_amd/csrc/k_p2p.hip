@@ -159,16 +159,16 @@ void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s) {
     SFMM_LAUNCH_CHECK();
 }
 
-void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int np, const int* tfirst,
-                const int* tcount, const double* tx, const double* ty, const double* tz, NearLists& out,
-                hipStream_t s) {
+// ent_t: the target box of every entry
+void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_t, int nbox, int np,
+                const int* tfirst, const int* tcount, const double* tx, const double* ty, const double* tz,
+                NearLists& out, hipStream_t s) {
     out.near_off.resize(nbox + 1);
     out.far_off.resize(nbox + 1);
     out.n_near = out.n_far = 0;
     if (nbox <= 0) return;
-    DVec<int> ent_t, near, far, npos, fpos, tot;
+    DVec<int> near, far, npos, fpos, tot;
     const int n1 = std::max(np, 1);
-    ent_t.resize(n1);
     near.resize(n1);
     far.resize(n1);
     npos.resize(n1);
@@ -176,9 +176,7 @@ void near_split(const FmmCtx& c, const int* off, const int* src, int nbox, int n
     tot.resize(2);
     fill_i32(tot.data(), 2, 0, s);
     if (np > 0) {
-        k_entry_box<<<nblk(np, 256), 256, 0, s>>>(off, nbox, np, ent_t.data());
-        SFMM_LAUNCH_CHECK();
-        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t.data(), src, np, tfirst, tcount, tx, ty, tz,
+        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t, src, np, tfirst, tcount, tx, ty, tz,
                                                    near.data(), far.data());
         SFMM_LAUNCH_CHECK();
         scan_excl_i32(near.data(), npos.data(), np, tot.data(), s);

@@ -247,13 +247,17 @@ __device__ bool box_far(const WalkCtx& w, int s, int t) {
     return mac_far(cs, ct, gs[6], gt[6], csd, ctd, dd{gs[6], gs[7]}, dd{gt[6], gt[7]}, w.c_s, w.c_t);
 }
 
-// One round of the walk in three launches.  Thread g of k_walk_round_scan
-// classifies pairs 4g .. 4g+3 and the block scans the three counts of its
-// threads (children pairs, M2L pairs, P2P pairs); k_walk_block_scan scans
-// the block totals; k_walk_round_emit writes each thread's outputs from its
-// base offsets, in pair order (so the lists come out in the same order as a
-// scan over single pairs).
-constexpr int kWalkItems = 4, kWalkThreads = 256;
+// One round of the walk in three launches, sized on the device: the round's
+// frontier size and output bases sit in st[0..2] (written by the previous
+// round's emit), so rounds can be queued without reading anything back.  The
+// pairs are taken in chunks of kWalkChunk, chunk c by workgroup c mod grid.
+// Thread g of chunk c classifies pairs 4g .. 4g+3 of the chunk and the
+// workgroup scans the three counts of its threads (children pairs, M2L
+// pairs, P2P pairs); k_walk_chunk_scan scans the chunk totals;
+// k_walk_emit writes each thread's outputs from its base offsets, in pair
+// order (so the lists come out in the same order as a scan over single
+// pairs).
+constexpr int kWalkItems = 4, kWalkThreads = 256, kWalkChunk = kWalkItems * kWalkThreads;
 
 __device__ __forceinline__ uint8_t walk_action(const WalkCtx& w, int s, int t) {
     if (w.count[s] == 0) return A_NONE;
@@ -274,63 +278,70 @@ __device__ __forceinline__ int walk_nchild(uint8_t a) {
     return (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
 }
 
-__global__ void __launch_bounds__(kWalkThreads) k_walk_round_scan(const int2* __restrict__ F, int n, WalkCtx w,
-                                                                  uint8_t* __restrict__ action,
-                                                                  int* __restrict__ toff, int nthr,
-                                                                  int* __restrict__ btot, int nblk) {
+__global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __restrict__ F, const int* __restrict__ st,
+                                                                WalkCtx w, uint8_t* __restrict__ action,
+                                                                int* __restrict__ toff, int tstride,
+                                                                int* __restrict__ ctot, int cstride) {
     __shared__ int sh[3][kWalkThreads / 64];
-    const int g = blockIdx.x * kWalkThreads + threadIdx.x;
-    int c[3] = {0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < kWalkItems; ++i) {
-        const int k = g * kWalkItems + i;
-        if (k < n) {
-            const uint8_t a = walk_action(w, F[k].x, F[k].y);
-            action[k] = a;
-            c[0] += walk_nchild(a);
-            c[1] += a == A_M2L;
-            c[2] += a == A_P2P;
-        }
-    }
+    const int n = st[0];
+    const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int g = ch * kWalkThreads + threadIdx.x;
+        int c[3] = {0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        int x = c[j];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+        for (int i = 0; i < kWalkItems; ++i) {
+            const int k = g * kWalkItems + i;
+            if (k < n) {
+                const uint8_t a = walk_action(w, F[k].x, F[k].y);
+                action[k] = a;
+                c[0] += walk_nchild(a);
+                c[1] += a == A_M2L;
+                c[2] += a == A_P2P;
+            }
         }
-        if (lane == 63) sh[j][wv] = x;
-        c[j] = x - c[j];  // exclusive within the wave
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        int before = 0, all = 0;
+        for (int j = 0; j < 3; ++j) {
+            int x = c[j];
 #pragma unroll
-        for (int v = 0; v < kWalkThreads / 64; ++v) {
-            before += v < wv ? sh[j][v] : 0;
-            all += sh[j][v];
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) sh[j][wv] = x;
+            c[j] = x - c[j];  // exclusive within the wave
         }
-        toff[(size_t)j * nthr + g] = before + c[j];
-        if (threadIdx.x == 0) btot[(size_t)j * nblk + blockIdx.x] = all;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            int before = 0, all = 0;
+#pragma unroll
+            for (int v = 0; v < kWalkThreads / 64; ++v) {
+                before += v < wv ? sh[j][v] : 0;
+                all += sh[j][v];
+            }
+            toff[(size_t)j * tstride + g] = before + c[j];
+            if (threadIdx.x == 0) ctot[(size_t)j * cstride + ch] = all;
+        }
+        __syncthreads();  // sh is rewritten by the next chunk
     }
 }
 
-// exclusive scans of the three block-total arrays (one workgroup each, in
-// chunks with a running carry); tot[j] = the total of array j
-__global__ void __launch_bounds__(256) k_walk_block_scan(const int* __restrict__ btot, int nblk,
-                                                         int* __restrict__ boff, int* __restrict__ tot) {
+// exclusive scans of the three chunk-total arrays (one workgroup each, in
+// pieces of 256 with a running carry); tot[j] = the total of array j
+__global__ void __launch_bounds__(256) k_walk_chunk_scan(const int* __restrict__ st, const int* __restrict__ ctot,
+                                                         int cstride, int* __restrict__ coff, int* __restrict__ tot) {
     __shared__ int sh[256 / 64];
+    const int n = st[0];
+    const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
     const int j = blockIdx.x;
-    const int* in = btot + (size_t)j * nblk;
-    int* out = boff + (size_t)j * nblk;
+    const int* in = ctot + (size_t)j * cstride;
+    int* out = coff + (size_t)j * cstride;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int carry = 0;
-    for (int c0 = 0; c0 < nblk; c0 += 256) {
+    for (int c0 = 0; c0 < nchunk; c0 += 256) {
         const int i = c0 + threadIdx.x;
-        const int v = i < nblk ? in[i] : 0;
+        const int v = i < nchunk ? in[i] : 0;
         int x = v;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -345,7 +356,7 @@ __global__ void __launch_bounds__(256) k_walk_block_scan(const int* __restrict__
             before += q < wv ? sh[q] : 0;
             all += sh[q];
         }
-        if (i < nblk) out[i] = carry + before + x - v;
+        if (i < nchunk) out[i] = carry + before + x - v;
         carry += all;
         __syncthreads();
     }
@@ -354,71 +365,91 @@ __global__ void __launch_bounds__(256) k_walk_block_scan(const int* __restrict__
 
 __device__ uint64_t pair_key(int s, int t) { return ((uint64_t)(uint32_t)t << 32) | (uint32_t)s; }
 
-__global__ void __launch_bounds__(kWalkThreads) k_walk_round_emit(const int2* __restrict__ F, int n, WalkCtx w,
-                                                                  const uint8_t* __restrict__ action,
-                                                                  const int* __restrict__ toff, int nthr,
-                                                                  const int* __restrict__ boff, int nblk,
-                                                                  int2* __restrict__ Fnext, uint64_t* __restrict__ m2l,
-                                                                  int m2l_base, uint64_t* __restrict__ p2p,
-                                                                  int p2p_base) {
-    const int g = blockIdx.x * kWalkThreads + threadIdx.x;
-    if (g * kWalkItems >= n) return;
-    int oc = boff[blockIdx.x] + toff[g];
-    int om = boff[(size_t)nblk + blockIdx.x] + toff[(size_t)nthr + g];
-    int op = boff[2 * (size_t)nblk + blockIdx.x] + toff[2 * (size_t)nthr + g];
-#pragma unroll
-    for (int i = 0; i < kWalkItems; ++i) {
-        const int k = g * kWalkItems + i;
-        if (k >= n) break;
-        const int s = F[k].x, t = F[k].y;
-        const uint8_t a = action[k];
-        int2* out = Fnext + oc;
-        switch (a) {
-            case A_M2L: m2l[m2l_base + om++] = pair_key(s, t); break;
-            case A_P2P: p2p[p2p_base + op++] = pair_key(s, t); break;
-            case A_SPLIT_S:
-                for (int q = 0; q < 4; ++q) out[q] = make_int2(w.child0[s] + q, t);
-                break;
-            case A_SPLIT_T:
-                for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.child0[t] + q);
-                break;
-            case A_SPLIT_SELF:
-                for (int q = 0; q < 4; ++q)
-                    for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.child0[s] + q, w.child0[s] + r);
-                break;
-            default: break;
+// Emit of one round.  The next frontier (tot[0] pairs) and the lists'
+// new ends are checked against the capacities first: when anything would not
+// fit, nothing is written, *overflow is set and the next round is empty (the
+// caller then runs the walk again with room to spare).  Otherwise workgroup 0
+// writes the next round's st (frontier size, M2L and P2P bases).
+__global__ void __launch_bounds__(kWalkThreads) k_walk_emit(const int2* __restrict__ F, const int* __restrict__ st,
+                                                            WalkCtx w, const uint8_t* __restrict__ action,
+                                                            const int* __restrict__ toff, int tstride,
+                                                            const int* __restrict__ coff, int cstride,
+                                                            const int* __restrict__ tot, WalkCaps cap,
+                                                            int2* __restrict__ Fnext, uint64_t* __restrict__ m2l,
+                                                            uint64_t* __restrict__ p2p, int* __restrict__ st_next,
+                                                            int* __restrict__ overflow) {
+    const int n = st[0], bm = st[1], bp = st[2];
+    const int nc = tot[0], am = tot[1], ap = tot[2];
+    const bool fits = nc <= cap.frontier && (int64_t)bm + am <= cap.m2l && (int64_t)bp + ap <= cap.p2p;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (fits) {
+            st_next[0] = nc;
+            st_next[1] = bm + am;
+            st_next[2] = bp + ap;
+        } else {
+            *overflow = 1;
+            st_next[0] = 0;
+            st_next[1] = bm;
+            st_next[2] = bp;
         }
-        oc += walk_nchild(a);
+    }
+    if (!fits) return;
+    const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
+    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int g = ch * kWalkThreads + threadIdx.x;
+        if (g * kWalkItems >= n) continue;
+        int oc = coff[ch] + toff[g];
+        int om = bm + coff[(size_t)cstride + ch] + toff[(size_t)tstride + g];
+        int op = bp + coff[2 * (size_t)cstride + ch] + toff[2 * (size_t)tstride + g];
+#pragma unroll
+        for (int i = 0; i < kWalkItems; ++i) {
+            const int k = g * kWalkItems + i;
+            if (k >= n) break;
+            const int s = F[k].x, t = F[k].y;
+            const uint8_t a = action[k];
+            int2* out = Fnext + oc;
+            switch (a) {
+                case A_M2L: m2l[om++] = pair_key(s, t); break;
+                case A_P2P: p2p[op++] = pair_key(s, t); break;
+                case A_SPLIT_S:
+                    for (int q = 0; q < 4; ++q) out[q] = make_int2(w.child0[s] + q, t);
+                    break;
+                case A_SPLIT_T:
+                    for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.child0[t] + q);
+                    break;
+                case A_SPLIT_SELF:
+                    for (int q = 0; q < 4; ++q)
+                        for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.child0[s] + q, w.child0[s] + r);
+                    break;
+                default: break;
+            }
+            oc += walk_nchild(a);
+        }
     }
 }
 
-void walk_round_scan(const int2* F, int n, const WalkCtx& w, uint8_t* action, int* toff, int* btot, int* boff,
-                     int* tot, hipStream_t s) {
-    if (n <= 0) return;
-    const int nthr = (n + kWalkItems - 1) / kWalkItems;
-    const int nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
-    k_walk_round_scan<<<nblk, kWalkThreads, 0, s>>>(F, n, w, action, toff, nblk * kWalkThreads, btot, nblk);
+WalkScratch walk_scratch_sizes(int n) {
+    WalkScratch z;
+    const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
+    z.chunks = nchunk > 0 ? nchunk : 1;
+    z.threads = z.chunks * kWalkThreads;
+    return z;
+}
+
+void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* toff, int tstride,
+                     int* ctot, int* coff, int cstride, int* tot, int grid, hipStream_t s) {
+    k_walk_classify<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, toff, tstride, ctot, cstride);
     SFMM_LAUNCH_CHECK();
-    k_walk_block_scan<<<3, 256, 0, s>>>(btot, nblk, boff, tot);
+    k_walk_chunk_scan<<<3, 256, 0, s>>>(st, ctot, cstride, coff, tot);
     SFMM_LAUNCH_CHECK();
 }
 
-void walk_round_emit(const int2* F, int n, const WalkCtx& w, const uint8_t* action, const int* toff,
-                     const int* boff, int2* Fnext, uint64_t* m2l, int m2l_base, uint64_t* p2p, int p2p_base,
-                     hipStream_t s) {
-    if (n <= 0) return;
-    const int nthr = (n + kWalkItems - 1) / kWalkItems;
-    const int nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
-    k_walk_round_emit<<<nblk, kWalkThreads, 0, s>>>(F, n, w, action, toff, nblk * kWalkThreads, boff, nblk, Fnext,
-                                                    m2l, m2l_base, p2p, p2p_base);
+void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* toff,
+                     int tstride, const int* coff, int cstride, const int* tot, const WalkCaps& cap, int2* Fnext,
+                     uint64_t* m2l, uint64_t* p2p, int* st_next, int* overflow, int grid, hipStream_t s) {
+    k_walk_emit<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, toff, tstride, coff, cstride, tot, cap, Fnext, m2l, p2p,
+                                             st_next, overflow);
     SFMM_LAUNCH_CHECK();
-}
-
-// sizes of the per-round scratch of walk_round_scan for n pairs
-void walk_round_sizes(int n, int* nthr_total, int* nblk) {
-    const int nthr = (n + kWalkItems - 1) / kWalkItems;
-    *nblk = (nthr + kWalkThreads - 1) / kWalkThreads;
-    *nthr_total = *nblk * kWalkThreads;
 }
 
 // ------------------------------------------------------------------ lists
@@ -436,16 +467,20 @@ __global__ void k_csr_offsets(const uint64_t* sorted, int np, int nbox, int* off
     off[b] = lo;
 }
 
-__global__ void k_pair_sources(const uint64_t* sorted, int np, int* src) {
+// source box of every entry, and (ent != nullptr) its target box
+__global__ void k_pair_sources(const uint64_t* sorted, int np, int* src, int* ent) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < np) src[k] = (int)(uint32_t)(sorted[k] & 0xffffffffULL);
+    if (k >= np) return;
+    const uint64_t v = sorted[k];
+    src[k] = (int)(uint32_t)(v & 0xffffffffULL);
+    if (ent) ent[k] = (int)(uint32_t)(v >> 32);
 }
 
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, hipStream_t s) {
+void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* ent, hipStream_t s) {
     k_csr_offsets<<<nblocks(nbox + 1, 256), 256, 0, s>>>(sorted, npairs, nbox, off);
     SFMM_LAUNCH_CHECK();
     if (npairs > 0) {
-        k_pair_sources<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, src);
+        k_pair_sources<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, src, ent);
         SFMM_LAUNCH_CHECK();
     }
 }

@@ -205,6 +205,38 @@ __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, 
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of each digit's row of the digit-major histogram (one
+// workgroup per digit, chunks of kScanTile with a running carry); dtot[d] =
+// the digit's total count.  The digit bases (scan of dtot) are added by the
+// scatter.
+__global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restrict__ hist, int nblk,
+                                                             int* __restrict__ offs, int* __restrict__ dtot) {
+    __shared__ int sh[kScanThreads / 64];
+    const int d = blockIdx.x;
+    const int* in = hist + (size_t)d * nblk;
+    int* out = offs + (size_t)d * nblk;
+    int carry = 0;
+    for (int c0 = 0; c0 < nblk; c0 += kScanTile) {
+        const int base = c0 + threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nblk ? in[base + k] : 0;
+            sum += v[k];
+        }
+        int tot;
+        int run = carry + block_excl_scan(sum, sh, &tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < nblk) out[base + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[d] = carry;
+}
+
 // Stable scatter of one tile.  The ranks give every key its position in the
 // tile sorted by digit (the tile's digit counts come from the histogram
 // pass: same tiles); the keys are staged there in LDS and then written out
@@ -212,7 +244,7 @@ __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, 
 // digit's run.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                            uint32_t* vout, int64_t n, int shift, int nblk,
-                                                           const int* offs, const int* hist) {
+                                                           const int* offs, const int* dtot, const int* hist) {
     __shared__ int gbase[256];  // global start of each digit's run of this tile
     __shared__ int lbase[256];  // start of each digit's run inside the tile
     __shared__ int run[256];    // keys of each digit placed so far
@@ -222,7 +254,10 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, 
     __shared__ uint32_t sv[kRsTile];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    gbase[t] = offs[t * nblk + blockIdx.x];
+    {
+        int all;
+        gbase[t] = offs[t * nblk + blockIdx.x] + block_excl_scan(dtot[t], wsum, &all);
+    }
     run[t] = 0;
     // exclusive scan of this tile's digit counts
     {
@@ -295,7 +330,7 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
     uint32_t* v2 = vals ? (uint32_t*)pool_alloc(sizeof(uint32_t) * n) : nullptr;
     int* hist = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
     int* offs = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
-    int* tot = (int*)pool_alloc(sizeof(int));
+    int* dtot = (int*)pool_alloc(sizeof(int) * 256);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     const int npass = (bits - begin_bit + 7) / 8;
@@ -304,8 +339,9 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
         const int shift = begin_bit + 8 * pass;
         k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, nblk, hist);
         SFMM_LAUNCH_CHECK();
-        scan_excl_i32(hist, offs, 256 * (int64_t)nblk, tot, s);
-        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, hist);
+        k_rs_rowscan<<<256, kScanThreads, 0, s>>>(hist, nblk, offs, dtot);
+        SFMM_LAUNCH_CHECK();
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot, hist);
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -319,7 +355,7 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
     if (v2) pool_free(v2);
     pool_free(hist);
     pool_free(offs);
-    pool_free(tot);
+    pool_free(dtot);
 }
 
 // ------------------------------------------------------------------ sum

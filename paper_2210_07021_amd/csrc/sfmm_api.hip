@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -129,7 +130,8 @@ struct sfmm_plan_impl {
     DVec<double> mult, local;
     DVec<float> multf;  // precision tier: FP32 A-blocks of the multipoles
     // per-pair order policies
-    DVec<int> m2l_ent;        // target box of every FMM-act entry
+    DVec<int> m2l_ent;        // target box of every FMM-act entry (per-pair order policies)
+    DVec<int> p2p_ent;        // target box of every direct-act entry (until the near-field split)
     DVec<float> mlp_w;        // order network (learned policy)
     DVec<float4> decay;       // per-box multipole decay features
     DVec<uint8_t> m2l_ord;    // order of every FMM act (last execute)
@@ -258,12 +260,132 @@ void build_tree(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
 
 // Stable sort on the target field only: within one target the pairs keep the
 // walk's (deterministic) emission order.
-void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, DVec<int>& src, hipStream_t s) {
+void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, DVec<int>& src, DVec<int>* ent,
+                       hipStream_t s) {
     off.resize((size_t)nbox + 1);
     src.resize(std::max(np, 1));
+    if (ent) ent->resize(std::max(np, 1));
     if (np > 0) radix_sort_u64(pairs.data(), nullptr, np, 32 + bits_for(nbox), s, 32);
-    pairs_to_csr(pairs.data(), np, nbox, off.data(), src.data(), s);
+    pairs_to_csr(pairs.data(), np, nbox, off.data(), src.data(), ent ? ent->data() : nullptr, s);
     SFMM_HIP(hipStreamSynchronize(s));
+}
+
+// Capacities of the queued walk, as multiples of the box count: the largest
+// needs seen so far in this process (x 1.25), at least the defaults.
+std::mutex g_walk_mu;
+double g_walk_ratio[3] = {24.0, 40.0, 40.0};  // frontier, M2L, P2P pairs per box
+
+constexpr int kWalkBatch = 8;        // rounds queued between two read-backs
+constexpr int kWalkMaxRounds = 64;   // a round raises level(S) + level(T): at most 2 x 29 + 1 rounds
+constexpr int kWalkGrid = 1024;      // workgroups of a queued round (each takes chunks in turn)
+
+// The frontier form of Algorithm 1.  Queued mode: rounds run back to back on
+// the device with fixed capacities, the host reading the frontier size every
+// kWalkBatch rounds; a round that would overflow ends the walk with
+// *overflow set.  Exact mode: the host reads each round's totals and grows
+// every buffer before the emit.  Both produce the same lists.
+bool walk(sfmm_plan_impl& P, const WalkCtx& w, bool exact, DVec<uint64_t>& m2l, DVec<uint64_t>& p2p, int* n_m2l,
+          int* n_p2p, hipStream_t s) {
+    // Algorithm 1 starts at INTERACTION(root, root): root is not a leaf and
+    // equals itself, so the first round is every pair of its 12 children
+    std::vector<int2> f0;
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) f0.push_back(make_int2(i, j));
+    const int n0 = (int)f0.size();
+    // SFMM_WALK_RATIO (pairs per box, all three capacities, no lower bound)
+    // overrides the capacities: tests use it to drive the overflow path
+    const char* forced = std::getenv("SFMM_WALK_RATIO");
+    WalkCaps cap;
+    {
+        std::lock_guard<std::mutex> lk(g_walk_mu);
+        const double lo = forced ? 1.0 : 65536.0;
+        auto c = [&](double r) { return (int)std::min(2.0e9, std::max(lo, r * P.nbox)); };
+        const double f = forced ? std::atof(forced) : 0.0;
+        cap.frontier = exact ? n0 : c(forced ? f : g_walk_ratio[0]);
+        cap.m2l = exact ? 1 : c(forced ? f : g_walk_ratio[1]);
+        cap.p2p = exact ? 1 : c(forced ? f : g_walk_ratio[2]);
+    }
+    DVec<int2> F, G;
+    F.resize(std::max(cap.frontier, n0));
+    G.resize(cap.frontier);
+    m2l.resize(cap.m2l);
+    p2p.resize(cap.p2p);
+    DVec<uint8_t> action;
+    DVec<int> toff, ctot, coff, tot, rs;
+    tot.resize(3);
+    rs.resize(4 * (kWalkMaxRounds + 1) + 1);
+    int* overflow = rs.data() + 4 * (kWalkMaxRounds + 1);
+    fill_i32(rs.data(), 4 * (kWalkMaxRounds + 1) + 1, 0, s);
+    const int st0[3] = {n0, 0, 0};
+    SFMM_HIP(hipMemcpyAsync(rs.data(), st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    SFMM_HIP(hipMemcpyAsync(F.data(), f0.data(), f0.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    int n = n0, rounds = 0;
+    WalkScratch z = walk_scratch_sizes(exact ? n0 : cap.frontier);
+    action.resize(exact ? n0 : cap.frontier);
+    toff.resize(3 * (size_t)z.threads);
+    ctot.resize(3 * (size_t)z.chunks);
+    coff.resize(3 * (size_t)z.chunks);
+    for (int r = 0; r < kWalkMaxRounds; ++r) {
+        const int* st = rs.data() + 4 * r;
+        int* st_next = rs.data() + 4 * (r + 1);
+        if (exact) {
+            z = walk_scratch_sizes(n);
+            action.resize(std::max(n, 1));
+            toff.resize(3 * (size_t)z.threads);
+            ctot.resize(3 * (size_t)z.chunks);
+            coff.resize(3 * (size_t)z.chunks);
+            const int grid = std::min(kWalkGrid, z.chunks);
+            walk_round_scan(F.data(), st, w, action.data(), toff.data(), z.threads, ctot.data(), coff.data(),
+                            z.chunks, tot.data(), grid, s);
+            SFMM_HIP(hipMemcpyAsync(P.pin->p, tot.data(), 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+            SFMM_HIP(hipMemcpyAsync(P.pin->p + 3, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+            SFMM_HIP(hipStreamSynchronize(s));
+            const int nc = P.pin->p[0], am = P.pin->p[1], ap = P.pin->p[2];
+            const int64_t em = (int64_t)P.pin->p[4] + am, ep = (int64_t)P.pin->p[5] + ap;
+            if (em > 0x7fffffff || ep > 0x7fffffff) throw Error(ST_INVALID_ARG, "interaction lists too large");
+            m2l.grow((size_t)std::max<int64_t>(em, 1), s);
+            p2p.grow((size_t)std::max<int64_t>(ep, 1), s);
+            G.resize(std::max(nc, 1));
+            cap.frontier = std::max(nc, 1);
+            cap.m2l = (int)m2l.n;
+            cap.p2p = (int)p2p.n;
+            walk_round_emit(F.data(), st, w, action.data(), toff.data(), z.threads, coff.data(), z.chunks, tot.data(),
+                            cap, G.data(), m2l.data(), p2p.data(), st_next, overflow, grid, s);
+            n = nc;
+        } else {
+            walk_round_scan(F.data(), st, w, action.data(), toff.data(), z.threads, ctot.data(), coff.data(),
+                            z.chunks, tot.data(), kWalkGrid, s);
+            walk_round_emit(F.data(), st, w, action.data(), toff.data(), z.threads, coff.data(), z.chunks, tot.data(),
+                            cap, G.data(), m2l.data(), p2p.data(), st_next, overflow, kWalkGrid, s);
+            if ((r + 1) % kWalkBatch == 0) {
+                SFMM_HIP(hipMemcpyAsync(P.pin->p, st_next, sizeof(int), hipMemcpyDeviceToHost, s));
+                SFMM_HIP(hipStreamSynchronize(s));
+                n = P.pin->p[0];
+            }
+        }
+        std::swap(F.p, G.p);
+        std::swap(F.n, G.n);
+        std::swap(F.cap, G.cap);
+        rounds = r + 1;
+        if (n == 0) break;
+    }
+    std::vector<int> h(4 * (kWalkMaxRounds + 1) + 1);
+    SFMM_HIP(hipMemcpyAsync(h.data(), rs.data(), h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    if (h.back()) return false;  // overflow: the lists are incomplete
+    if (h[4 * rounds] != 0) throw Error(ST_INTERNAL, "the interaction walk did not end");
+    *n_m2l = h[4 * rounds + 1];
+    *n_p2p = h[4 * rounds + 2];
+    int fmax = 0;
+    for (int r = 0; r <= rounds; ++r) fmax = std::max(fmax, h[4 * r]);
+    if (!forced) {
+        std::lock_guard<std::mutex> lk(g_walk_mu);
+        const double nb = std::max(1, P.nbox);
+        g_walk_ratio[0] = std::max(g_walk_ratio[0], 1.25 * fmax / nb);
+        g_walk_ratio[1] = std::max(g_walk_ratio[1], 1.25 * *n_m2l / nb);
+        g_walk_ratio[2] = std::max(g_walk_ratio[2], 1.25 * *n_p2p / nb);
+    }
+    return true;
 }
 
 void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
@@ -276,52 +398,21 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     w.gdd = P.gdd.data();
     w.c_s = P.opt.c_s;
     w.c_t = P.opt.c_t;
-    // Algorithm 1 starts at INTERACTION(root, root): root is not a leaf and
-    // equals itself, so the first round is every pair of its 12 children
-    std::vector<int2> f0;
-    for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j) f0.push_back(make_int2(i, j));
-    DVec<int2> F, G;
-    F.resize(f0.size());
-    SFMM_HIP(hipMemcpyAsync(F.data(), f0.data(), f0.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    DVec<uint8_t> action;
-    DVec<int> toff, btot, boff, tots;
-    tots.resize(3);
     DVec<uint64_t> m2l, p2p;
-    int n = (int)f0.size(), n_m2l = 0, n_p2p = 0;
-    while (n > 0) {
-        int nthr, nblk;
-        walk_round_sizes(n, &nthr, &nblk);
-        action.resize(n);
-        toff.resize(3 * (size_t)nthr);
-        btot.resize(3 * (size_t)nblk);
-        boff.resize(3 * (size_t)nblk);
-        walk_round_scan(F.data(), n, w, action.data(), toff.data(), btot.data(), boff.data(), tots.data(), s);
-        SFMM_HIP(hipMemcpyAsync(P.pin->p, tots.data(), 3 * sizeof(int), hipMemcpyDeviceToHost, s));
-        SFMM_HIP(hipStreamSynchronize(s));
-        const int nc = P.pin->p[0], am = P.pin->p[1], ap = P.pin->p[2];
-        if ((int64_t)n_m2l + am > 0x7fffffff || (int64_t)n_p2p + ap > 0x7fffffff)
-            throw Error(ST_INVALID_ARG, "interaction lists too large");
-        m2l.grow((size_t)n_m2l + am, s);
-        p2p.grow((size_t)n_p2p + ap, s);
-        G.resize(std::max(nc, 1));
-        walk_round_emit(F.data(), n, w, action.data(), toff.data(), boff.data(), G.data(), m2l.data(), n_m2l,
-                        p2p.data(), n_p2p, s);
-        n_m2l += am;
-        n_p2p += ap;
-        std::swap(F.p, G.p);
-        std::swap(F.n, G.n);
-        std::swap(F.cap, G.cap);
-        n = nc;
-    }
+    int n_m2l = 0, n_p2p = 0;
+    if (!walk(P, w, false, m2l, p2p, &n_m2l, &n_p2p, s) && !walk(P, w, true, m2l, p2p, &n_m2l, &n_p2p, s))
+        throw Error(ST_INTERNAL, "the interaction walk overflowed its exactly sized buffers");
     prof.end(stage_walk);
     StageScope st(prof, S_LISTS);
     P.n_m2l = n_m2l;
     P.n_p2p = n_p2p;
     m2l.grow(std::max(n_m2l, 1), s);
     p2p.grow(std::max(n_p2p, 1), s);
-    sort_pairs_to_csr(m2l, n_m2l, P.nbox, P.m2l_off, P.m2l_src, s);
-    sort_pairs_to_csr(p2p, n_p2p, P.nbox, P.p2p_off, P.p2p_src, s);
+    // target box of every entry: the per-pair order policies need it for the
+    // FMM acts, the near-field split for the direct acts
+    const bool ent = P.opt.order_policy != SFMM_ORDER_FIXED;
+    sort_pairs_to_csr(m2l, n_m2l, P.nbox, P.m2l_off, P.m2l_src, ent ? &P.m2l_ent : nullptr, s);
+    sort_pairs_to_csr(p2p, n_p2p, P.nbox, P.p2p_off, P.p2p_src, &P.p2p_ent, s);
     // M2L work order: target boxes with the longest lists first, so the lanes
     // of a wave carry similar work
     DVec<uint64_t> k;
@@ -359,8 +450,9 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     fill_i32(P.tcount.data(), P.nbox, 0, s);
     locate_targets(P.tkeys.data(), P.M, P.child0.data(), P.level.data(), P.tleaf.data(), s);
     target_ranges(P.tleaf.data(), P.M, P.tfirst.data(), P.tcount.data(), s);
-    near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.nbox, P.n_p2p, P.tfirst.data(), P.tcount.data(),
-               P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
+    near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.p2p_ent.data(), P.nbox, P.n_p2p, P.tfirst.data(),
+               P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
+    P.p2p_ent.reset();  // stream-ordered pool: later work on this stream may reuse it
     const int segn = P.opt.near_segment > 0 ? P.opt.near_segment : kSegNear;
     const int segf = P.opt.far_segment > 0 ? P.opt.far_segment : kSegFar;
     build_items(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), P.tcount.data(), P.nbox, segn,
@@ -493,10 +585,6 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         {
             StageScope st(prof, S_TGT);
             build_targets(*P, tgt, s);
-        }
-        if (o.order_policy != SFMM_ORDER_FIXED && P->n_m2l > 0) {
-            P->m2l_ent.resize(P->n_m2l);
-            entry_box(P->m2l_off.data(), P->nbox, P->n_m2l, P->m2l_ent.data(), s);
         }
         if (o.order_policy == SFMM_ORDER_LEARNED) {
             P->mlp_w.resize(kMlpWeights);

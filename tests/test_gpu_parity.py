@@ -244,3 +244,28 @@ def test_bitwise_reproducible(oracle_lib):
     assert torch.equal(a1, a3) and torch.equal(b1, b3)
     p1.close()
     p2.close()
+
+
+@pytest.mark.parametrize("ratio", ["0.05", "3"])
+def test_walk_overflow_reruns_exactly(ratio, monkeypatch, oracle_lib):
+    """The queued walk with capacities too small for its lists (SFMM_WALK_RATIO
+    pairs per box) overflows and reruns with exact sizing: same lists and
+    bit-identical results as a plan with the default capacities."""
+    import torch
+    src, q, tgt = skies.workload("clustered-1e6", scale=0.02)
+    tgt = tgt[:, ::11].copy()
+    sf = _sf()
+    _say(f"[walk overflow] ratio {ratio}: N={src.shape[1]} M={tgt.shape[1]}")
+    ref = sf.Plan(src, q, tgt, tolerance=1e-8)
+    a1, b1 = ref.execute()
+    m1, p1 = ref.export_lists()
+    monkeypatch.setenv("SFMM_WALK_RATIO", ratio)
+    plan = sf.Plan(src, q, tgt, tolerance=1e-8)
+    monkeypatch.delenv("SFMM_WALK_RATIO")
+    a2, b2 = plan.execute()
+    m2, p2 = plan.export_lists()
+    torch.cuda.synchronize()
+    assert np.array_equal(m1, m2) and np.array_equal(p1, p2)
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+    ref.close()
+    plan.close()

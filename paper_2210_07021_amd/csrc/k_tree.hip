@@ -141,11 +141,80 @@ __global__ void k_make_children(int b0, int nb, int child_base, const int* flag,
     }
 }
 
+// First index in [lo, hi) whose key is >= v (hi when none), found by the 64
+// lanes of a wave together: each step tests 64 evenly spaced keys of the
+// range and keeps the gap where the predicate turns true, so a range of n
+// keys takes about log(n) / log(65) dependent loads.  Every lane returns the
+// same index (the loop is uniform across the wave).
+__device__ int wave_lower_bound_u64(const uint64_t* __restrict__ a, int lo, int hi, uint64_t v) {
+    const int lane = threadIdx.x & 63;
+    while (hi > lo) {
+        const int n = hi - lo;
+        if (n <= 64) {
+            const bool p = lane < n && a[lo + lane] >= v;
+            const uint64_t m = __ballot(p);
+            return m ? lo + (int)__ffsll((unsigned long long)m) - 1 : hi;
+        }
+        const int q = lo + (int)(((int64_t)(lane + 1) * n) / 65);  // in [lo, hi)
+        const uint64_t m = __ballot(a[q] >= v);
+        const int j = m ? (int)__ffsll((unsigned long long)m) - 1 : 64;
+        const int qprev = j > 0 ? __shfl(q, j - 1, 64) : lo - 1;
+        const int qj = j < 64 ? __shfl(q, j, 64) : hi;
+        lo = qprev + 1;
+        hi = qj;
+    }
+    return lo;
+}
+
+// k_make_children with one wave per box (levels of few, large boxes)
+__global__ void k_make_children_wave(int b0, int nb, int child_base, const int* flag, const int* off,
+                                     const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                                     int* parent, int* child0) {
+    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nb) return;  // uniform across the wave
+    const int b = b0 + i;
+    if (!flag[i]) {
+        if (lane == 0) child0[b] = -1;
+        return;
+    }
+    const int c0 = child_base + 4 * off[i];
+    const int L = level[b] + 1;
+    const int shift = 2 * (kOrder - L);
+    const int end = first[b] + count[b];
+    int lo = first[b];
+    int e[4];
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t pix = pixel[b] * 4 + (uint64_t)c;
+        e[c] = wave_lower_bound_u64(keys, lo, end, (pix + 1) << shift);
+        lo = e[c];
+    }
+    e[3] = end;
+    if (lane < 4) {
+        const int c = lane;
+        const int st = c == 0 ? first[b] : e[c - 1];
+        level[c0 + c] = L;
+        pixel[c0 + c] = pixel[b] * 4 + (uint64_t)c;
+        first[c0 + c] = st;
+        count[c0 + c] = e[c] - st;
+        parent[c0 + c] = b;
+        child0[c0 + c] = -1;
+    }
+    if (lane == 0) child0[b] = c0;
+}
+
 void tree_make_children(int b0, int nb, int child_base, const int* flag, const int* off, const uint64_t* keys,
                         int* level, uint64_t* pixel, int* first, int* count, int* parent, int* child0,
                         hipStream_t s) {
-    k_make_children<<<nblocks(nb, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys, level, pixel, first,
-                                                    count, parent, child0);
+    if (nb <= 0) return;
+    if (nb < 65536) {
+        k_make_children_wave<<<nblocks((int64_t)nb * 64, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys,
+                                                                           level, pixel, first, count, parent,
+                                                                           child0);
+    } else {
+        k_make_children<<<nblocks(nb, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys, level, pixel, first,
+                                                        count, parent, child0);
+    }
     SFMM_LAUNCH_CHECK();
 }
 

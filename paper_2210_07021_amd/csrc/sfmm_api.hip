@@ -277,7 +277,7 @@ double g_walk_ratio[3] = {24.0, 40.0, 40.0};  // frontier, M2L, P2P pairs per bo
 
 constexpr int kWalkBatch = 8;        // rounds queued between two read-backs
 constexpr int kWalkMaxRounds = 64;   // a round raises level(S) + level(T): at most 2 x 29 + 1 rounds
-constexpr int kWalkGrid = 1024;      // workgroups of a queued round (each takes chunks in turn)
+constexpr int kWalkGrid = 8192;      // workgroups of a queued round (each takes chunks in turn)
 
 // The frontier form of Algorithm 1.  Queued mode: rounds run back to back on
 // the device with fixed capacities, the host reading the frontier size every

@@ -138,11 +138,18 @@ void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t
 struct WalkCtx {
     const int* child0;
     const int* count;
-    const double* cen;
-    const double* rad;
-    const double* gdd;
+    const double4* geo;    // [nb] FP64 centre x, y, z and radius R
+    const double2* strig;  // [nb] cos, sin of c_s R
+    const double4* ttrig;  // [nb] cos, sin of R and of R / c_t
+    const int2* cc;        // [nb] child0, count
+    const double* gdd;     // [nb][8] double-double centre and radius
+    const double* dtrig;   // [nb][12] double-double cos, sin of c_s R, R, R / c_t
     double c_s, c_t;
 };
+// the walk's per-box records (geo, cc) from the box table
+void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
+                double c_s, double c_t, double4* geo, double2* strig, double4* ttrig, int2* cc, double* dtrig,
+                hipStream_t s);
 // M2L order: boxes of levels <= lc first, then the others; longest list
 // first within each part (16-bit keys, ties in table order)
 // One walk round in three launches (classify + per-chunk scans, scan of the

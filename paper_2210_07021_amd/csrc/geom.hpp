@@ -249,6 +249,66 @@ SFMM_HD BoxGeomDD box_geometry(int level, uint64_t pix) {
 // "B_T is far from B_S" (Sec. 3.5): d - R_T - c_s R_S > 0 and R_T < c_t d,
 // each by more than the relative tie guard.  FP64 first; double-double when
 // either margin is within kMacFilter of zero.
+// The FP64 filter of mac_far (+1 far, -1 not far, 0 undecided: the
+// double-double test decides), without an angle: for a threshold X in [0, 3), d > X
+// exactly when sin(d - X) = |c_S x c_T| cos X - (c_S . c_T) sin X > 0 (d - X
+// lies in (-pi, pi]), and |sin(d - X)| <= |d - X|, so a value beyond
+// kMacFilter settles the sign of d - X as a margin of d would.  The two
+// thresholds are X1 = R_T + c_s R_S and X2 = R_T / c_t; st = (cos, sin) of
+// c_s R_S, tt = (cos, sin) of R_T and of R_T / c_t, from the FP64 radii.
+// The FP64 error of either value is below 1e-14.  X >= 3 is left undecided
+// (coarse boxes, few pairs) unless it exceeds pi, where the pair cannot be
+// far.
+SFMM_HD int mac_far_filter_trig(double csx, double csy, double csz, double ctx, double cty, double ctz, double rs,
+                                double rt, double2 st, double4 tt, double c_s, double c_t) {
+    const double x1 = rt + c_s * rs, x2 = rt / c_t;
+    if (x1 > 3.14159265359 || x2 > 3.14159265359) return -1;  // beyond pi + 2e-12
+    if (x1 >= 3.0 || x2 >= 3.0) return 0;
+    const double cx = csy * ctz - csz * cty, cy = csz * ctx - csx * ctz, cz = csx * cty - csy * ctx;
+    const double sn = sqrt(cx * cx + cy * cy + cz * cz), cs = csx * ctx + csy * cty + csz * ctz;
+    const double cx1 = tt.x * st.x - tt.y * st.y, sx1 = tt.y * st.x + tt.x * st.y;
+    const double v1 = sn * cx1 - cs * sx1;
+    const double v2 = sn * tt.z - cs * tt.w;
+    if (v1 < -kMacFilter || v2 < -kMacFilter) return -1;
+    if (v1 > kMacFilter && v2 > kMacFilter) return 1;
+    return 0;
+}
+
+// The exact decision of a near-tie: mac_far_filter_trig's test in
+// double-double, v1 = sin(d - X1), v2 = sin(d - X2) from the double-double
+// centres and the boxes' double-double cos / sin tables (ts: c_s R_S; tt:
+// R_T, then R_T / c_t; cos before sin), far when both exceed kTieAbs.  The
+// double-double errors stay below 1e-30 and a margin that is not an exact
+// tie is far above 1e-20 at every depth, so exact ties come out not far, as
+// the strict inequalities of the MAC say.  X >= pi: the pair cannot be far.
+constexpr double kTieAbs = 1e-20;
+SFMM_HD bool mac_far_dd_trig(const dd* cs, const dd* ct, dd rs, dd rt, const dd* ts, const dd* tt, double c_s,
+                             double c_t) {
+    const dd pi = dd_mul_d(dd_half_pi(), 2.0);
+    const dd x1 = dd_add(rt, dd_mul_d(rs, c_s));
+    const dd x2 = dd_div(rt, dd_from(c_t));
+    if (!dd_lt(x1, pi) || !dd_lt(x2, pi)) return false;
+    const dd cx = dd_sub(dd_mul(cs[1], ct[2]), dd_mul(cs[2], ct[1]));
+    const dd cy = dd_sub(dd_mul(cs[2], ct[0]), dd_mul(cs[0], ct[2]));
+    const dd cz = dd_sub(dd_mul(cs[0], ct[1]), dd_mul(cs[1], ct[0]));
+    const dd sn = dd_sqrt(dd_add(dd_add(dd_mul(cx, cx), dd_mul(cy, cy)), dd_mul(cz, cz)));
+    const dd c = dd_add(dd_add(dd_mul(cs[0], ct[0]), dd_mul(cs[1], ct[1])), dd_mul(cs[2], ct[2]));
+    const dd cx1 = dd_sub(dd_mul(tt[0], ts[0]), dd_mul(tt[1], ts[1]));
+    const dd sx1 = dd_add(dd_mul(tt[1], ts[0]), dd_mul(tt[0], ts[1]));
+    const dd v1 = dd_sub(dd_sub(dd_mul(sn, cx1), dd_mul(c, sx1)), dd_from(kTieAbs));
+    const dd v2 = dd_sub(dd_sub(dd_mul(sn, tt[2]), dd_mul(c, tt[3])), dd_from(kTieAbs));
+    return v1.hi > 0.0 && v2.hi > 0.0;
+}
+
+// The double-double test of mac_far alone.
+SFMM_HD bool mac_far_dd(const dd* cs_dd, const dd* ct_dd, dd rs_dd, dd rt_dd, double c_s, double c_t) {
+    const dd D = angdist_dd(cs_dd, ct_dd);
+    const dd guard = dd_mul_d(D, kTieRel);
+    const dd M1 = dd_sub(dd_sub(dd_sub(D, rt_dd), dd_mul_d(rs_dd, c_s)), guard);
+    const dd M2 = dd_sub(dd_sub(dd_mul_d(D, c_t), rt_dd), guard);
+    return M1.hi > 0.0 && M2.hi > 0.0;
+}
+
 SFMM_HD bool mac_far(const double* cs, const double* ct, double rs, double rt,
                      const dd* cs_dd, const dd* ct_dd, dd rs_dd, dd rt_dd,
                      double c_s, double c_t) {

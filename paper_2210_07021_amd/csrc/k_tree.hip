@@ -243,6 +243,43 @@ void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen, 
     SFMM_LAUNCH_CHECK();
 }
 
+__global__ void k_walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0,
+                             const int* count, double c_s, double c_t, double4* geo, double2* strig, double4* ttrig,
+                             int2* cc, double* dtrig) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double r = rad[b];
+    geo[b] = make_double4(cen[4 * b], cen[4 * b + 1], cen[4 * b + 2], r);
+    double s1, c1, s2, c2, s3, c3;
+    sincos(c_s * r, &s1, &c1);
+    sincos(r, &s2, &c2);
+    sincos(r / c_t, &s3, &c3);
+    strig[b] = make_double2(c1, s1);
+    ttrig[b] = make_double4(c2, s2, c3, s3);
+    cc[b] = make_int2(child0[b], count[b]);
+    // double-double tables for the exact decisions of near-ties
+    const dd R = {gdd[8 * (size_t)b + 6], gdd[8 * (size_t)b + 7]};
+    const dd ang[3] = {dd_mul_d(R, c_s), R, dd_div(R, dd_from(c_t))};
+    double* o = dtrig + 12 * (size_t)b;
+    for (int k = 0; k < 3; ++k) {
+        dd sn, cs;
+        dd_sincos(ang[k], &sn, &cs);
+        o[4 * k + 0] = cs.hi;
+        o[4 * k + 1] = cs.lo;
+        o[4 * k + 2] = sn.hi;
+        o[4 * k + 3] = sn.lo;
+    }
+}
+
+void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
+                double c_s, double c_t, double4* geo, double2* strig, double4* ttrig, int2* cc, double* dtrig,
+                hipStream_t s) {
+    if (nb <= 0) return;
+    k_walk_boxes<<<nblocks(nb, 128), 128, 0, s>>>(nb, cen, rad, gdd, child0, count, c_s, c_t, geo, strig, ttrig, cc,
+                                                  dtrig);
+    SFMM_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ targets
 __global__ void k_locate(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -306,16 +343,6 @@ void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t
 // leaf, so no recursion is lost) and is dropped.
 enum : uint8_t { A_NONE = 0, A_M2L = 1, A_P2P = 2, A_SPLIT_S = 3, A_SPLIT_T = 4, A_SPLIT_SELF = 5 };
 
-__device__ bool box_far(const WalkCtx& w, int s, int t) {
-    const double* gs = w.gdd + 8 * s;
-    const double* gt = w.gdd + 8 * t;
-    const double cs[3] = {gs[0], gs[2], gs[4]};
-    const double ct[3] = {gt[0], gt[2], gt[4]};
-    const dd csd[3] = {{gs[0], gs[1]}, {gs[2], gs[3]}, {gs[4], gs[5]}};
-    const dd ctd[3] = {{gt[0], gt[1]}, {gt[2], gt[3]}, {gt[4], gt[5]}};
-    return mac_far(cs, ct, gs[6], gt[6], csd, ctd, dd{gs[6], gs[7]}, dd{gt[6], gt[7]}, w.c_s, w.c_t);
-}
-
 // One round of the walk in three launches, sized on the device: the round's
 // frontier size and output bases sit in st[0..2] (written by the previous
 // round's emit), so rounds can be queued without reading anything back.  The
@@ -328,41 +355,104 @@ __device__ bool box_far(const WalkCtx& w, int s, int t) {
 // pairs).
 constexpr int kWalkItems = 4, kWalkThreads = 256, kWalkChunk = kWalkItems * kWalkThreads;
 
-__device__ __forceinline__ uint8_t walk_action(const WalkCtx& w, int s, int t) {
-    if (w.count[s] == 0) return A_NONE;
-    if (s == t) return (w.child0[s] < 0) ? A_P2P : A_SPLIT_SELF;
-    if (box_far(w, s, t)) return A_M2L;
-    const bool sl = w.child0[s] < 0, tl = w.child0[t] < 0;
+__device__ __forceinline__ int walk_nchild(uint8_t a) {
+    return (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
+}
+
+// walk_action with the FP64 filters only: A_TIE where a double-double
+// decision is needed (a MAC margin or a radius difference near zero)
+constexpr uint8_t A_TIE = 7;
+__device__ __forceinline__ uint8_t walk_action_fast(const WalkCtx& w, int s, int t) {
+    const int2 bs = w.cc[s];
+    if (bs.y == 0) return A_NONE;
+    if (s == t) return (bs.x < 0) ? A_P2P : A_SPLIT_SELF;
+    const int2 bt = w.cc[t];
+    const double4 gs = w.geo[s], gt = w.geo[t];
+    const double rs = gs.w, rt = gt.w;
+    const int f = mac_far_filter_trig(gs.x, gs.y, gs.z, gt.x, gt.y, gt.z, rs, rt, w.strig[s], w.ttrig[t], w.c_s,
+                                      w.c_t);
+    if (f > 0) return A_M2L;
+    if (f == 0) return A_TIE;
+    const bool sl = bs.x < 0, tl = bt.x < 0;
     if (!sl && !tl) {
-        const double* gs = w.gdd + 8 * s;
-        const double* gt = w.gdd + 8 * t;
-        return radius_greater(gs[6], gt[6], dd{gs[6], gs[7]}, dd{gt[6], gt[7]}) ? A_SPLIT_S : A_SPLIT_T;
+        const double diff = rs - rt;
+        if (!(fabs(diff) > 1e-13 * (rs + rt))) return A_TIE;
+        return diff > 0.0 ? A_SPLIT_S : A_SPLIT_T;
     }
     if (!sl) return A_SPLIT_S;
     if (!tl) return A_SPLIT_T;
     return A_P2P;
 }
 
-__device__ __forceinline__ int walk_nchild(uint8_t a) {
-    return (a == A_SPLIT_S || a == A_SPLIT_T) ? 4 : (a == A_SPLIT_SELF ? 16 : 0);
+// walk_action_fast's A_TIE cases decided exactly (double-double)
+__device__ uint8_t walk_action_tie(const WalkCtx& w, int s, int t) {
+    const int2 bs = w.cc[s], bt = w.cc[t];
+    const double4 gs4 = w.geo[s], gt4 = w.geo[t];
+    const double* a = w.gdd + 8 * (size_t)s;
+    const double* b = w.gdd + 8 * (size_t)t;
+    int f = mac_far_filter_trig(gs4.x, gs4.y, gs4.z, gt4.x, gt4.y, gt4.z, gs4.w, gt4.w, w.strig[s], w.ttrig[t],
+                                w.c_s, w.c_t);
+    if (f == 0) {
+        const dd csd[3] = {{a[0], a[1]}, {a[2], a[3]}, {a[4], a[5]}};
+        const dd ctd[3] = {{b[0], b[1]}, {b[2], b[3]}, {b[4], b[5]}};
+        const double* ta = w.dtrig + 12 * (size_t)s;
+        const double* tb = w.dtrig + 12 * (size_t)t;
+        const dd ts[2] = {{ta[0], ta[1]}, {ta[2], ta[3]}};
+        const dd tt[4] = {{tb[4], tb[5]}, {tb[6], tb[7]}, {tb[8], tb[9]}, {tb[10], tb[11]}};
+        f = mac_far_dd_trig(csd, ctd, dd{a[6], a[7]}, dd{b[6], b[7]}, ts, tt, w.c_s, w.c_t) ? 1 : -1;
+    }
+    if (f > 0) return A_M2L;
+    const bool sl = bs.x < 0, tl = bt.x < 0;
+    if (!sl && !tl) return radius_greater(a[6], b[6], dd{a[6], a[7]}, dd{b[6], b[7]}) ? A_SPLIT_S : A_SPLIT_T;
+    if (!sl) return A_SPLIT_S;
+    if (!tl) return A_SPLIT_T;
+    return A_P2P;
 }
 
+// Classification of each chunk: FP64 decisions first; the near-ties of the
+// chunk are gathered in LDS and decided exactly by consecutive threads (no
+// wave runs that code for one lane); then the three counts of every thread
+// (children pairs, M2L pairs, P2P pairs) are scanned across the workgroup:
+// toff per thread, ctot per chunk.
 __global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __restrict__ F, const int* __restrict__ st,
                                                                 WalkCtx w, uint8_t* __restrict__ action,
                                                                 int* __restrict__ toff, int tstride,
                                                                 int* __restrict__ ctot, int cstride) {
     __shared__ int sh[3][kWalkThreads / 64];
+    __shared__ int ntie;
+    __shared__ short tie_at[kWalkChunk];
+    __shared__ uint8_t tie_act[kWalkChunk];
     const int n = st[0];
     const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
         const int g = ch * kWalkThreads + threadIdx.x;
+        if (threadIdx.x == 0) ntie = 0;
+        __syncthreads();
+        uint8_t act[kWalkItems];
+#pragma unroll
+        for (int i = 0; i < kWalkItems; ++i) {
+            const int k = g * kWalkItems + i;
+            act[i] = A_NONE;
+            if (k < n) {
+                const int2 f = F[k];
+                act[i] = walk_action_fast(w, f.x, f.y);
+                if (act[i] == A_TIE) tie_at[atomicAdd(&ntie, 1)] = (short)(threadIdx.x * kWalkItems + i);
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < ntie; j += kWalkThreads) {
+            const int li = tie_at[j];
+            const int2 f = F[ch * kWalkChunk + li];
+            tie_act[li] = walk_action_tie(w, f.x, f.y);
+        }
+        __syncthreads();
         int c[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < kWalkItems; ++i) {
             const int k = g * kWalkItems + i;
             if (k < n) {
-                const uint8_t a = walk_action(w, F[k].x, F[k].y);
+                const uint8_t a = act[i] == A_TIE ? tie_act[threadIdx.x * kWalkItems + i] : act[i];
                 action[k] = a;
                 c[0] += walk_nchild(a);
                 c[1] += a == A_M2L;
@@ -392,7 +482,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __re
             toff[(size_t)j * tstride + g] = before + c[j];
             if (threadIdx.x == 0) ctot[(size_t)j * cstride + ch] = all;
         }
-        __syncthreads();  // sh is rewritten by the next chunk
+        __syncthreads();  // sh, ntie and the tie lists are reused by the next chunk
     }
 }
 
@@ -481,14 +571,14 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_emit(const int2* __restri
                 case A_M2L: m2l[om++] = pair_key(s, t); break;
                 case A_P2P: p2p[op++] = pair_key(s, t); break;
                 case A_SPLIT_S:
-                    for (int q = 0; q < 4; ++q) out[q] = make_int2(w.child0[s] + q, t);
+                    for (int q = 0; q < 4; ++q) out[q] = make_int2(w.cc[s].x + q, t);
                     break;
                 case A_SPLIT_T:
-                    for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.child0[t] + q);
+                    for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.cc[t].x + q);
                     break;
                 case A_SPLIT_SELF:
                     for (int q = 0; q < 4; ++q)
-                        for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.child0[s] + q, w.child0[s] + r);
+                        for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.cc[s].x + q, w.cc[s].x + r);
                     break;
                 default: break;
             }

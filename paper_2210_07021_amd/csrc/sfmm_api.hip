@@ -390,12 +390,26 @@ bool walk(sfmm_plan_impl& P, const WalkCtx& w, bool exact, DVec<uint64_t>& m2l, 
 
 void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     const int stage_walk = prof.begin(S_WALK);
+    DVec<double4> geo, ttrig;
+    DVec<double2> strig;
+    DVec<int2> cc;
+    DVec<double> dtrig;
+    geo.resize(std::max(P.nbox, 1));
+    strig.resize(std::max(P.nbox, 1));
+    ttrig.resize(std::max(P.nbox, 1));
+    cc.resize(std::max(P.nbox, 1));
+    dtrig.resize(12 * (size_t)std::max(P.nbox, 1));
+    walk_boxes(P.nbox, P.cen.data(), P.rad.data(), P.gdd.data(), P.child0.data(), P.count.data(), P.opt.c_s,
+               P.opt.c_t, geo.data(), strig.data(), ttrig.data(), cc.data(), dtrig.data(), s);
     WalkCtx w;
     w.child0 = P.child0.data();
     w.count = P.count.data();
-    w.cen = P.cen.data();
-    w.rad = P.rad.data();
+    w.geo = geo.data();
+    w.strig = strig.data();
+    w.ttrig = ttrig.data();
+    w.cc = cc.data();
     w.gdd = P.gdd.data();
+    w.dtrig = dtrig.data();
     w.c_s = P.opt.c_s;
     w.c_t = P.opt.c_t;
     DVec<uint64_t> m2l, p2p;

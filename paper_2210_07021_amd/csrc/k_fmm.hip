@@ -16,11 +16,17 @@ __device__ __forceinline__ Frame box_frame(const double* cen, int b, double* rho
     return make_frame(c[0], c[1], c[2]);
 }
 
-// Lemma 1 on every non-empty leaf
+// Lemma 1 on every leaf (an empty leaf gets a zero record: with the split
+// boxes written by k_m2m, every record is written and needs no clearing)
 template <int P>
 __global__ void __launch_bounds__(128) k_p2m(FmmCtx c, int nb) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb || c.child0[b] >= 0 || c.count[b] == 0) return;
+    if (b >= nb || c.child0[b] >= 0) return;
+    if (c.count[b] == 0) {
+        double* out = c.mult + (size_t)b * (2 * P + 2);
+        for (int k = 0; k < 2 * P + 2; ++k) out[k] = 0.0;
+        return;
+    }
     double rho;
     const Frame f = box_frame(c.cen, b, &rho);
     const double inv_rho = 1.0 / rho;
@@ -81,8 +87,12 @@ __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, 
     if (i >= n) return;
     const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
-    if (k0 == k1) return;
     const size_t ew = 2 * (size_t)c.p + 2;
+    if (k0 == k1) {  // nothing to add; a first pass still writes the record
+        if (!acc_in)
+            for (size_t k = 0; k < ew; ++k) c.local[(size_t)t * ew + k] = 0.0;
+        return;
+    }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
     double* out = c.local + (size_t)t * ew;
@@ -98,6 +108,8 @@ __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, 
     }
 #pragma unroll
     for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
+    if (!acc_in)  // a first pass below the record order clears the rest
+        for (size_t k = 2 * P + 2; k < ew; ++k) out[k] = 0.0;
 }
 
 // Precision tier: FP32 copy of every multipole A-block, [nb][2p]
@@ -118,8 +130,12 @@ __global__ void __launch_bounds__(128) k_m2l_f32(FmmCtx c, const float* __restri
     if (i >= n) return;
     const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
-    if (k0 == k1) return;
     const size_t ew = 2 * (size_t)c.p + 2, fw = 2 * (size_t)c.p;
+    if (k0 == k1) {  // nothing to add; a first pass still writes the record
+        if (!acc_in)
+            for (size_t k = 0; k < ew; ++k) c.local[(size_t)t * ew + k] = 0.0;
+        return;
+    }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
     double* out = c.local + (size_t)t * ew;
@@ -145,6 +161,7 @@ __global__ void __launch_bounds__(128) k_m2l_f32(FmmCtx c, const float* __restri
         out[1] = cq[1];
 #pragma unroll
         for (int k = 0; k < 2 * P; ++k) out[2 + k] = (double)acc[k];
+        for (size_t k = 2 * P + 2; k < ew; ++k) out[k] = 0.0;  // a first pass below the record order
     }
 }
 

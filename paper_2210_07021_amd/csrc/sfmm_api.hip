@@ -634,9 +634,8 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
             fill_f64(defl, 3 * P.M, 0.0, s);
             return SFMM_OK;
         }
-        const size_t ne = (size_t)P.nbox * (2 * P.p + 2);
-        fill_f64(P.mult.data(), ne, 0.0, s);
-        fill_f64(P.local.data(), ne, 0.0, s);
+        // every multipole record is written by Lemma 1 (leaves) or Lemma 2
+        // (split boxes), every local record by the first M2L pass
         const FmmCtx c = P.ctx();
         const int nlev = (int)P.lvl_start.size() - 1;
         Profiler prof(s);

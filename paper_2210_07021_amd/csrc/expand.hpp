@@ -283,6 +283,64 @@ SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
     acc[1] += Q;
 }
 
+// translate_add without an accumulator: in(k) gives input entry k and
+// out(k, v) takes output entry k as soon as it is formed (entries 2..2P+1 in
+// order, then C and Q), for kernels with one translation per lane.  Without
+// the 2P + 2 accumulator registers two waves fit on a SIMD.
+template <int P, class In, class Out>
+SFMM_HD void translate_emit(const In& in, const TransGeom& G, const Out& out) {
+    double ar[P + 1], ai[P + 1];
+    const double C = in(0), Q = in(1);
+    ar[0] = 0.0;
+    ai[0] = 0.0;
+    cplx pw = G.ph1;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplx a = {in(2 * l), in(2 * l + 1)};
+        const cplx v = cmul(pw, a);
+        ar[l] = v.re;
+        ai[l] = v.im;
+        pw = cmul(pw, G.ph1);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int j = P - 1; j >= i; --j) {
+            ar[j] = fma(G.b, ar[j + 1], ar[j]);
+            ai[j] = fma(G.b, ai[j + 1], ai[j]);
+        }
+    }
+    const double u0 = ar[0];
+    double gn = G.g;
+#pragma unroll
+    for (int n = 1; n <= P; ++n) {
+        ar[n] *= gn;
+        ai[n] *= gn;
+        gn *= G.g;
+    }
+#pragma unroll
+    for (int i = P - 2; i >= 0; --i) {
+#pragma unroll
+        for (int j = i; j <= P - 2; ++j) {
+            ar[j + 2] = fma(G.a, ar[j + 1], ar[j + 2]);
+            ai[j + 2] = fma(G.a, ai[j + 1], ai[j + 2]);
+        }
+    }
+    cplx pw2 = G.ph2;
+    double an = G.a;
+#pragma unroll
+    for (int l = 1; l <= P; ++l) {
+        const cplx v = {ar[l] - (Q / l) * an, ai[l]};
+        const cplx o = cmul(pw2, v);
+        out(2 * l, o.re);
+        out(2 * l + 1, o.im);
+        pw2 = cmul(pw2, G.ph2);
+        an *= G.a;
+    }
+    out(0, C + Q * G.clog + 2.0 * u0);
+    out(1, Q);
+}
+
 // Lemma 1 for a set of particles about centre f with scale rho; C carries the
 // zero-mean gauge's share sum q / (4 pi) (Eq. STAND_CONDITION).
 // The precision tier's Lemma 3 translation: the A-block (scaled, FP32, A[2l-2]

@@ -41,9 +41,10 @@ __global__ void __launch_bounds__(128) k_p2m(FmmCtx c, int nb) {
 }
 
 // Lemma 2: every split box of one level gathers its 4 children.  Four
-// consecutive lanes per box, lane 4i + k translating child k; the four
-// translated records are summed by two lane exchanges, (c0 + c1) + (c2 + c3),
-// and lane 4i writes the box's record.
+// consecutive lanes per box, lane 4i + k translating child k (an empty child
+// has a zero record); each output entry is summed over the four lanes by two
+// lane exchanges, (c0 + c1) + (c2 + c3), as it is formed, and lane 4i writes
+// it.
 template <int P>
 __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,27 +53,18 @@ __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
     const int b = b0 + i;
     const int ch0 = c.child0[b];
     if (ch0 < 0) return;
-    double acc[2 * P + 2];
-#pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
     const int ch = ch0 + kc;
-    if (c.count[ch] > 0) {
-        double rho_t, rho_s;
-        const Frame ft = box_frame(c.cen, b, &rho_t);
-        const Frame fs = box_frame(c.cen, ch, &rho_s);
-        const TransGeom G = trans_geom<kM2M>(fs, rho_s, ft, rho_t);
-        translate_add<P>(c.mult + (size_t)ch * (2 * P + 2), G, acc);
-    }
-#pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) {
-        acc[k] += __shfl_xor(acc[k], 1, 64);
-        acc[k] += __shfl_xor(acc[k], 2, 64);
-    }
-    if (kc == 0) {
-        double* out = c.mult + (size_t)b * (2 * P + 2);
-#pragma unroll
-        for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
-    }
+    double rho_t, rho_s;
+    const Frame ft = box_frame(c.cen, b, &rho_t);
+    const Frame fs = box_frame(c.cen, ch, &rho_s);
+    const TransGeom G = trans_geom<kM2M>(fs, rho_s, ft, rho_t);
+    const double* in = c.mult + (size_t)ch * (2 * P + 2);
+    double* out = c.mult + (size_t)b * (2 * P + 2);
+    translate_emit<P>([&](int k) { return in[k]; }, G, [&](int k, double v) {
+        double s = v + __shfl_xor(v, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (kc == 0) out[k] = s;
+    });
 }
 
 // Lemma 3: each target box sums its FMM-act list (boxes taken longest list

@@ -196,6 +196,7 @@ struct FmmCtx {
     const double4* spt;  // sources sorted by key: x, y, z, q
     double* mult;        // [nb][2p+2]
     double* local;       // [nb][2p+2]
+    const double* zrec;  // [2p+2] zeros
 };
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s);
 void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s);

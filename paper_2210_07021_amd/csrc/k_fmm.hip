@@ -104,6 +104,56 @@ __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, 
         for (size_t k = 2 * P + 2; k < ew; ++k) out[k] = 0.0;
 }
 
+// Lemma 3 with four lanes per target box (a team): in each round lane r of
+// the team translates entry k0 + 4 round + r of the box's list (a zero
+// record past the end); every output entry is summed over the team by two
+// lane exchanges as it is formed and added by the lane that owns it (entry
+// k by lane k mod 4), so no lane holds the whole accumulator and two waves
+// fit on a SIMD.
+template <int P>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_team(FmmCtx c, const int* order, int n, const int* off, const int* src, bool acc_in) {
+    constexpr int EW = 2 * P + 2, NA = (EW + 3) / 4;
+    __shared__ double sacc[NA * 128];
+    double* acc = sacc + threadIdx.x;  // entry 4q + r at acc[q * 128]
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid >> 2, r = gid & 3;
+    if (i >= n) return;  // the four lanes of a team leave together
+    const int t = order ? order[i] : i;
+    const int k0 = off[t], k1 = off[t + 1];
+    const size_t ew = 2 * (size_t)c.p + 2;
+    double* out = c.local + (size_t)t * ew;
+    if (k0 == k1) {
+        if (!acc_in)
+            for (size_t k = r; k < ew; k += 4) out[k] = 0.0;
+        return;
+    }
+    for (int q = 0; q < NA; ++q) acc[q * 128] = (acc_in && 4 * q + r < EW) ? out[4 * q + r] : 0.0;
+    double rho_t;
+    const Frame ft = box_frame(c.cen, t, &rho_t);
+    for (int kb = k0; kb < k1; kb += 4) {
+        const int k = kb + r;
+        const bool live = k < k1;
+        const int s = live ? src[k] : src[k0];
+        double rho_s;
+        const Frame fs = box_frame(c.cen, s, &rho_s);
+        const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
+        const double* in = live ? c.mult + (size_t)s * ew : c.zrec;
+        translate_emit<P>([&](int e) { return in[e]; }, G, [&](int e, double v) {
+            double sum = v + __shfl_xor(v, 1, 64);
+            sum += __shfl_xor(sum, 2, 64);
+            // one writer per slot: the LDS add needs no read-back, and the
+            // sums keep their order (round by round)
+            if (r == (e & 3))
+                __hip_atomic_fetch_add(acc + (e >> 2) * 128, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        });
+    }
+    for (int q = 0; q < NA; ++q)
+        if (4 * q + r < EW) out[4 * q + r] = acc[q * 128];
+    if (!acc_in)
+        for (size_t k = EW + r; k < ew; k += 4) out[k] = 0.0;
+}
+
 // Precision tier: FP32 copy of every multipole A-block, [nb][2p]
 __global__ void k_mult_to_f32(const double* __restrict__ mult, int p, int nb, float* __restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -217,7 +267,7 @@ void fmm_m2l(const FmmCtx& c, int p, bool acc_in, const int* order, int n, const
              hipStream_t s) {
     if (n <= 0) return;
     if (p < 1 || p > c.p) throw Error(ST_INTERNAL, "M2L order above the record order");
-#define L_(P) case P: k_m2l<P><<<nblk(n, 128), 128, 0, s>>>(c, order, n, off, src, acc_in); break;
+#define L_(P) case P: k_m2l_team<P><<<nblk(4 * (int64_t)n, 128), 128, 0, s>>>(c, order, n, off, src, acc_in); break;
     SFMM_DISPATCH(p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();

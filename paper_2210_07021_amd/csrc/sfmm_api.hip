@@ -128,6 +128,7 @@ struct sfmm_plan_impl {
     mutable long long n_p2p_pairs = -1, n_m2p_evals = -1;  // summed on the first stats request
     // expansions
     DVec<double> mult, local;
+    DVec<double> zrec;  // one zero record (lanes past the end of an FMM-act list)
     DVec<float> multf;  // precision tier: FP32 A-blocks of the multipoles
     // per-pair order policies
     DVec<int> m2l_ent;        // target box of every FMM-act entry (per-pair order policies)
@@ -153,6 +154,7 @@ struct sfmm_plan_impl {
         c.spt = spt.data();
         c.mult = mult.data();
         c.local = local.data();
+        c.zrec = zrec.data();
         return c;
     }
 };
@@ -610,6 +612,8 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         const size_t ne = (size_t)P->nbox * (2 * P->p + 2);
         P->mult.resize(ne);
         P->local.resize(ne);
+        P->zrec.resize(2 * (size_t)P->p + 2);
+        fill_f64(P->zrec.data(), 2 * (size_t)P->p + 2, 0.0, s);
         SFMM_HIP(hipStreamSynchronize(s));
         *out = P.release();
         return SFMM_OK;

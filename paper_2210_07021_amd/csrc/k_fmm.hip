@@ -8,6 +8,22 @@
 
 namespace sfmm {
 
+// Sum of a double over the four lanes of a quad (lanes 4i .. 4i + 3), every
+// lane getting the sum: two butterfly steps with DPP quad permutations
+// (lane exchanges inside the VALU, no LDS), (v0 + v1) + (v2 + v3) on every
+// lane of the quad.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi2, lo2);
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_quad<0xB1>(v);     // quad_perm [1, 0, 3, 2]: lane ^ 1
+    return v + dpp_quad<0x4E>(v);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+}
+
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 
 __device__ __forceinline__ Frame box_frame(const double* cen, int b, double* rho) {
@@ -61,8 +77,7 @@ __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
     const double* in = c.mult + (size_t)ch * (2 * P + 2);
     double* out = c.mult + (size_t)b * (2 * P + 2);
     translate_emit<P>([&](int k) { return in[k]; }, G, [&](int k, double v) {
-        double s = v + __shfl_xor(v, 1, 64);
-        s += __shfl_xor(s, 2, 64);
+        const double s = quad_sum(v);
         if (kc == 0) out[k] = s;
     });
 }
@@ -110,12 +125,21 @@ __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, 
 // lane exchanges as it is formed and added by the lane that owns it (entry
 // k by lane k mod 4), so no lane holds the whole accumulator and two waves
 // fit on a SIMD.
+// Lemma 3 with four lanes per target box (a team): in each round lane r of
+// the team translates entry k0 + 4 round + r of the box's list (a zero
+// record past the end).  Every output entry is summed over the team as it
+// is formed (quad_sum); the accumulator is shared out: lane r owns entries
+// 2 + 4q + r (slot q) and, for r < 2, entry r (slot NG), in LDS.  The sums
+// of entries 2 + 4q .. 5 + 4q are held until the group is complete and then
+// each lane adds its own with one LDS add (single writer per slot, so the
+// sums keep their round order).  No lane holds the whole accumulator: two
+// waves fit on a SIMD.
 template <int P>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l_team(FmmCtx c, const int* order, int n, const int* off, const int* src, bool acc_in) {
-    constexpr int EW = 2 * P + 2, NA = (EW + 3) / 4;
+    constexpr int EW = 2 * P + 2, NG = (2 * P + 3) / 4, NA = NG + 1;
     __shared__ double sacc[NA * 128];
-    double* acc = sacc + threadIdx.x;  // entry 4q + r at acc[q * 128]
+    double* acc = sacc + threadIdx.x;  // slot q at acc[q * 128]
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = gid >> 2, r = gid & 3;
     if (i >= n) return;  // the four lanes of a team leave together
@@ -128,7 +152,11 @@ k_m2l_team(FmmCtx c, const int* order, int n, const int* off, const int* src, bo
             for (size_t k = r; k < ew; k += 4) out[k] = 0.0;
         return;
     }
-    for (int q = 0; q < NA; ++q) acc[q * 128] = (acc_in && 4 * q + r < EW) ? out[4 * q + r] : 0.0;
+    auto entry = [&](int q) { return q < NG ? 2 + 4 * q + r : r; };  // entry held in slot q (r < 2 for slot NG)
+    for (int q = 0; q < NA; ++q) {
+        const int e = entry(q);
+        acc[q * 128] = (acc_in && e < EW && (q < NG || r < 2)) ? out[e] : 0.0;
+    }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
     for (int kb = k0; kb < k1; kb += 4) {
@@ -139,17 +167,29 @@ k_m2l_team(FmmCtx c, const int* order, int n, const int* off, const int* src, bo
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
         const double* in = live ? c.mult + (size_t)s * ew : c.zrec;
+        double pend[4], cq[2];
         translate_emit<P>([&](int e) { return in[e]; }, G, [&](int e, double v) {
-            double sum = v + __shfl_xor(v, 1, 64);
-            sum += __shfl_xor(sum, 2, 64);
-            // one writer per slot: the LDS add needs no read-back, and the
-            // sums keep their order (round by round)
-            if (r == (e & 3))
-                __hip_atomic_fetch_add(acc + (e >> 2) * 128, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const double sum = quad_sum(v);
+            if (e < 2) {
+                cq[e] = sum;
+                return;
+            }
+            const int j = (e - 2) & 3;
+            pend[j] = sum;
+            if (j == 3 || e == EW - 1) {  // group complete: lane r adds entry 2 + 4q + r
+                const double mine = r == 0 ? pend[0] : r == 1 ? pend[1] : r == 2 ? pend[2] : pend[3];
+                if (j == 3 || r <= j)  // a partial last group holds entries up to lane j's
+                    __hip_atomic_fetch_add(acc + ((e - 2) >> 2) * 128, mine, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         });
+        if (r < 2) __hip_atomic_fetch_add(acc + NG * 128, r == 0 ? cq[0] : cq[1], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    for (int q = 0; q < NA; ++q)
-        if (4 * q + r < EW) out[4 * q + r] = acc[q * 128];
+    for (int q = 0; q < NA; ++q) {
+        const int e = entry(q);
+        if (e < EW && (q < NG || r < 2)) out[e] = acc[q * 128];
+    }
     if (!acc_in)
         for (size_t k = EW + r; k < ew; k += 4) out[k] = 0.0;
 }

@@ -38,7 +38,7 @@ KERNEL_SOURCES = {
     "p2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
     "m2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
 }
-KERNEL_NAMES = {"m2l": "k_m2l", "p2p": "k_p2p", "m2p": "k_m2p"}
+KERNEL_NAMES = {"m2l": "k_m2l_team", "p2p": "k_p2p", "m2p": "k_m2p"}
 
 
 def source_hash(stage: str) -> str:

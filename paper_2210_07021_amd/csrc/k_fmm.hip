@@ -82,43 +82,6 @@ __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
     });
 }
 
-// Lemma 3: each target box sums its FMM-act list (boxes taken longest list
-// first so the lanes of a wave carry similar work).  P is the order of the
-// translation, c.p that of the records (P <= c.p: a per-pair order policy
-// runs one pass per order with the pairs of that order, adding to the
-// record's first 2P+2 entries, acc = true).
-template <int P>
-__global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, const int* off, const int* src,
-                                            bool acc_in) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int t = order ? order[i] : i;
-    const int k0 = off[t], k1 = off[t + 1];
-    const size_t ew = 2 * (size_t)c.p + 2;
-    if (k0 == k1) {  // nothing to add; a first pass still writes the record
-        if (!acc_in)
-            for (size_t k = 0; k < ew; ++k) c.local[(size_t)t * ew + k] = 0.0;
-        return;
-    }
-    double rho_t;
-    const Frame ft = box_frame(c.cen, t, &rho_t);
-    double* out = c.local + (size_t)t * ew;
-    double acc[2 * P + 2];
-#pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = acc_in ? out[k] : 0.0;
-    for (int k = k0; k < k1; ++k) {
-        const int s = src[k];
-        double rho_s;
-        const Frame fs = box_frame(c.cen, s, &rho_s);
-        const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
-        translate_add<P>(c.mult + (size_t)s * ew, G, acc);
-    }
-#pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) out[k] = acc[k];
-    if (!acc_in)  // a first pass below the record order clears the rest
-        for (size_t k = 2 * P + 2; k < ew; ++k) out[k] = 0.0;
-}
-
 // Lemma 3 with four lanes per target box (a team): in each round lane r of
 // the team translates entry k0 + 4 round + r of the box's list (a zero
 // record past the end); every output entry is summed over the team by two
@@ -133,7 +96,12 @@ __global__ void __launch_bounds__(128) k_m2l(FmmCtx c, const int* order, int n, 
 // of entries 2 + 4q .. 5 + 4q are held until the group is complete and then
 // each lane adds its own with one LDS add (single writer per slot, so the
 // sums keep their round order).  No lane holds the whole accumulator: two
-// waves fit on a SIMD.
+// waves fit on a SIMD.  Target boxes are taken in `order` (longest list
+// first, so the teams of a wave carry similar work).  P is the order of the
+// translation, c.p that of the records (P <= c.p: a per-pair order policy
+// runs one pass per order with the pairs of that order, adding to the
+// records' first 2P + 2 entries, acc_in = true; a first pass, acc_in =
+// false, writes whole records).
 template <int P>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l_team(FmmCtx c, const int* order, int n, const int* off, const int* src, bool acc_in) {

@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink N (quick runs only)")
     ap.add_argument("--tolerance", type=float, default=1e-10)
     ap.add_argument("--order", type=int, default=0, help="fixed order instead of the tolerance")
-    ap.add_argument("--leaf-size", type=int, default=32)
+    ap.add_argument("--leaf-size", type=int, default=56)  # the fastest of a leaf-size sweep on clustered-1e7
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-tier (FP32 mixed) leg")

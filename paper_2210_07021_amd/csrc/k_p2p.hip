@@ -3,22 +3,22 @@
 // of T's close leaves.
 //
 // At planning time each direct-act list is split in two (near_split):
-//   * a close leaf S whose centre is more than 3 R_S from every target of T
-//     (and that holds enough particles for it to pay) is taken through its
+//   * a close leaf S whose centre is more than R_S / x from every target of
+//     T (and that holds enough particles for it to pay) is taken through its
 //     own multipole expansion (Lemma 1) at each target: k_m2p.  By Eq.
-//     MUL_ERR the truncation there is below (Q~/2pi) x^(p+1)/((p+1)(1-x))
-//     with x ~ 1/3, under 1e-15 Q~ for p >= 28; the split is only made for
-//     p >= 12 and for leaves with at least p/4 + 2 particles (the expansion
-//     costs about p/4 pair evaluations).  Big leaves of sparse regions next
-//     to dense clumps are where it matters: their targets otherwise meet
-//     every particle of the clump directly.
+//     MUL_ERR the truncation there is below (Q~/2pi) x^(p+1)/((p+1)(1-x));
+//     x is at most 1/3 and makes x^(p+1) at most 1e-4 times the tolerance of
+//     order p (m2p_ratio).  The split is only made for p >= 12 and for leaves
+//     with at least p/4 + 2 particles.  Big leaves of sparse regions next to
+//     dense clumps are where it matters: their targets otherwise meet every
+//     particle of the clump directly.
 //   * every other close leaf is summed particle by particle: k_p2p.
 //
 // k_p2p: one 64-wide wavefront (a 64-thread workgroup) owns one target leaf
 // and takes its targets in groups of ng <= 64.  The lanes form ng teams of
 // L = floor(64 / ng) lanes, team t owning target t of the group.  The close
 // leaves' particle ranges are concatenated into one flat index space (wave
-// prefix sum of their counts); each tile of 256 particles is decoded once
+// prefix sum of their counts); each tile of 128 particles is decoded once
 // (binary search by lane shuffles) and staged in LDS, and lane r of a team
 // takes particles r, r + L, ... of the tile.  The four partial sums stay in
 // registers across all tiles; at the end of the group the team's lanes are
@@ -42,6 +42,8 @@
 // and with Q_near = sum q over the summed leaves (from their Lemma 1 Q),
 //   4 pi psi_near = S + (1 - log 4) Q_near.
 #include "common.hpp"
+#include <algorithm>
+#include <cmath>
 #include "expand.hpp"
 
 namespace sfmm {
@@ -57,7 +59,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kM2PMinOrder = 12;
-constexpr double kM2PRatio = 3.0;  // every target beyond 3 R_S from the leaf centre
+// A close leaf S is evaluated through its Lemma 1 expansion at the targets
+// of T when every target is beyond ratio R_S from its centre, ratio = 1 / x
+// with the truncation term x^(p+1) at most 1e-4 tau_p (tau_p: the tolerance
+// that gives order p, 1e-10 at p = 36 by the order policy), and at least 3:
+// ratio 3 down to p = 20, 4.4 at p = 12.  And when S holds at least p/4 + 2
+// particles (measured at p = 36: lower ratios or a higher count move more
+// work than they save).
+double m2p_ratio(int p) {
+    const double tau = 1e-10 * std::exp((p - 36) * std::log(0.58));
+    const double x = std::min(1.0 / 3.0, std::pow(1e-4 * tau, 1.0 / (p + 1)));
+    return 1.0 / x;
+}
+int m2p_min_count(int p) { return (p + 8 + 3) / 4; }  // ceil(p/4 + 2)
 
 // ------------------------------------------------------------ list split
 // Target box of every direct-act entry: the last box whose list starts at
@@ -79,14 +93,15 @@ __global__ void k_entry_box(const int* __restrict__ off, int nbox, int np, int* 
 __global__ void k_near_flags(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src, int np,
                              const int* __restrict__ tfirst, const int* __restrict__ tcount,
                              const double* __restrict__ tx, const double* __restrict__ ty,
-                             const double* __restrict__ tz, int* __restrict__ near, int* __restrict__ far) {
+                             const double* __restrict__ tz, double ratio, int min_count,
+                             int* __restrict__ near, int* __restrict__ far) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
     const int T = ent_t[k], S = src[k];
     const int nt = tcount[T];
     bool is_far = false;
-    if (nt > 0 && c.p >= kM2PMinOrder && 4 * c.count[S] >= c.p + 8) {
-        const double a = kM2PRatio * c.rad[S];
+    if (nt > 0 && c.p >= kM2PMinOrder && c.count[S] >= min_count) {
+        const double a = ratio * c.rad[S];
         if (a < 3.0) {
             const double* cs = c.cen + 4 * (size_t)S;
             const double* ct = c.cen + 4 * (size_t)T;
@@ -176,8 +191,8 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
     tot.resize(2);
     fill_i32(tot.data(), 2, 0, s);
     if (np > 0) {
-        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t, src, np, tfirst, tcount, tx, ty, tz,
-                                                   near.data(), far.data());
+        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t, src, np, tfirst, tcount, tx, ty, tz, m2p_ratio(c.p),
+                                                   m2p_min_count(c.p), near.data(), far.data());
         SFMM_LAUNCH_CHECK();
         scan_excl_i32(near.data(), npos.data(), np, tot.data(), s);
         scan_excl_i32(far.data(), fpos.data(), np, tot.data() + 1, s);

@@ -12,7 +12,7 @@ import time
 
 
 def autotune(src, q, tgt, tolerance: float = 1e-10, precision: int = 0,
-             leaf_sizes=(16, 24, 32, 48, 64), segments=(64, 128, 256), repeats: int = 2, **fixed):
+             leaf_sizes=(16, 24, 32, 40, 48, 56, 64, 80), segments=(64, 128, 256), repeats: int = 2, **fixed):
     import torch
     from . import Plan
     src = torch.as_tensor(src, dtype=torch.float64).cuda() if not isinstance(src, torch.Tensor) else src

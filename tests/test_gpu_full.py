@@ -1,6 +1,6 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark times (tolerance 1e-10, leaf size 64), on seeded samples of targets
-that the oracle evaluates one by one."""
+benchmark times (tolerance 1e-10, leaf size 56), and at a small leaf size, on
+seeded samples of targets that the oracle evaluates one by one."""
 import numpy as np
 import pytest
 
@@ -14,15 +14,16 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("workload,sample", [("clustered-1e6", 2000), ("clustered-1e7", 400)])
-def test_full_size_sampled_parity(workload, sample, oracle_lib):
+@pytest.mark.parametrize("workload,sample,leaf", [("clustered-1e6", 2000, 56), ("clustered-1e7", 400, 56),
+                                                  ("clustered-1e6", 1000, 24)])
+def test_full_size_sampled_parity(workload, sample, leaf, oracle_lib):
     import torch
     import paper_2210_07021_amd as sf
     print(f"[full] {workload}: generating", flush=True)
     src, q, tgt = skies.workload(workload)
     M = tgt.shape[1]
-    print(f"[full] {workload}: N={src.shape[1]} M={M} plan+execute", flush=True)
-    plan = sf.Plan(src, q, tgt, tolerance=1e-10, leaf_size=64)
+    print(f"[full] {workload}: N={src.shape[1]} M={M} leaf {leaf} plan+execute", flush=True)
+    plan = sf.Plan(src, q, tgt, tolerance=1e-10, leaf_size=leaf)
     psi, defl = plan.execute()
     torch.cuda.synchronize()
     st = plan.stats()

@@ -1,0 +1,93 @@
+"""The library's device math compiled for the host (tests/host_math.cpp, the
+same headers as the HIP kernels): double-double sin/cos, the pair loop's
+log and reciprocal, and the walk's angle-free MAC filter, against
+references computed here in higher precision."""
+import os
+import random
+import shutil
+import subprocess
+from decimal import Decimal, getcontext
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def host_math(tmp_path_factory):
+    if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("host_math") / "host_math")
+    cmd = [HIPCC, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+           os.path.join(HERE, "host_math.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return exe
+
+
+def _run(exe, mode, text=""):
+    r = subprocess.run([exe, mode], input=text, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return r.stdout.split("\n")
+
+
+def _sin_cos(h, l):
+    # Taylor series at 70 digits (|x| <= 8 here); the argument h + l is
+    # formed at that precision too
+    getcontext().prec = 70
+    x = Decimal(h) + Decimal(l)
+    s = c = Decimal(0)
+    term, k = Decimal(1), 0
+    while k < 120:
+        if k % 4 == 0:
+            c += term
+        elif k % 4 == 1:
+            s += term
+        elif k % 4 == 2:
+            c -= term
+        else:
+            s -= term
+        k += 1
+        term = term * x / k
+    return s, c
+
+
+def test_dd_sincos_is_double_double_accurate(host_math):
+    rng = random.Random(7)
+    xs = [(h, rng.uniform(-1, 1) * abs(h) * 1e-17) for h in
+          [rng.uniform(-7, 7) for _ in range(400)] + [rng.uniform(-1e-3, 1e-3) for _ in range(100)]]
+    xs += [(1.5707963267948966, 6.123233995736766e-17), (3.141592653589793, 1.2246467991473532e-16), (0.0, 0.0)]
+    out = _run(host_math, "sincos", "".join(f"{h.hex()} {l.hex()}\n" for h, l in xs))
+    worst = 0.0
+    for (h, l), line in zip(xs, out):
+        v = [Decimal(float.fromhex(t)) for t in line.split()]
+        s, c = _sin_cos(h, l)
+        worst = max(worst, float(abs(v[0] + v[1] - s)), float(abs(v[2] + v[3] - c)))
+    assert worst < 1e-31, worst
+
+
+def test_pair_log_and_reciprocal_within_a_few_ulp(host_math):
+    import math
+    getcontext().prec = 40
+    rng = random.Random(11)
+    xs = [rng.uniform(0, 4) for _ in range(3000)] + [10 ** rng.uniform(-33, 0.6) for _ in range(3000)]
+    xs += [1.0, 2.0, 4.0, 0.5, 1e-32, 0.7071067811865476, 1.4142135623730951]
+    out = _run(host_math, "log", "".join(x.hex() + "\n" for x in xs))
+    wl = wi = 0.0
+    for x, line in zip(xs, out):
+        lg, inv = (float.fromhex(t) for t in line.split())
+        el, ei = Decimal(x).ln(), 1 / Decimal(x)
+        if el != 0:
+            wl = max(wl, float(abs(Decimal(lg) - el)) / math.ulp(abs(float(el))))
+        wi = max(wi, float(abs(Decimal(inv) - ei)) / math.ulp(abs(float(ei))))
+    assert wl < 4 and wi < 3, (wl, wi)
+
+
+def test_angle_free_mac_filter_never_contradicts_the_angle(host_math):
+    fields = _run(host_math, "mac")[0].split()
+    n, decided, undecided, wrong, tie_checked, tie_wrong, tie_disagree = (int(t) for t in fields)
+    assert wrong == 0 and tie_wrong == 0 and tie_disagree == 0
+    # the samples reach both regimes, and many near-ties are settled by long double
+    assert decided > n // 2 and undecided > n // 10 and tie_checked > n // 20

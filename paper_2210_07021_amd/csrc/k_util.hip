@@ -195,12 +195,17 @@ constexpr int kRsWaves = kRsThreads / 64;
 __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, int* hist) {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    int d[kRsRounds];
+#pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
         const int64_t i = base + r * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+        d[r] = i < n ? (int)((keys[i] >> shift) & 255) : -1;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r)
+        if (d[r] >= 0) atomicAdd(&h[d[r]], 1);
     __syncthreads();
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
@@ -237,60 +242,42 @@ __global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restri
     if (threadIdx.x == 0) dtot[d] = carry;
 }
 
-// Stable scatter of one tile.  The ranks give every key its position in the
-// tile sorted by digit (the tile's digit counts come from the histogram
-// pass: same tiles); the keys are staged there in LDS and then written out
-// in that order, so consecutive lanes write consecutive addresses within each
-// digit's run.
+// Stable scatter of one tile of kRsTile keys.  Wave w owns the tile's w-th
+// quarter and walks it in rounds of 64 keys: lanes with equal digits find
+// each other by ballots over the digit's bits, and a wave-private count per
+// digit gives every key its rank among the equal digits before it in the
+// quarter.  One pass over the counts of the four waves then places each key
+// in the tile sorted by digit (LDS), and the sorted tile is written out, so
+// consecutive lanes write consecutive addresses within each digit's run.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                            uint32_t* vout, int64_t n, int shift, int nblk,
-                                                           const int* offs, const int* dtot, const int* hist) {
-    __shared__ int gbase[256];  // global start of each digit's run of this tile
-    __shared__ int lbase[256];  // start of each digit's run inside the tile
-    __shared__ int run[256];    // keys of each digit placed so far
-    __shared__ int wcnt[kRsWaves][256];
+                                                           const int* offs, const int* dtot) {
+    __shared__ int wcnt[kRsWaves][256];  // per-wave digit counts, then each wave's first slot per digit
+    __shared__ int goff[256];            // global position of slot 0 of each digit's run of this tile
     __shared__ int wsum[kRsWaves];
     __shared__ uint64_t sk[kRsTile];
     __shared__ uint32_t sv[kRsTile];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    {
-        int all;
-        gbase[t] = offs[t * nblk + blockIdx.x] + block_excl_scan(dtot[t], wsum, &all);
-    }
-    run[t] = 0;
-    // exclusive scan of this tile's digit counts
-    {
-        const int c = hist[t * nblk + blockIdx.x];
-        int x = c;
+    constexpr int kQuarter = kRsTile / kRsWaves;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        int before = 0;
+    for (int k = 0; k < 256; k += 64) wcnt[wave][k + lane] = 0;
+    const int64_t q0 = (int64_t)blockIdx.x * kRsTile + wave * kQuarter;
+    uint64_t key[kRsRounds];
+    uint32_t val[kRsRounds];
 #pragma unroll
-        for (int w = 0; w < kRsWaves; ++w) before += w < wave ? wsum[w] : 0;
-        lbase[t] = before + x - c;
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t i = q0 + r * 64 + lane;
+        key[r] = i < n ? kin[i] : 0;
+        val[r] = (vin && i < n) ? vin[i] : 0u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
-    for (int r = 0; r < kRsRounds; ++r) {
+    int dg[kRsRounds], at[kRsRounds];
+    __syncthreads();
 #pragma unroll
-        for (int w = 0; w < kRsWaves; ++w) wcnt[w][t] = 0;
-        __syncthreads();
-        const int64_t i = tile0 + r * kRsThreads + t;
-        const bool valid = i < n;
-        uint64_t key = 0;
-        uint32_t val = 0;
-        int d = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin ? vin[i] : 0u;
-            d = (int)((key >> shift) & 255);
-        }
+    for (int r = 0; r < kRsRounds; ++r) {
+        const bool valid = q0 + r * 64 + lane < n;
+        const int d = (int)((key[r] >> shift) & 255);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -298,27 +285,49 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, 
             peers &= ((d >> b) & 1) ? m : ~m;
         }
         const int rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int pos = lbase[d] + run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            sk[pos] = key;
-            sv[pos] = val;
-        }
-        __syncthreads();
-        int add = 0;
-#pragma unroll
-        for (int w = 0; w < kRsWaves; ++w) add += wcnt[w][t];
-        run[t] += add;
+        const int before = wcnt[wave][d];
+        // every lane of the wave has read the count before its leader moves it
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wcnt[wave][d] = before + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        dg[r] = valid ? d : -1;
+        at[r] = before + rank;
     }
     __syncthreads();
+    {
+        int c[kRsWaves], tot = 0;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) {
+            c[w] = wcnt[w][t];
+            tot += c[w];
+        }
+        int all;
+        const int lbase = block_excl_scan(tot, wsum, &all);
+        goff[t] = offs[t * nblk + blockIdx.x] + block_excl_scan(dtot[t], wsum, &all) - lbase;
+        int run = lbase;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) {
+            wcnt[w][t] = run;
+            run += c[w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        if (dg[r] >= 0) {
+            const int pos = wcnt[wave][dg[r]] + at[r];
+            sk[pos] = key[r];
+            sv[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
     const int cnt = (int)min((int64_t)kRsTile, n - tile0);
     for (int p = t; p < cnt; p += kRsThreads) {
-        const uint64_t key = sk[p];
-        const int d = (int)((key >> shift) & 255);
-        const int pos = gbase[d] + (p - lbase[d]);
-        kout[pos] = key;
+        const uint64_t k = sk[p];
+        const int64_t pos = (int64_t)goff[(int)((k >> shift) & 255)] + p;
+        if (pos < 0 || pos >= n) continue;  // unreachable with consistent counts
+        kout[pos] = k;
         if (vout) vout[pos] = sv[p];
     }
 }
@@ -341,7 +350,7 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
         SFMM_LAUNCH_CHECK();
         k_rs_rowscan<<<256, kScanThreads, 0, s>>>(hist, nblk, offs, dtot);
         SFMM_LAUNCH_CHECK();
-        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot, hist);
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot);
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);

@@ -107,6 +107,11 @@ void fill_i32(int* p, size_t n, int v, hipStream_t s);
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s);
 // stable LSD radix sort of (key, value) pairs on key bits [begin_bit, bits)
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit = 0);
+// The same sort, ping-ponging between the caller's buffers (kalt / valt hold
+// n elements; valt may be null when vals is): returns the buffer holding the
+// sorted keys, *vout (if not null) the one holding the values.
+uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint32_t* valt, int64_t n, int bits,
+                            hipStream_t s, int begin_bit, uint32_t** vout);
 void sum_f64(const double* x, int64_t n, double* out, hipStream_t s, int stride = 1);  // sum of x[i * stride]
 void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 
@@ -130,7 +135,7 @@ void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen /
                   double* rad, double* gdd /*[nb][8]*/, hipStream_t s);
 void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf,
                     hipStream_t s);
-void target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount, hipStream_t s);
+void target_ranges(const int* leaf, int64_t m, int nbox, int* tfirst, int* tcount, hipStream_t s);
 void flag_nonzero(const int* count, int n, int* flag, hipStream_t s);
 void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t s);
 

@@ -88,70 +88,123 @@ __global__ void k_entry_box(const int* __restrict__ off, int nbox, int np, int* 
     ent_t[k] = lo;
 }
 
-// 1 in near[k] / far[k] when entry k goes to the direct sum / the multipole
-// evaluation; both 0 when its target box holds no target.
-__global__ void k_near_flags(FmmCtx c, const int* __restrict__ ent_t, const int* __restrict__ src, int np,
-                             const int* __restrict__ tfirst, const int* __restrict__ tcount,
-                             const double* __restrict__ tx, const double* __restrict__ ty,
-                             const double* __restrict__ tz, double ratio, int min_count,
-                             int* __restrict__ near, int* __restrict__ far) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np) return;
-    const int T = ent_t[k], S = src[k];
-    const int nt = tcount[T];
-    bool is_far = false;
-    if (nt > 0 && c.p >= kM2PMinOrder && c.count[S] >= min_count) {
-        const double a = ratio * c.rad[S];
-        if (a < 3.0) {
-            const double* cs = c.cen + 4 * (size_t)S;
-            const double* ct = c.cen + 4 * (size_t)T;
-            // whole box T beyond a + R_T (every point of a box lies within R of its centre)
-            const double b = a + c.rad[T];
-            const double ex = cs[0] - ct[0], ey = cs[1] - ct[1], ez = cs[2] - ct[2];
-            const double d2 = ex * ex + ey * ey + ez * ez;
-            const double hb = 2.0 * sin(0.5 * b);
-            if (b < 3.0 && d2 > hb * hb * (1.0 + 1e-12)) {
-                is_far = true;
-            } else {
-                const double h = 2.0 * sin(0.5 * a);
-                const double thr = h * h;
-                is_far = true;
-                const int t0 = tfirst[T];
-                for (int i = t0; i < t0 + nt; ++i) {
-                    const double dx = tx[i] - cs[0], dy = ty[i] - cs[1], dz = tz[i] - cs[2];
-                    if (!(dx * dx + dy * dy + dz * dz > thr)) {
-                        is_far = false;
-                        break;
+// flag[k] = 1 when entry k goes to the direct sum, 2 when it goes to the
+// multipole evaluation, 0 when its target box holds no target; bnear / bfar
+// count each block's entries of the two kinds.
+constexpr int kNearBlk = 256;
+__global__ void __launch_bounds__(kNearBlk) k_near_flags(FmmCtx c, const int* __restrict__ ent_t,
+                                                         const int* __restrict__ src, int np,
+                                                         const int* __restrict__ tfirst,
+                                                         const int* __restrict__ tcount,
+                                                         const double* __restrict__ tx,
+                                                         const double* __restrict__ ty,
+                                                         const double* __restrict__ tz, double ratio, int min_count,
+                                                         uint8_t* __restrict__ flag, int* __restrict__ bnear,
+                                                         int* __restrict__ bfar) {
+    __shared__ int wn[kNearBlk / 64], wf[kNearBlk / 64];
+    const int k = blockIdx.x * kNearBlk + threadIdx.x;
+    bool is_near = false, is_far = false;
+    if (k < np) {
+        const int T = ent_t[k], S = src[k];
+        const int nt = tcount[T];
+        if (nt > 0 && c.p >= kM2PMinOrder && c.count[S] >= min_count) {
+            const double a = ratio * c.rad[S];
+            if (a < 3.0) {
+                const double* cs = c.cen + 4 * (size_t)S;
+                const double* ct = c.cen + 4 * (size_t)T;
+                // whole box T beyond a + R_T (every point of a box lies within R of its centre)
+                const double b = a + c.rad[T];
+                const double ex = cs[0] - ct[0], ey = cs[1] - ct[1], ez = cs[2] - ct[2];
+                const double d2 = ex * ex + ey * ey + ez * ez;
+                const double hb = 2.0 * sin(0.5 * b);
+                if (b < 3.0 && d2 > hb * hb * (1.0 + 1e-12)) {
+                    is_far = true;
+                } else {
+                    const double h = 2.0 * sin(0.5 * a);
+                    const double thr = h * h;
+                    is_far = true;
+                    const int t0 = tfirst[T];
+                    for (int i = t0; i < t0 + nt; ++i) {
+                        const double dx = tx[i] - cs[0], dy = ty[i] - cs[1], dz = tz[i] - cs[2];
+                        if (!(dx * dx + dy * dy + dz * dz > thr)) {
+                            is_far = false;
+                            break;
+                        }
                     }
                 }
             }
         }
+        is_near = nt > 0 && !is_far;
+        flag[k] = (uint8_t)((is_near ? 1 : 0) | (is_far ? 2 : 0));
     }
-    near[k] = (nt > 0 && !is_far) ? 1 : 0;
-    far[k] = is_far ? 1 : 0;
+    const uint64_t mn = __ballot(is_near), mf = __ballot(is_far);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        wn[wave] = __popcll(mn);
+        wf[wave] = __popcll(mf);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sn = 0, sf = 0;
+        for (int w = 0; w < kNearBlk / 64; ++w) {
+            sn += wn[w];
+            sf += wf[w];
+        }
+        bnear[blockIdx.x] = sn;
+        bfar[blockIdx.x] = sf;
+    }
 }
 
-__global__ void k_near_scatter(const int* __restrict__ src, int np, const int* __restrict__ near,
-                               const int* __restrict__ npos, const int* __restrict__ far,
-                               const int* __restrict__ fpos, int* __restrict__ near_src,
-                               int* __restrict__ far_src) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// Entry k's place in the near and far lists: its block's base (scan of the
+// block counts) plus the entries of its kind before it in the block.  The
+// first entry of each target box also records the two places, which become
+// the box's CSR offsets.
+__global__ void __launch_bounds__(kNearBlk) k_near_scatter(const int* __restrict__ src,
+                                                           const int* __restrict__ ent_t, int np,
+                                                           const uint8_t* __restrict__ flag,
+                                                           const int* __restrict__ bnoff,
+                                                           const int* __restrict__ bfoff, int* __restrict__ near_src,
+                                                           int* __restrict__ far_src, int* __restrict__ first_near,
+                                                           int* __restrict__ first_far) {
+    __shared__ int wn[kNearBlk / 64], wf[kNearBlk / 64];
+    const int k = blockIdx.x * kNearBlk + threadIdx.x;
+    const int f = k < np ? flag[k] : 0;
+    const uint64_t mn = __ballot(f & 1), mf = __ballot(f & 2);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        wn[wave] = __popcll(mn);
+        wf[wave] = __popcll(mf);
+    }
+    __syncthreads();
     if (k >= np) return;
-    if (near[k]) near_src[npos[k]] = src[k];
-    if (far[k]) far_src[fpos[k]] = src[k];
+    int pn = bnoff[blockIdx.x], pf = bfoff[blockIdx.x];
+    for (int w = 0; w < wave; ++w) {
+        pn += wn[w];
+        pf += wf[w];
+    }
+    const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    pn += __popcll(mn & lt);
+    pf += __popcll(mf & lt);
+    if (f & 1) near_src[pn] = src[k];
+    if (f & 2) far_src[pf] = src[k];
+    const int T = ent_t[k];
+    if (k == 0 || ent_t[k - 1] != T) {
+        first_near[T] = pn;
+        first_far[T] = pf;
+    }
 }
 
-// CSR offsets of the two lists (entry k of the full list lands at npos[k] /
-// fpos[k], so box b starts where its first full-list entry would land)
-__global__ void k_near_offsets(const int* __restrict__ off, int nbox, int np, const int* __restrict__ npos,
-                               const int* __restrict__ ntot, const int* __restrict__ fpos,
-                               const int* __restrict__ ftot, int* __restrict__ near_off,
-                               int* __restrict__ far_off) {
+// CSR offsets of the two lists: box b starts where the entry off[b] of the
+// full list (the first entry of the first non-empty box >= b) would land.
+__global__ void k_near_offsets(const int* __restrict__ off, const int* __restrict__ ent_t, int nbox, int np,
+                               const int* __restrict__ first_near, const int* __restrict__ ntot,
+                               const int* __restrict__ first_far, const int* __restrict__ ftot,
+                               int* __restrict__ near_off, int* __restrict__ far_off) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbox) return;
     const int k = off[b];
-    near_off[b] = k < np ? npos[k] : *ntot;
-    far_off[b] = k < np ? fpos[k] : *ftot;
+    near_off[b] = k < np ? first_near[ent_t[k]] : *ntot;
+    far_off[b] = k < np ? first_far[ent_t[k]] : *ftot;
 }
 
 // Work of each box: pairs[T] = tcount[T] * (particles of the near leaves),
@@ -174,7 +227,6 @@ void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s) {
     SFMM_LAUNCH_CHECK();
 }
 
-// ent_t: the target box of every entry
 void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_t, int nbox, int np,
                 const int* tfirst, const int* tcount, const double* tx, const double* ty, const double* tz,
                 NearLists& out, hipStream_t s) {
@@ -182,20 +234,24 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
     out.far_off.resize(nbox + 1);
     out.n_near = out.n_far = 0;
     if (nbox <= 0) return;
-    DVec<int> near, far, npos, fpos, tot;
-    const int n1 = std::max(np, 1);
-    near.resize(n1);
-    far.resize(n1);
-    npos.resize(n1);
-    fpos.resize(n1);
+    const int nb = std::max((np + kNearBlk - 1) / kNearBlk, 1);
+    DVec<uint8_t> flag;
+    DVec<int> bnear, bfar, bnoff, bfoff, first_near, first_far, tot;
+    flag.resize(std::max(np, 1));
+    bnear.resize(nb);
+    bfar.resize(nb);
+    bnoff.resize(nb);
+    bfoff.resize(nb);
+    first_near.resize(nbox);
+    first_far.resize(nbox);
     tot.resize(2);
     fill_i32(tot.data(), 2, 0, s);
     if (np > 0) {
-        k_near_flags<<<nblk(np, 256), 256, 0, s>>>(c, ent_t, src, np, tfirst, tcount, tx, ty, tz, m2p_ratio(c.p),
-                                                   m2p_min_count(c.p), near.data(), far.data());
+        k_near_flags<<<nb, kNearBlk, 0, s>>>(c, ent_t, src, np, tfirst, tcount, tx, ty, tz, m2p_ratio(c.p),
+                                             m2p_min_count(c.p), flag.data(), bnear.data(), bfar.data());
         SFMM_LAUNCH_CHECK();
-        scan_excl_i32(near.data(), npos.data(), np, tot.data(), s);
-        scan_excl_i32(far.data(), fpos.data(), np, tot.data() + 1, s);
+        scan_excl_i32(bnear.data(), bnoff.data(), nb, tot.data(), s);
+        scan_excl_i32(bfar.data(), bfoff.data(), nb, tot.data() + 1, s);
     }
     int h[2] = {0, 0};
     SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
@@ -205,12 +261,14 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
     out.near_src.resize(std::max(h[0], 1));
     out.far_src.resize(std::max(h[1], 1));
     if (np > 0) {
-        k_near_scatter<<<nblk(np, 256), 256, 0, s>>>(src, np, near.data(), npos.data(), far.data(), fpos.data(),
-                                                     out.near_src.data(), out.far_src.data());
+        k_near_scatter<<<nb, kNearBlk, 0, s>>>(src, ent_t, np, flag.data(), bnoff.data(), bfoff.data(),
+                                               out.near_src.data(), out.far_src.data(), first_near.data(),
+                                               first_far.data());
         SFMM_LAUNCH_CHECK();
     }
-    k_near_offsets<<<nblk(nbox + 1, 256), 256, 0, s>>>(off, nbox, np, npos.data(), tot.data(), fpos.data(),
-                                                       tot.data() + 1, out.near_off.data(), out.far_off.data());
+    k_near_offsets<<<nblk(nbox + 1, 256), 256, 0, s>>>(off, ent_t, nbox, np, first_near.data(), tot.data(),
+                                                       first_far.data(), tot.data() + 1, out.near_off.data(),
+                                                       out.far_off.data());
     SFMM_LAUNCH_CHECK();
     SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }

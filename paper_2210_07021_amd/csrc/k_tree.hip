@@ -300,17 +300,27 @@ void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const in
     SFMM_LAUNCH_CHECK();
 }
 
+// Sorted targets: each leaf's targets form one run.  The run's first target
+// writes tfirst, its last one the end index into tcount; k_range_counts turns
+// the end into a count (tcount starts at 0, so empty leaves stay 0).
 __global__ void k_target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     const int b = leaf[i];
     if (i == 0 || leaf[i - 1] != b) tfirst[b] = (int)i;
-    atomicAdd(&tcount[b], 1);  // integer counts: order-independent
+    if (i == m - 1 || leaf[i + 1] != b) tcount[b] = (int)(i + 1);
 }
 
-void target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount, hipStream_t s) {
+__global__ void k_range_counts(const int* tfirst, int nbox, int* tcount) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox && tcount[b] > 0) tcount[b] -= tfirst[b];
+}
+
+void target_ranges(const int* leaf, int64_t m, int nbox, int* tfirst, int* tcount, hipStream_t s) {
     if (m <= 0) return;
     k_target_ranges<<<nblocks(m, 256), 256, 0, s>>>(leaf, m, tfirst, tcount);
+    SFMM_LAUNCH_CHECK();
+    k_range_counts<<<nblocks(nbox, 256), 256, 0, s>>>(tfirst, nbox, tcount);
     SFMM_LAUNCH_CHECK();
 }
 

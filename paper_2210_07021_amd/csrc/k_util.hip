@@ -332,16 +332,16 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, 
     }
 }
 
-void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit) {
-    if (n <= 1 || bits <= begin_bit) return;
+uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint32_t* valt, int64_t n, int bits,
+                            hipStream_t s, int begin_bit, uint32_t** vout) {
+    if (vout) *vout = vals;
+    if (n <= 1 || bits <= begin_bit) return keys;
     const int nblk = (int)((n + kRsTile - 1) / kRsTile);
-    uint64_t* k2 = (uint64_t*)pool_alloc(sizeof(uint64_t) * n);
-    uint32_t* v2 = vals ? (uint32_t*)pool_alloc(sizeof(uint32_t) * n) : nullptr;
     int* hist = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
     int* offs = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
     int* dtot = (int*)pool_alloc(sizeof(int) * 256);
-    uint64_t *ka = keys, *kb = k2;
-    uint32_t *va = vals, *vb = v2;
+    uint64_t *ka = keys, *kb = kalt;
+    uint32_t *va = vals, *vb = vals ? valt : nullptr;
     const int npass = (bits - begin_bit + 7) / 8;
     if (begin_bit + 8 * npass > 64) begin_bit = 64 - 8 * npass;
     for (int pass = 0; pass < npass; ++pass) {
@@ -355,16 +355,27 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    if (npass & 1) {  // an odd number of passes leaves the result in the scratch buffers
-        SFMM_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-        if (vals) SFMM_HIP(hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-    }
     SFMM_HIP(hipStreamSynchronize(s));
-    pool_free(k2);
-    if (v2) pool_free(v2);
     pool_free(hist);
     pool_free(offs);
     pool_free(dtot);
+    if (vout) *vout = va;
+    return ka;
+}
+
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit) {
+    if (n <= 1 || bits <= begin_bit) return;
+    uint64_t* k2 = (uint64_t*)pool_alloc(sizeof(uint64_t) * n);
+    uint32_t* v2 = vals ? (uint32_t*)pool_alloc(sizeof(uint32_t) * n) : nullptr;
+    uint32_t* vr = nullptr;
+    const uint64_t* kr = radix_sort_u64_pp(keys, vals, k2, v2, n, bits, s, begin_bit, &vr);
+    if (kr != keys) {  // an odd number of passes leaves the result in the scratch buffers
+        SFMM_HIP(hipMemcpyAsync(keys, kr, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        if (vals) SFMM_HIP(hipMemcpyAsync(vals, vr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+        SFMM_HIP(hipStreamSynchronize(s));
+    }
+    pool_free(k2);
+    if (v2) pool_free(v2);
 }
 
 // ------------------------------------------------------------------ sum

@@ -267,8 +267,13 @@ void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, 
     off.resize((size_t)nbox + 1);
     src.resize(std::max(np, 1));
     if (ent) ent->resize(std::max(np, 1));
-    if (np > 0) radix_sort_u64(pairs.data(), nullptr, np, 32 + bits_for(nbox), s, 32);
-    pairs_to_csr(pairs.data(), np, nbox, off.data(), src.data(), ent ? ent->data() : nullptr, s);
+    DVec<uint64_t> alt;
+    const uint64_t* sorted = pairs.data();
+    if (np > 0) {
+        alt.resize(np);
+        sorted = radix_sort_u64_pp(pairs.data(), nullptr, alt.data(), nullptr, np, 32 + bits_for(nbox), s, 32, nullptr);
+    }
+    pairs_to_csr(sorted, np, nbox, off.data(), src.data(), ent ? ent->data() : nullptr, s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -465,7 +470,7 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     fill_i32(P.tfirst.data(), P.nbox, 0, s);
     fill_i32(P.tcount.data(), P.nbox, 0, s);
     locate_targets(P.tkeys.data(), P.M, P.child0.data(), P.level.data(), P.tleaf.data(), s);
-    target_ranges(P.tleaf.data(), P.M, P.tfirst.data(), P.tcount.data(), s);
+    target_ranges(P.tleaf.data(), P.M, P.nbox, P.tfirst.data(), P.tcount.data(), s);
     near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.p2p_ent.data(), P.nbox, P.n_p2p, P.tfirst.data(),
                P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
     P.p2p_ent.reset();  // stream-ordered pool: later work on this stream may reuse it

@@ -135,6 +135,15 @@ void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen /
                   double* rad, double* gdd /*[nb][8]*/, hipStream_t s);
 void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf,
                     hipStream_t s);
+// Queued tree levels (device-resident level bounds ls, chunk counts ccnt of
+// at least ceil(cap / kTreeChunk) entries, per-box ranks wpre of cap
+// entries, overflow flag ctl[0]).
+constexpr int kTreeChunk = 1024;
+constexpr int kWaveLevel = 65536;  // levels below this many boxes use a wave per box
+void tree_init_queued(int* ls, int nls, int* ctl, hipStream_t s);
+void tree_level_queued(int* ls, int L, int* ccnt, int* wpre, int grid, int cgrid, int cap, int* ctl, int m,
+                       int split_ok, const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                       int* parent, int* child0, hipStream_t s);
 void target_ranges(const int* leaf, int64_t m, int nbox, int* tfirst, int* tcount, hipStream_t s);
 void flag_nonzero(const int* count, int n, int* flag, hipStream_t s);
 void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t s);

@@ -112,17 +112,17 @@ void tree_split_flags(int b0, int nb, const int* level, const int* count, int m,
     SFMM_LAUNCH_CHECK();
 }
 
-__global__ void k_make_children(int b0, int nb, int child_base, const int* flag, const int* off,
-                                const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
-                                int* parent, int* child0) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int b = b0 + i;
-    if (!flag[i]) {
+// The four children of box b (pixel p at level L) when it splits (slot >= 0:
+// the split box's index among its level's split boxes, children at
+// child_base + 4 slot): each child's point range is cut from the parent's
+// sorted keys; child0[b] = -1 when it does not split.
+__device__ void children_thread(int b, int slot, int child_base, const uint64_t* __restrict__ keys, int* level,
+                                uint64_t* pixel, int* first, int* count, int* parent, int* child0) {
+    if (slot < 0) {
         child0[b] = -1;
         return;
     }
-    const int c0 = child_base + 4 * off[i];
+    const int c0 = child_base + 4 * slot;
     child0[b] = c0;
     const int L = level[b] + 1;
     const int shift = 2 * (kOrder - L);
@@ -139,6 +139,14 @@ __global__ void k_make_children(int b0, int nb, int child_base, const int* flag,
         child0[c0 + c] = -1;
         lo = e;
     }
+}
+
+__global__ void k_make_children(int b0, int nb, int child_base, const int* flag, const int* off,
+                                const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                                int* parent, int* child0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    children_thread(b0 + i, flag[i] ? off[i] : -1, child_base, keys, level, pixel, first, count, parent, child0);
 }
 
 // First index in [lo, hi) whose key is >= v (hi when none), found by the 64
@@ -166,48 +174,52 @@ __device__ int wave_lower_bound_u64(const uint64_t* __restrict__ a, int lo, int 
     return lo;
 }
 
-// k_make_children with one wave per box (levels of few, large boxes)
-__global__ void k_make_children_wave(int b0, int nb, int child_base, const int* flag, const int* off,
-                                     const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
-                                     int* parent, int* child0) {
-    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+// children_thread with the whole wave on one box (levels of few, large
+// boxes); b and slot are uniform across the wave.
+__device__ void children_wave(int b, int slot, int child_base, const uint64_t* __restrict__ keys, int* level,
+                              uint64_t* pixel, int* first, int* count, int* parent, int* child0) {
     const int lane = threadIdx.x & 63;
-    if (i >= nb) return;  // uniform across the wave
-    const int b = b0 + i;
-    if (!flag[i]) {
+    if (slot < 0) {
         if (lane == 0) child0[b] = -1;
         return;
     }
-    const int c0 = child_base + 4 * off[i];
+    const int c0 = child_base + 4 * slot;
     const int L = level[b] + 1;
     const int shift = 2 * (kOrder - L);
     const int end = first[b] + count[b];
-    int lo = first[b];
-    int e[4];
-    for (int c = 0; c < 3; ++c) {
-        const uint64_t pix = pixel[b] * 4 + (uint64_t)c;
-        e[c] = wave_lower_bound_u64(keys, lo, end, (pix + 1) << shift);
-        lo = e[c];
-    }
-    e[3] = end;
+    const int f0 = first[b];
+    const uint64_t pb = pixel[b] * 4;
+    const int e0 = wave_lower_bound_u64(keys, f0, end, (pb + 1) << shift);
+    const int e1 = wave_lower_bound_u64(keys, e0, end, (pb + 2) << shift);
+    const int e2 = wave_lower_bound_u64(keys, e1, end, (pb + 3) << shift);
     if (lane < 4) {
         const int c = lane;
-        const int st = c == 0 ? first[b] : e[c - 1];
+        const int st = c == 0 ? f0 : c == 1 ? e0 : c == 2 ? e1 : e2;
+        const int en = c == 0 ? e0 : c == 1 ? e1 : c == 2 ? e2 : end;
         level[c0 + c] = L;
-        pixel[c0 + c] = pixel[b] * 4 + (uint64_t)c;
+        pixel[c0 + c] = pb + (uint64_t)c;
         first[c0 + c] = st;
-        count[c0 + c] = e[c] - st;
+        count[c0 + c] = en - st;
         parent[c0 + c] = b;
         child0[c0 + c] = -1;
     }
     if (lane == 0) child0[b] = c0;
 }
 
+// k_make_children with one wave per box
+__global__ void k_make_children_wave(int b0, int nb, int child_base, const int* flag, const int* off,
+                                     const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                                     int* parent, int* child0) {
+    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (i >= nb) return;  // uniform across the wave
+    children_wave(b0 + i, flag[i] ? off[i] : -1, child_base, keys, level, pixel, first, count, parent, child0);
+}
+
 void tree_make_children(int b0, int nb, int child_base, const int* flag, const int* off, const uint64_t* keys,
                         int* level, uint64_t* pixel, int* first, int* count, int* parent, int* child0,
                         hipStream_t s) {
     if (nb <= 0) return;
-    if (nb < 65536) {
+    if (nb < kWaveLevel) {
         k_make_children_wave<<<nblocks((int64_t)nb * 64, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys,
                                                                            level, pixel, first, count, parent,
                                                                            child0);
@@ -215,6 +227,135 @@ void tree_make_children(int b0, int nb, int child_base, const int* flag, const i
         k_make_children<<<nblocks(nb, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys, level, pixel, first,
                                                         count, parent, child0);
     }
+    SFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ queued levels
+// The same level loop with the level bounds in device memory (ls[L] ..
+// ls[L+1] - 1 are level L's boxes), so levels run back to back without a
+// read-back each: per level, split counts per chunk of kTreeChunk boxes, one
+// workgroup scanning the chunk counts (and setting ls[L+2], or the overflow
+// flag ctl[0] when the children would pass the capacity), then the children.
+constexpr int kTreeThreads = 256;
+constexpr int kTreePer = kTreeChunk / kTreeThreads;
+
+__device__ int tree_block_excl(int v, int* sh, int* total) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kTreeThreads / 64; ++w) {
+        const int ws = sh[w];
+        before += (w < wv) ? ws : 0;
+        all += ws;
+    }
+    *total = all;
+    __syncthreads();
+    return before + x - v;
+}
+
+__global__ void k_tree_init(int* ls, int nls, int* ctl) {
+    const int t = threadIdx.x;
+    if (t < nls) ls[t] = (t == 0) ? 0 : 12;
+    if (t == 0) ctl[0] = 0;
+}
+
+// Per chunk: the split count, and for each box its rank among the chunk's
+// split boxes (wpre, -1 when it does not split).
+__global__ void __launch_bounds__(kTreeThreads) k_tree_count(const int* ls, int L, const int* count, int m,
+                                                              int split_ok, int* ccnt, int* wpre) {
+    __shared__ int sh[kTreeThreads / 64];
+    const int b0 = ls[L], nb = ls[L + 1] - b0;
+    const int nch = (nb + kTreeChunk - 1) / kTreeChunk;
+    for (int j = blockIdx.x; j < nch; j += gridDim.x) {
+        const int i0 = j * kTreeChunk + threadIdx.x * kTreePer;
+        int f[kTreePer], c = 0;
+#pragma unroll
+        for (int q = 0; q < kTreePer; ++q) {
+            f[q] = (split_ok && i0 + q < nb && count[b0 + i0 + q] > m) ? 1 : 0;
+            c += f[q];
+        }
+        int tot;
+        int e = tree_block_excl(c, sh, &tot);
+#pragma unroll
+        for (int q = 0; q < kTreePer; ++q) {
+            if (i0 + q < nb) wpre[i0 + q] = f[q] ? e : -1;
+            e += f[q];
+        }
+        if (threadIdx.x == 0) ccnt[j] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(kTreeThreads) k_tree_scan(int* ls, int L, int* ccnt, int cap, int* ctl) {
+    __shared__ int sh[kTreeThreads / 64];
+    const int nb = ls[L + 1] - ls[L];
+    const int nch = (nb + kTreeChunk - 1) / kTreeChunk;
+    int carry = 0;
+    for (int c0 = 0; c0 < nch; c0 += kTreeThreads) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nch ? ccnt[i] : 0;
+        int tot;
+        const int e = tree_block_excl(v, sh, &tot);
+        if (i < nch) ccnt[i] = carry + e;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const int64_t need = (int64_t)ls[L + 1] + 4 * (int64_t)carry;
+        if (ctl[0] || need > cap) {
+            ctl[0] = 1;
+            ls[L + 2] = ls[L + 1];
+        } else {
+            ls[L + 2] = (int)need;
+        }
+    }
+}
+
+// Children of every box of the level: a wave per box on levels of fewer
+// than kWaveLevel boxes, else a thread per box (grid-stride either way).
+__global__ void __launch_bounds__(kTreeThreads) k_tree_children(const int* ls, int L, const int* ccnt,
+                                                                 const int* wpre, const int* ctl,
+                                                                 const uint64_t* __restrict__ keys, int* level,
+                                                                 uint64_t* pixel, int* first, int* count,
+                                                                 int* parent, int* child0) {
+    if (ctl[0]) return;
+    const int b0 = ls[L], nb = ls[L + 1] - b0, child_base = ls[L + 1];
+    if (nb < kWaveLevel) {
+        const int nw = gridDim.x * (kTreeThreads / 64);
+        for (int i = blockIdx.x * (kTreeThreads / 64) + (threadIdx.x >> 6); i < nb; i += nw) {
+            const int r = wpre[i];
+            children_wave(b0 + i, r >= 0 ? ccnt[i / kTreeChunk] + r : -1, child_base, keys, level, pixel, first,
+                          count, parent, child0);
+        }
+    } else {
+        for (int i = blockIdx.x * kTreeThreads + threadIdx.x; i < nb; i += gridDim.x * kTreeThreads) {
+            const int r = wpre[i];
+            children_thread(b0 + i, r >= 0 ? ccnt[i / kTreeChunk] + r : -1, child_base, keys, level, pixel, first,
+                            count, parent, child0);
+        }
+    }
+}
+
+void tree_init_queued(int* ls, int nls, int* ctl, hipStream_t s) {
+    k_tree_init<<<1, 64, 0, s>>>(ls, nls, ctl);
+    SFMM_LAUNCH_CHECK();
+}
+
+void tree_level_queued(int* ls, int L, int* ccnt, int* wpre, int grid, int cgrid, int cap, int* ctl, int m,
+                       int split_ok, const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
+                       int* parent, int* child0, hipStream_t s) {
+    k_tree_count<<<grid, kTreeThreads, 0, s>>>(ls, L, count, m, split_ok, ccnt, wpre);
+    SFMM_LAUNCH_CHECK();
+    k_tree_scan<<<1, kTreeThreads, 0, s>>>(ls, L, ccnt, cap, ctl);
+    SFMM_LAUNCH_CHECK();
+    k_tree_children<<<cgrid, kTreeThreads, 0, s>>>(ls, L, ccnt, wpre, ctl, keys, level, pixel, first, count, parent,
+                                                   child0);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -216,16 +216,11 @@ void sort_points(const double* in, const double* q_in, int64_t n, DVec<double4>*
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
-void build_tree(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
-    const int stage_tree = prof.begin(S_TREE);
-    const int m = P.opt.leaf_size;
-    size_t cap = 12 + 8 * (size_t)(P.N / std::max(1, m)) + 64;
-    P.level.resize(cap);
-    P.pixel.resize(cap);
-    P.first.resize(cap);
-    P.count.resize(cap);
-    P.parent.resize(cap);
-    P.child0.resize(cap);
+constexpr int kTreeBatch = 8;  // queued levels between two read-backs
+
+// Levels with a host read of the split count after each: the arrays grow as
+// needed.
+void build_levels_exact(sfmm_plan_impl& P, int m, hipStream_t s) {
     tree_base_level(P.skeys.data(), P.N, P.level.data(), P.pixel.data(), P.first.data(), P.count.data(),
                     P.parent.data(), P.child0.data(), s);
     P.lvl_start.assign({0, 12});
@@ -251,6 +246,62 @@ void build_tree(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
                            P.first.data(), P.count.data(), P.parent.data(), P.child0.data(), s);
         P.lvl_start.push_back((int)need);
     }
+}
+
+// Levels queued kTreeBatch at a time with the level bounds on the device;
+// false when the children of some level would pass cap boxes (nothing of
+// the partial build is kept then).
+bool build_levels_queued(sfmm_plan_impl& P, int m, int cap, hipStream_t s) {
+    constexpr int kLs = 32;  // level bounds ls[0 .. max_level + 2]
+    DVec<int> ls, ctl, ccnt, wpre;
+    ls.resize(kLs);
+    ctl.resize(1);
+    const int nch = (cap + kTreeChunk - 1) / kTreeChunk;
+    ccnt.resize(nch);
+    wpre.resize(cap);
+    const int grid = std::min(nch, 1024);
+    const int cgrid = 2048;  // 8192 waves
+    tree_base_level(P.skeys.data(), P.N, P.level.data(), P.pixel.data(), P.first.data(), P.count.data(),
+                    P.parent.data(), P.child0.data(), s);
+    tree_init_queued(ls.data(), kLs, ctl.data(), s);
+    const int lmax = P.opt.max_level;
+    int* h = P.pin->p;
+    for (int L = 0;;) {
+        const int Lend = std::min(L + kTreeBatch, lmax + 1);
+        for (; L < Lend; ++L)
+            tree_level_queued(ls.data(), L, ccnt.data(), wpre.data(), grid, cgrid, cap, ctl.data(), m,
+                              L < lmax ? 1 : 0, P.skeys.data(), P.level.data(), P.pixel.data(), P.first.data(), P.count.data(),
+                              P.parent.data(), P.child0.data(), s);
+        SFMM_HIP(hipMemcpyAsync(h, ls.data(), sizeof(int) * kLs, hipMemcpyDeviceToHost, s));
+        SFMM_HIP(hipMemcpyAsync(h + kLs, ctl.data(), sizeof(int), hipMemcpyDeviceToHost, s));
+        SFMM_HIP(hipStreamSynchronize(s));
+        if (h[kLs]) return false;
+        // the first level that split nothing ends the tree
+        for (int z = 0; z < L; ++z) {
+            if (h[z + 2] == h[z + 1]) {
+                P.lvl_start.assign(h, h + z + 2);
+                return true;
+            }
+        }
+        if (L > lmax) throw Error(ST_INTERNAL, "tree levels did not terminate");
+    }
+}
+
+void build_tree(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
+    const int stage_tree = prof.begin(S_TREE);
+    const int m = P.opt.leaf_size;
+    size_t cap = 12 + 8 * (size_t)(P.N / std::max(1, m)) + 64;
+    // SFMM_TREE_CAP (boxes) overrides the capacity of the queued levels:
+    // tests use it to drive the fallback
+    if (const char* forced = std::getenv("SFMM_TREE_CAP")) cap = std::max<size_t>(12, std::strtoull(forced, nullptr, 10));
+    cap = std::min<size_t>(cap, 0x7fffffff);
+    P.level.resize(cap);
+    P.pixel.resize(cap);
+    P.first.resize(cap);
+    P.count.resize(cap);
+    P.parent.resize(cap);
+    P.child0.resize(cap);
+    if (!build_levels_queued(P, m, (int)cap, s)) build_levels_exact(P, m, s);
     prof.end(stage_tree);
     P.nbox = P.lvl_start.back();
     P.cen.resize(4 * (size_t)P.nbox);
@@ -598,7 +649,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         if (N > 0) {
             DVec<double> qt;
             qt.resize(1);
-            sum_f64(reinterpret_cast<const double*>(P->spt.data()) + 3, N, qt.data(), s, 4);  // the q of every record
+            sum_f64(q, N, qt.data(), s);  // the caller's charges, contiguous
             SFMM_HIP(hipMemcpy(&P->q_total, qt.data(), sizeof(double), hipMemcpyDeviceToHost));
         }
         build_tree(*P, s, prof);

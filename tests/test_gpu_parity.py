@@ -269,3 +269,33 @@ def test_walk_overflow_reruns_exactly(ratio, monkeypatch, oracle_lib):
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
     ref.close()
     plan.close()
+
+
+@pytest.mark.parametrize("cap", ["12", "700"])
+def test_tree_overflow_rebuilds_exactly(cap, monkeypatch, oracle_lib):
+    """The queued tree levels with a box capacity too small for the tree
+    (SFMM_TREE_CAP boxes) give up and rebuild level by level with exact
+    sizing: same box table, lists and bit-identical results as a plan with
+    the default capacity."""
+    import torch
+    src, q, tgt = skies.workload("clustered-1e6", scale=0.02)
+    tgt = tgt[:, ::11].copy()
+    sf = _sf()
+    _say(f"[tree overflow] cap {cap}: N={src.shape[1]} M={tgt.shape[1]}")
+    ref = sf.Plan(src, q, tgt, tolerance=1e-8, leaf_size=16)
+    a1, b1 = ref.execute()
+    monkeypatch.setenv("SFMM_TREE_CAP", cap)
+    plan = sf.Plan(src, q, tgt, tolerance=1e-8, leaf_size=16)
+    monkeypatch.delenv("SFMM_TREE_CAP")
+    a2, b2 = plan.execute()
+    torch.cuda.synchronize()
+    assert ref.stats()["n_boxes"] > int(cap)
+    t1, t2 = ref.export_boxes(), plan.export_boxes()
+    for f in ("level", "pixel", "first", "count", "parent", "child0", "centre", "radius"):
+        assert np.array_equal(t1[f], t2[f]), f
+    m1, p1 = ref.export_lists()
+    m2, p2 = plan.export_lists()
+    assert np.array_equal(m1, m2) and np.array_equal(p1, p2)
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+    ref.close()
+    plan.close()

@@ -176,15 +176,12 @@ void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd,
 struct WalkCaps {
     int frontier, m2l, p2p;
 };
-struct WalkScratch {
-    int chunks, threads;  // chunks of a round of n pairs, and threads = chunks x block size
-};
-WalkScratch walk_scratch_sizes(int n);
-void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* toff, int tstride,
-                     int* ctot, int* coff, int cstride, int* tot, int grid, hipStream_t s);
-void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* toff,
-                     int tstride, const int* coff, int cstride, const int* tot, const WalkCaps& cap, int2* Fnext,
-                     uint64_t* m2l, uint64_t* p2p, int* st_next, int* overflow, int grid, hipStream_t s);
+int walk_chunks(int n);  // chunks of a round of n pairs (at least 1)
+void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* ctot, int* coff,
+                     int cstride, int* tot, int grid, hipStream_t s);
+void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* coff,
+                     int cstride, const int* tot, const WalkCaps& cap, int2* Fnext, uint64_t* m2l, uint64_t* p2p,
+                     int* st_next, int* overflow, int grid, hipStream_t s);
 void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
                     hipStream_t s);
 // precision tier: M2L into boxes of levels <= kFp32CoarseLevel stays FP64

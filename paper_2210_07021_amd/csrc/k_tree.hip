@@ -497,13 +497,13 @@ enum : uint8_t { A_NONE = 0, A_M2L = 1, A_P2P = 2, A_SPLIT_S = 3, A_SPLIT_T = 4,
 // One round of the walk in three launches, sized on the device: the round's
 // frontier size and output bases sit in st[0..2] (written by the previous
 // round's emit), so rounds can be queued without reading anything back.  The
-// pairs are taken in chunks of kWalkChunk, chunk c by workgroup c mod grid.
-// Thread g of chunk c classifies pairs 4g .. 4g+3 of the chunk and the
-// workgroup scans the three counts of its threads (children pairs, M2L
-// pairs, P2P pairs); k_walk_chunk_scan scans the chunk totals;
-// k_walk_emit writes each thread's outputs from its base offsets, in pair
-// order (so the lists come out in the same order as a scan over single
-// pairs).
+// pairs are taken in chunks of kWalkChunk, chunk c by workgroup c mod grid,
+// in kWalkItems passes of kWalkThreads consecutive pairs (lane order = pair
+// order).  k_walk_classify writes each pair's action and the chunk's three
+// totals (children pairs, M2L pairs, P2P pairs); k_walk_chunk_scan scans the
+// chunk totals; k_walk_emit scans the chunk's actions again and writes every
+// output at its place in pair order, consecutive lanes to consecutive slots
+// (so the lists come out in the same order as a scan over single pairs).
 constexpr int kWalkItems = 4, kWalkThreads = 256, kWalkChunk = kWalkItems * kWalkThreads;
 
 __device__ __forceinline__ int walk_nchild(uint8_t a) {
@@ -560,14 +560,41 @@ __device__ uint8_t walk_action_tie(const WalkCtx& w, int s, int t) {
     return A_P2P;
 }
 
+// Three counts of a thread summed over the workgroup (kWalkThreads):
+// exclusive prefix in thread order (ex) and total (all).
+__device__ __forceinline__ void walk_block_scan3(const int c[3], int (*sh)[kWalkThreads / 64], int ex[3], int all[3]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        x[j] = c[j];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x[j], o, 64);
+            if (lane >= o) x[j] += y;
+        }
+        if (lane == 63) sh[j][wv] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int v = 0; v < kWalkThreads / 64; ++v) {
+            before += v < wv ? sh[j][v] : 0;
+            tot += sh[j][v];
+        }
+        ex[j] = before + x[j] - c[j];
+        all[j] = tot;
+    }
+    __syncthreads();  // sh is reused by the caller
+}
+
 // Classification of each chunk: FP64 decisions first; the near-ties of the
 // chunk are gathered in LDS and decided exactly by consecutive threads (no
-// wave runs that code for one lane); then the three counts of every thread
-// (children pairs, M2L pairs, P2P pairs) are scanned across the workgroup:
-// toff per thread, ctot per chunk.
+// wave runs that code for one lane); then the chunk's three totals.
 __global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __restrict__ F, const int* __restrict__ st,
                                                                 WalkCtx w, uint8_t* __restrict__ action,
-                                                                int* __restrict__ toff, int tstride,
                                                                 int* __restrict__ ctot, int cstride) {
     __shared__ int sh[3][kWalkThreads / 64];
     __shared__ int ntie;
@@ -575,65 +602,48 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __re
     __shared__ uint8_t tie_act[kWalkChunk];
     const int n = st[0];
     const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int g = ch * kWalkThreads + threadIdx.x;
+        const int k0 = ch * kWalkChunk;
         if (threadIdx.x == 0) ntie = 0;
         __syncthreads();
         uint8_t act[kWalkItems];
 #pragma unroll
         for (int i = 0; i < kWalkItems; ++i) {
-            const int k = g * kWalkItems + i;
+            const int li = i * kWalkThreads + threadIdx.x;
             act[i] = A_NONE;
-            if (k < n) {
-                const int2 f = F[k];
+            if (k0 + li < n) {
+                const int2 f = F[k0 + li];
                 act[i] = walk_action_fast(w, f.x, f.y);
-                if (act[i] == A_TIE) tie_at[atomicAdd(&ntie, 1)] = (short)(threadIdx.x * kWalkItems + i);
+                if (act[i] == A_TIE) tie_at[atomicAdd(&ntie, 1)] = (short)li;
             }
         }
         __syncthreads();
         for (int j = threadIdx.x; j < ntie; j += kWalkThreads) {
             const int li = tie_at[j];
-            const int2 f = F[ch * kWalkChunk + li];
+            const int2 f = F[k0 + li];
             tie_act[li] = walk_action_tie(w, f.x, f.y);
         }
         __syncthreads();
         int c[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < kWalkItems; ++i) {
-            const int k = g * kWalkItems + i;
-            if (k < n) {
-                const uint8_t a = act[i] == A_TIE ? tie_act[threadIdx.x * kWalkItems + i] : act[i];
-                action[k] = a;
+            const int li = i * kWalkThreads + threadIdx.x;
+            if (k0 + li < n) {
+                const uint8_t a = act[i] == A_TIE ? tie_act[li] : act[i];
+                action[k0 + li] = a;
                 c[0] += walk_nchild(a);
                 c[1] += a == A_M2L;
                 c[2] += a == A_P2P;
             }
         }
+        int ex[3], all[3];
+        walk_block_scan3(c, sh, ex, all);
+        if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            int x = c[j];
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            if (lane == 63) sh[j][wv] = x;
-            c[j] = x - c[j];  // exclusive within the wave
+            for (int j = 0; j < 3; ++j) ctot[(size_t)j * cstride + ch] = all[j];
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            int before = 0, all = 0;
-#pragma unroll
-            for (int v = 0; v < kWalkThreads / 64; ++v) {
-                before += v < wv ? sh[j][v] : 0;
-                all += sh[j][v];
-            }
-            toff[(size_t)j * tstride + g] = before + c[j];
-            if (threadIdx.x == 0) ctot[(size_t)j * cstride + ch] = all;
-        }
-        __syncthreads();  // sh, ntie and the tie lists are reused by the next chunk
+        // sh, ntie and the tie lists are reused by the next chunk (the scan
+        // ends with a barrier)
     }
 }
 
@@ -682,12 +692,12 @@ __device__ uint64_t pair_key(int s, int t) { return ((uint64_t)(uint32_t)t << 32
 // writes the next round's st (frontier size, M2L and P2P bases).
 __global__ void __launch_bounds__(kWalkThreads) k_walk_emit(const int2* __restrict__ F, const int* __restrict__ st,
                                                             WalkCtx w, const uint8_t* __restrict__ action,
-                                                            const int* __restrict__ toff, int tstride,
                                                             const int* __restrict__ coff, int cstride,
                                                             const int* __restrict__ tot, WalkCaps cap,
                                                             int2* __restrict__ Fnext, uint64_t* __restrict__ m2l,
                                                             uint64_t* __restrict__ p2p, int* __restrict__ st_next,
                                                             int* __restrict__ overflow) {
+    __shared__ int sh[3][kWalkThreads / 64];
     const int n = st[0], bm = st[1], bp = st[2];
     const int nc = tot[0], am = tot[1], ap = tot[2];
     const bool fits = nc <= cap.frontier && (int64_t)bm + am <= cap.m2l && (int64_t)bp + ap <= cap.p2p;
@@ -706,59 +716,60 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_emit(const int2* __restri
     if (!fits) return;
     const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
     for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int g = ch * kWalkThreads + threadIdx.x;
-        if (g * kWalkItems >= n) continue;
-        int oc = coff[ch] + toff[g];
-        int om = bm + coff[(size_t)cstride + ch] + toff[(size_t)tstride + g];
-        int op = bp + coff[2 * (size_t)cstride + ch] + toff[2 * (size_t)tstride + g];
-#pragma unroll
-        for (int i = 0; i < kWalkItems; ++i) {
-            const int k = g * kWalkItems + i;
-            if (k >= n) break;
-            const int s = F[k].x, t = F[k].y;
-            const uint8_t a = action[k];
-            int2* out = Fnext + oc;
-            switch (a) {
-                case A_M2L: m2l[om++] = pair_key(s, t); break;
-                case A_P2P: p2p[op++] = pair_key(s, t); break;
-                case A_SPLIT_S:
-                    for (int q = 0; q < 4; ++q) out[q] = make_int2(w.cc[s].x + q, t);
-                    break;
-                case A_SPLIT_T:
-                    for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.cc[t].x + q);
-                    break;
-                case A_SPLIT_SELF:
-                    for (int q = 0; q < 4; ++q)
-                        for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.cc[s].x + q, w.cc[s].x + r);
-                    break;
-                default: break;
+        const int k0 = ch * kWalkChunk;
+        int oc = coff[ch];
+        int om = bm + coff[(size_t)cstride + ch];
+        int op = bp + coff[2 * (size_t)cstride + ch];
+        for (int i = 0; i < kWalkItems && k0 + i * kWalkThreads < n; ++i) {  // uniform across the workgroup
+            const int k = k0 + i * kWalkThreads + threadIdx.x;
+            const uint8_t a = k < n ? action[k] : A_NONE;
+            const int c[3] = {walk_nchild(a), a == A_M2L, a == A_P2P};
+            int ex[3], all[3];
+            walk_block_scan3(c, sh, ex, all);
+            if (a != A_NONE) {
+                const int s = F[k].x, t = F[k].y;
+                int2* out = Fnext + oc + ex[0];
+                switch (a) {
+                    case A_M2L: m2l[om + ex[1]] = pair_key(s, t); break;
+                    case A_P2P: p2p[op + ex[2]] = pair_key(s, t); break;
+                    case A_SPLIT_S:
+                        for (int q = 0; q < 4; ++q) out[q] = make_int2(w.cc[s].x + q, t);
+                        break;
+                    case A_SPLIT_T:
+                        for (int q = 0; q < 4; ++q) out[q] = make_int2(s, w.cc[t].x + q);
+                        break;
+                    case A_SPLIT_SELF:
+                        for (int q = 0; q < 4; ++q)
+                            for (int r = 0; r < 4; ++r) out[4 * q + r] = make_int2(w.cc[s].x + q, w.cc[s].x + r);
+                        break;
+                    default: break;
+                }
             }
-            oc += walk_nchild(a);
+            oc += all[0];
+            om += all[1];
+            op += all[2];
         }
     }
 }
 
-WalkScratch walk_scratch_sizes(int n) {
-    WalkScratch z;
+int walk_chunks(int n) {
     const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
-    z.chunks = nchunk > 0 ? nchunk : 1;
-    z.threads = z.chunks * kWalkThreads;
-    return z;
+    return nchunk > 0 ? nchunk : 1;
 }
 
-void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* toff, int tstride,
-                     int* ctot, int* coff, int cstride, int* tot, int grid, hipStream_t s) {
-    k_walk_classify<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, toff, tstride, ctot, cstride);
+void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* action, int* ctot, int* coff,
+                     int cstride, int* tot, int grid, hipStream_t s) {
+    k_walk_classify<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, ctot, cstride);
     SFMM_LAUNCH_CHECK();
     k_walk_chunk_scan<<<3, 256, 0, s>>>(st, ctot, cstride, coff, tot);
     SFMM_LAUNCH_CHECK();
 }
 
-void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* toff,
-                     int tstride, const int* coff, int cstride, const int* tot, const WalkCaps& cap, int2* Fnext,
-                     uint64_t* m2l, uint64_t* p2p, int* st_next, int* overflow, int grid, hipStream_t s) {
-    k_walk_emit<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, toff, tstride, coff, cstride, tot, cap, Fnext, m2l, p2p,
-                                             st_next, overflow);
+void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* coff,
+                     int cstride, const int* tot, const WalkCaps& cap, int2* Fnext, uint64_t* m2l, uint64_t* p2p,
+                     int* st_next, int* overflow, int grid, hipStream_t s) {
+    k_walk_emit<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, coff, cstride, tot, cap, Fnext, m2l, p2p, st_next,
+                                             overflow);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -369,7 +369,7 @@ bool walk(sfmm_plan_impl& P, const WalkCtx& w, bool exact, DVec<uint64_t>& m2l, 
     m2l.resize(cap.m2l);
     p2p.resize(cap.p2p);
     DVec<uint8_t> action;
-    DVec<int> toff, ctot, coff, tot, rs;
+    DVec<int> ctot, coff, tot, rs;
     tot.resize(3);
     rs.resize(4 * (kWalkMaxRounds + 1) + 1);
     int* overflow = rs.data() + 4 * (kWalkMaxRounds + 1);
@@ -378,23 +378,20 @@ bool walk(sfmm_plan_impl& P, const WalkCtx& w, bool exact, DVec<uint64_t>& m2l, 
     SFMM_HIP(hipMemcpyAsync(rs.data(), st0, sizeof(st0), hipMemcpyHostToDevice, s));
     SFMM_HIP(hipMemcpyAsync(F.data(), f0.data(), f0.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     int n = n0, rounds = 0;
-    WalkScratch z = walk_scratch_sizes(exact ? n0 : cap.frontier);
+    int nch = walk_chunks(exact ? n0 : cap.frontier);
     action.resize(exact ? n0 : cap.frontier);
-    toff.resize(3 * (size_t)z.threads);
-    ctot.resize(3 * (size_t)z.chunks);
-    coff.resize(3 * (size_t)z.chunks);
+    ctot.resize(3 * (size_t)nch);
+    coff.resize(3 * (size_t)nch);
     for (int r = 0; r < kWalkMaxRounds; ++r) {
         const int* st = rs.data() + 4 * r;
         int* st_next = rs.data() + 4 * (r + 1);
         if (exact) {
-            z = walk_scratch_sizes(n);
+            nch = walk_chunks(n);
             action.resize(std::max(n, 1));
-            toff.resize(3 * (size_t)z.threads);
-            ctot.resize(3 * (size_t)z.chunks);
-            coff.resize(3 * (size_t)z.chunks);
-            const int grid = std::min(kWalkGrid, z.chunks);
-            walk_round_scan(F.data(), st, w, action.data(), toff.data(), z.threads, ctot.data(), coff.data(),
-                            z.chunks, tot.data(), grid, s);
+            ctot.resize(3 * (size_t)nch);
+            coff.resize(3 * (size_t)nch);
+            const int grid = std::min(kWalkGrid, nch);
+            walk_round_scan(F.data(), st, w, action.data(), ctot.data(), coff.data(), nch, tot.data(), grid, s);
             SFMM_HIP(hipMemcpyAsync(P.pin->p, tot.data(), 3 * sizeof(int), hipMemcpyDeviceToHost, s));
             SFMM_HIP(hipMemcpyAsync(P.pin->p + 3, st, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
             SFMM_HIP(hipStreamSynchronize(s));
@@ -407,14 +404,13 @@ bool walk(sfmm_plan_impl& P, const WalkCtx& w, bool exact, DVec<uint64_t>& m2l, 
             cap.frontier = std::max(nc, 1);
             cap.m2l = (int)m2l.n;
             cap.p2p = (int)p2p.n;
-            walk_round_emit(F.data(), st, w, action.data(), toff.data(), z.threads, coff.data(), z.chunks, tot.data(),
-                            cap, G.data(), m2l.data(), p2p.data(), st_next, overflow, grid, s);
+            walk_round_emit(F.data(), st, w, action.data(), coff.data(), nch, tot.data(), cap, G.data(), m2l.data(),
+                            p2p.data(), st_next, overflow, grid, s);
             n = nc;
         } else {
-            walk_round_scan(F.data(), st, w, action.data(), toff.data(), z.threads, ctot.data(), coff.data(),
-                            z.chunks, tot.data(), kWalkGrid, s);
-            walk_round_emit(F.data(), st, w, action.data(), toff.data(), z.threads, coff.data(), z.chunks, tot.data(),
-                            cap, G.data(), m2l.data(), p2p.data(), st_next, overflow, kWalkGrid, s);
+            walk_round_scan(F.data(), st, w, action.data(), ctot.data(), coff.data(), nch, tot.data(), kWalkGrid, s);
+            walk_round_emit(F.data(), st, w, action.data(), coff.data(), nch, tot.data(), cap, G.data(), m2l.data(),
+                            p2p.data(), st_next, overflow, kWalkGrid, s);
             if ((r + 1) % kWalkBatch == 0) {
                 SFMM_HIP(hipMemcpyAsync(P.pin->p, st_next, sizeof(int), hipMemcpyDeviceToHost, s));
                 SFMM_HIP(hipStreamSynchronize(s));

@@ -187,8 +187,10 @@ sfmm_status sfmm_export_lists(sfmm_plan_t plan, int64_t* m2l_src, int64_t* m2l_t
                               int64_t* p2p_tgt);
 
 /* Host copies of the order-29 keys: src_keys [N] ascending with src_perm
- * [N] the caller index of each, tgt_keys [M] ascending with tgt_perm [M],
- * tgt_leaf [M] the leaf box of each sorted target. */
+ * [N] the caller index of each; for the targets in plan order (grouped by
+ * leaf box, ascending box index, caller order within a leaf) tgt_perm [M]
+ * the caller index, tgt_keys [M] the key and tgt_leaf [M] the leaf box of
+ * each. */
 sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_perm, uint64_t* tgt_keys,
                              int64_t* tgt_perm, int64_t* tgt_leaf);
 

@@ -121,8 +121,8 @@ void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 // than 1e-14, and compute their order-29 keys.
 void prepare_points(const double* in, const double* q /*nullable*/, int64_t n, double4* u /*[n] x,y,z,q*/,
                     uint64_t* keys, uint32_t* idx, int* err, hipStream_t s);
-void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
-                   hipStream_t s);
+void gather_targets(const uint32_t* idx, const uint64_t* leaf_sorted, int64_t n, const double4* u, double* ox,
+                    double* oy, double* oz, int* leaf, hipStream_t s);
 void gather_records(const uint32_t* idx, int64_t n, const double4* u, double4* out, hipStream_t s);
 void tree_base_level(const uint64_t* keys, int64_t n, int* level, uint64_t* pixel, int* first, int* count,
                      int* parent, int* child0, hipStream_t s);
@@ -133,7 +133,7 @@ void tree_make_children(int b0, int nb, int child_base, const int* flag, const i
                         hipStream_t s);
 void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen /*[nb][4]: x,y,z,rho*/,
                   double* rad, double* gdd /*[nb][8]*/, hipStream_t s);
-void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf,
+void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, uint64_t* leaf,
                     hipStream_t s);
 // Queued tree levels (device-resident level bounds ls, chunk counts ccnt of
 // at least ceil(cap / kTreeChunk) entries, per-box ranks wpre of cap

@@ -41,20 +41,23 @@ void prepare_points(const double* in, const double* q, int64_t n, double4* u, ui
     SFMM_LAUNCH_CHECK();
 }
 
-__global__ void k_gather_points(const uint32_t* idx, int64_t n, const double4* __restrict__ u, double* ox,
-                                double* oy, double* oz) {
+// Targets in plan order: coordinates (SoA) and leaf box of the target at
+// each position, from the leaf-sorted (leaf, index) pairs.
+__global__ void k_gather_targets(const uint32_t* idx, const uint64_t* leaf_sorted, int64_t n,
+                                 const double4* __restrict__ u, double* ox, double* oy, double* oz, int* leaf) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 v = u[idx[i]];
     ox[i] = v.x;
     oy[i] = v.y;
     oz[i] = v.z;
+    leaf[i] = (int)leaf_sorted[i];
 }
 
-void gather_points(const uint32_t* idx, int64_t n, const double4* u, double* ox, double* oy, double* oz,
-                   hipStream_t s) {
+void gather_targets(const uint32_t* idx, const uint64_t* leaf_sorted, int64_t n, const double4* u, double* ox,
+                    double* oy, double* oz, int* leaf, hipStream_t s) {
     if (n <= 0) return;
-    k_gather_points<<<nblocks(n, 256), 256, 0, s>>>(idx, n, u, ox, oy, oz);
+    k_gather_targets<<<nblocks(n, 256), 256, 0, s>>>(idx, leaf_sorted, n, u, ox, oy, oz, leaf);
     SFMM_LAUNCH_CHECK();
 }
 
@@ -422,7 +425,9 @@ void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd,
 }
 
 // ------------------------------------------------------------------ targets
-__global__ void k_locate(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf) {
+// Leaf box of each target from its key (any order of the targets), as the
+// 64-bit sort key of the target order.
+__global__ void k_locate(const uint64_t* keys, int64_t m, const int* child0, const int* level, uint64_t* leaf) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     const uint64_t k = keys[i];
@@ -431,17 +436,17 @@ __global__ void k_locate(const uint64_t* keys, int64_t m, const int* child0, con
         const int L = level[b] + 1;
         b = child0[b] + (int)((k >> (2 * (kOrder - L))) & 3);
     }
-    leaf[i] = b;
+    leaf[i] = (uint64_t)b;
 }
 
-void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, int* leaf,
+void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, uint64_t* leaf,
                     hipStream_t s) {
     if (m <= 0) return;
     k_locate<<<nblocks(m, 256), 256, 0, s>>>(keys, m, child0, level, leaf);
     SFMM_LAUNCH_CHECK();
 }
 
-// Sorted targets: each leaf's targets form one run.  The run's first target
+// Targets in plan order: each leaf's targets form one run.  The run's first target
 // writes tfirst, its last one the end index into tcount; k_range_counts turns
 // the end into a count (tcount starts at 0, so empty leaves stay 0).
 __global__ void k_target_ranges(const int* leaf, int64_t m, int* tfirst, int* tcount) {

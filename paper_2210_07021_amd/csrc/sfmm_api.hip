@@ -188,31 +188,31 @@ void validate(const sfmm_options& o) {
 // Sort points by key and keep the permutation; outputs resized here: the
 // sorted points as (x, y, z, q) records (sources, rec != nullptr) or as three
 // coordinate arrays (targets).
-void sort_points(const double* in, const double* q_in, int64_t n, DVec<double4>* rec, DVec<double>* ox,
-                 DVec<double>* oy, DVec<double>* oz, DVec<uint32_t>& perm, DVec<uint64_t>& keys,
-                 sfmm_plan_impl& P, hipStream_t s, const char* what) {
-    if (rec) {
-        rec->resize(n);
-    } else {
-        ox->resize(n);
-        oy->resize(n);
-        oz->resize(n);
-    }
+// Keys, records in caller order and the identity permutation; throws on
+// non-finite points or points off the unit sphere.
+void prepare_checked(const double* in, const double* q_in, int64_t n, DVec<double4>& u, DVec<uint64_t>& keys,
+                     DVec<uint32_t>& perm, sfmm_plan_impl& P, hipStream_t s, const char* what) {
+    DVec<int> err;
+    err.resize(1);
+    fill_i32(err.data(), 1, 0, s);
+    prepare_points(in, q_in, n, u.data(), keys.data(), perm.data(), err.data(), s);
+    const int e = read_int(err.data(), P, s);
+    if (e & 1) throw Error(ST_INVALID_ARG, std::string(what) + ": non-finite coordinates");
+    if (e & 2) throw Error(ST_INVALID_ARG, std::string(what) + ": points off the unit sphere by more than 1e-6");
+}
+
+// Sources: keys, sort by key, records (x, y, z, q) in key order.
+void sort_points(const double* in, const double* q_in, int64_t n, DVec<double4>& rec, DVec<uint32_t>& perm,
+                 DVec<uint64_t>& keys, sfmm_plan_impl& P, hipStream_t s, const char* what) {
+    rec.resize(n);
     perm.resize(n);
     keys.resize(n);
     if (n == 0) return;
     DVec<double4> u;
     u.resize(n);
-    DVec<int> err;
-    err.resize(1);
-    fill_i32(err.data(), 1, 0, s);
-    prepare_points(in, rec ? q_in : nullptr, n, u.data(), keys.data(), perm.data(), err.data(), s);
-    const int e = read_int(err.data(), P, s);
-    if (e & 1) throw Error(ST_INVALID_ARG, std::string(what) + ": non-finite coordinates");
-    if (e & 2) throw Error(ST_INVALID_ARG, std::string(what) + ": points off the unit sphere by more than 1e-6");
+    prepare_checked(in, q_in, n, u, keys, perm, P, s, what);
     radix_sort_u64(keys.data(), perm.data(), n, 62, s);
-    if (rec) gather_records(perm.data(), n, u.data(), rec->data(), s);
-    else gather_points(perm.data(), n, u.data(), ox->data(), oy->data(), oz->data(), s);
+    gather_records(perm.data(), n, u.data(), rec.data(), s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -509,15 +509,43 @@ int count_boxes(const WorkItems& w) {
     return w.n - extra;
 }
 
+// Targets: keys (kept in caller order), leaf box of each, and the plan order
+// = a stable sort by leaf box (a leaf's targets form one run, in caller
+// order; nothing downstream needs key order within a leaf).
 void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
-    sort_points(tgt, nullptr, P.M, nullptr, &P.tx, &P.ty, &P.tz, P.tperm, P.tkeys, P, s, "targets");
-    P.tleaf.resize(std::max<int64_t>(P.M, 1));
+    const int64_t M = P.M;
+    P.tx.resize(M);
+    P.ty.resize(M);
+    P.tz.resize(M);
+    P.tperm.resize(M);
+    P.tkeys.resize(M);
+    P.tleaf.resize(std::max<int64_t>(M, 1));
     P.tfirst.resize(P.nbox);
     P.tcount.resize(P.nbox);
     fill_i32(P.tfirst.data(), P.nbox, 0, s);
     fill_i32(P.tcount.data(), P.nbox, 0, s);
-    locate_targets(P.tkeys.data(), P.M, P.child0.data(), P.level.data(), P.tleaf.data(), s);
-    target_ranges(P.tleaf.data(), P.M, P.nbox, P.tfirst.data(), P.tcount.data(), s);
+    if (M > 0) {
+        DVec<double4> u;
+        DVec<uint64_t> leaf, leaf2;
+        DVec<uint32_t> perm2;
+        u.resize(M);
+        leaf.resize(M);
+        leaf2.resize(M);
+        perm2.resize(M);
+        prepare_checked(tgt, nullptr, M, u, P.tkeys, P.tperm, P, s, "targets");
+        locate_targets(P.tkeys.data(), M, P.child0.data(), P.level.data(), leaf.data(), s);
+        uint32_t* pv = nullptr;
+        const uint64_t* ls = radix_sort_u64_pp(leaf.data(), P.tperm.data(), leaf2.data(), perm2.data(), M,
+                                               bits_for(P.nbox), s, 0, &pv);
+        if (pv != P.tperm.data()) {
+            std::swap(P.tperm.p, perm2.p);
+            std::swap(P.tperm.n, perm2.n);
+            std::swap(P.tperm.cap, perm2.cap);
+        }
+        gather_targets(P.tperm.data(), ls, M, u.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tleaf.data(), s);
+        SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
+    }
+    target_ranges(P.tleaf.data(), M, P.nbox, P.tfirst.data(), P.tcount.data(), s);
     near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.p2p_ent.data(), P.nbox, P.n_p2p, P.tfirst.data(),
                P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.nl, s);
     P.p2p_ent.reset();  // stream-ordered pool: later work on this stream may reuse it
@@ -640,7 +668,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         Profiler prof(s);
         {
             StageScope st(prof, S_SRC);
-            sort_points(src, q, N, &P->spt, nullptr, nullptr, nullptr, P->sperm, P->skeys, *P, s, "sources");
+            sort_points(src, q, N, P->spt, P->sperm, P->skeys, *P, s, "sources");
         }
         if (N > 0) {
             DVec<double> qt;
@@ -862,8 +890,14 @@ sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_
         const sfmm_plan_impl& P = *plan;
         copy_widen(src_keys, P.skeys.data(), P.N);
         copy_widen(src_perm, P.sperm.data(), P.N);
-        copy_widen(tgt_keys, P.tkeys.data(), P.M);
         copy_widen(tgt_perm, P.tperm.data(), P.M);
+        if (tgt_keys && P.M > 0) {  // the keys are kept in caller order
+            std::vector<uint64_t> k(P.M);
+            SFMM_HIP(hipMemcpy(k.data(), P.tkeys.data(), sizeof(uint64_t) * P.M, hipMemcpyDeviceToHost));
+            std::vector<uint32_t> pm(P.M);
+            SFMM_HIP(hipMemcpy(pm.data(), P.tperm.data(), sizeof(uint32_t) * P.M, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < P.M; ++i) tgt_keys[i] = k[pm[i]];
+        }
         copy_widen(tgt_leaf, P.tleaf.data(), P.M);
         return SFMM_OK;
     } catch (const Error& e) {

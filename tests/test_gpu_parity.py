@@ -62,8 +62,10 @@ def test_tree_and_lists_bit_exact(name, gen, m, oracle_lib):
     k = plan.export_keys()
     assert np.array_equal(k["src_keys"], ot.keys)
     assert np.array_equal(k["src_perm"], ot.perm)
+    # targets: grouped by leaf box (ascending), caller order within a leaf
     okeys = np.array([oracle.key(*tgt[:, i]) for i in range(tgt.shape[1])], dtype=np.uint64)
-    order = np.argsort(okeys, kind="stable")
+    oleaf, _ = oracle.locate(ot, tgt)
+    order = np.argsort(oleaf, kind="stable")
     assert np.array_equal(k["tgt_keys"], okeys[order])
     assert np.array_equal(k["tgt_perm"], order)
     # box table
@@ -72,8 +74,6 @@ def test_tree_and_lists_bit_exact(name, gen, m, oracle_lib):
         assert np.array_equal(b[f], getattr(ot, f)), f
     assert np.array_equal(b["centre"], ot.centre)
     assert np.array_equal(b["radius"], ot.radius)
-    # target leaves
-    oleaf, _ = oracle.locate(ot, tgt)
     assert np.array_equal(k["tgt_leaf"], oleaf[order])
     # interaction lists, sources without particles dropped, sorted (T, S)
     om2l, op2p, margin = oracle.walk(ot)

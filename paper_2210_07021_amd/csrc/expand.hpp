@@ -84,38 +84,44 @@ SFMM_HD double log_f64(double x) {
     return fma(de, ln2_hi, fma(de, ln2_lo, lm));
 }
 
-// log x and 1/x of a positive normal double for the near-field pair loop:
-// log_f64's reduction, with the two reciprocals it and the caller need
-// (1/(2 + f) and 1/x) taken from one reciprocal of their product x (2 + f),
-// refined by two Newton steps (~3 ulp each, against 1 for separate ones),
-// and log m = 2s + 2s z q(z), z = s^2 <= (3 - 2 sqrt2)^2, with q the
-// degree-6 near-minimax polynomial (Chebyshev-node least squares) of
-// sum_k z^k / (2k + 3) on that interval: |error of log m| < 1e-17 relative
-// before rounding.
-SFMM_HD void log_recip_f64(double x, double* lg, double* inv) {
+// The pair loop's log and reciprocal with a table in place of the atanh
+// series: x = 2^e m, m in [1/2, 1); the top 7 fraction bits of m pick c_j =
+// 1/2 + (j + 1/2)/256 and tab[j] = {1/c_j, -log(1/c_j)} (log_tab_entry), so
+// that r = m/c_j - 1 (one FMA) has |r| < 2^-8 and
+//   log x = e log 2 - log(1/c_j) + log(1 + r),
+// log(1 + r) = r + r^2 (-1/2 + r/3 - ... + r^5/7), first omitted term below
+// 2^-67.  The absolute error is a few 1e-16 (no relative bound near x = 1,
+// where the terms cancel; the sums it feeds only need the absolute one).
+// 1/x is the reciprocal refined by two Newton steps.
+// The Horner coefficients of q(r) after its leading 1/7 (the last one, -1/2,
+// is an inline constant of the FMA): kernels take them as an argument, which
+// keeps them in scalar registers.
+struct LogPoly {
+    double c6, c5, c4, c3;  // -1/6, 1/5, -1/4, 1/3
+};
+constexpr LogPoly kLogPoly = {-1.0 / 6.0, 1.0 / 5.0, -0.25, 1.0 / 3.0};
+constexpr int kLogTab = 128;
+SFMM_HD double2 log_tab_entry(int j) {
+    const double c = 0.5 + (j + 0.5) / 256.0;
+    const double ci = 1.0 / c;
+    return make_double2(ci, -log_f64(ci));
+}
+
+SFMM_HD void log_recip_tab(double x, const double2* tab, const LogPoly& k, double* lg, double* inv) {
     int e;
-    double m = frexp(x, &e);
-    const bool lo = m < 0.70710678118654752440;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
-    const double f = m - 1.0;
-    const double d = 2.0 + f;
-    const double xd = x * d;
-    const double r = recip(xd);
-    *inv = d * r;
-    const double s = f * (x * r);
-    const double z = s * s;
-    double q = 0x1.2a6c879ca1a0fp-4;
-    q = fma(q, z, 0x1.3a13d6926d34bp-4);
-    q = fma(q, z, 0x1.7461f7c501a11p-4);
-    q = fma(q, z, 0x1.c71c65eba1800p-4);
-    q = fma(q, z, 0x1.2492492b194b9p-3);
-    q = fma(q, z, 0x1.99999999972f8p-3);
-    q = fma(q, z, 0x1.5555555555556p-2);
-    const double two_s = 2.0 * s;
-    const double lm = fma(two_s * z, q, two_s);
+    const double m = frexp(x, &e);
+    const int j = (int)((__builtin_bit_cast(unsigned long long, m) >> 45) & (kLogTab - 1));
+    const double2 t = tab[j];
+    const double r = fma(m, t.x, -1.0);
+    double q = fma(1.0 / 7.0, r, k.c6);
+    q = fma(q, r, k.c5);
+    q = fma(q, r, k.c4);
+    q = fma(q, r, k.c3);
+    q = fma(q, r, -0.5);
+    const double lp = fma(r * r, q, r);
     const double de = (double)e;
-    *lg = fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lm));
+    *lg = fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, t.y + lp));
+    *inv = recip(x);
 }
 
 struct cplx {

@@ -44,6 +44,7 @@
 #include "common.hpp"
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include "expand.hpp"
 
 namespace sfmm {
@@ -452,18 +453,20 @@ __device__ __forceinline__ void tile_store(TileF32& t, int k, double4 v) {
     t.lo[k] = make_float4((float)(v.x - (double)xh), (float)(v.y - (double)yh), (float)(v.z - (double)zh), 0.0f);
 }
 
-__device__ __forceinline__ void tile_pairs(const TileF64& t, int r, int L, int tn, double ax, double ay, double az,
-                                           double& p0, double& p1, double& p2, double& p3) {
+__device__ __forceinline__ void tile_pairs(const TileF64& t, const double2* ltab, const LogPoly& lk, int r, int L,
+                                           int tn, double ax, double ay, double az, double& p0, double& p1, double& p2,
+                                           double& p3) {
     for (int j = r; j < tn; j += L) {
         const double4 sp = t.p[j];
         const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
         // |d|^2 of two distinct unit vectors is >= ~1e-32: zero only for
-        // coincident points (no branch: every lane takes the same path)
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const bool coinc = d2 == 0.0;
-        double l0, i0;
-        log_recip_f64(coinc ? 1.0 : d2, &l0, &i0);
-        const double lg = coinc ? kLog4 : l0;
+        // coincident points, which take |d|^2 = 4 instead (log 4, and d = 0
+        // zeroes their deflection): both have a zero low word, so only the
+        // high word is switched (no branch: every lane takes the same path)
+        const double d2r = dx * dx + dy * dy + dz * dz;
+        const double d2 = __hiloint2double(d2r == 0.0 ? 0x40100000 : __double2hiint(d2r), __double2loint(d2r));
+        double lg, i0;
+        log_recip_tab(d2, ltab, lk, &lg, &i0);
         const double wi = sp.w * i0;
         p0 = fma(sp.w, lg, p0);
         p1 = fma(wi, dx, p1);
@@ -472,8 +475,9 @@ __device__ __forceinline__ void tile_pairs(const TileF64& t, int r, int L, int t
     }
 }
 
-__device__ __forceinline__ void tile_pairs(const TileF32& t, int r, int L, int tn, double ax, double ay, double az,
-                                           double& p0, double& p1, double& p2, double& p3) {
+__device__ __forceinline__ void tile_pairs(const TileF32& t, const double2*, const LogPoly&, int r, int L, int tn,
+                                           double ax, double ay, double az, double& p0, double& p1, double& p2,
+                                           double& p3) {
     const float axh = (float)ax, ayh = (float)ay, azh = (float)az;
     const float axl = (float)(ax - (double)axh), ayl = (float)(ay - (double)ayh), azl = (float)(az - (double)azh);
     constexpr float kLn2f = 0.693147180559945309f, kLog4f = 1.38629436111989061f;
@@ -505,7 +509,8 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                                            const int* __restrict__ tcount, const double* __restrict__ tx,
                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
-                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
+                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part,
+                                           LogPoly lk) {
     // the tile and the end-of-group reduction share one LDS block (fewer
     // bytes per wave, more waves per CU)
     constexpr size_t kSm = sizeof(Tile) > 4 * 64 * sizeof(double) ? sizeof(Tile) : 4 * 64 * sizeof(double);
@@ -513,6 +518,11 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
     Tile& tile = *reinterpret_cast<Tile*>(sm);
     double(*red)[64] = reinterpret_cast<double(*)[64]>(sm);
     const int lane = threadIdx.x;
+    // the FP64 pair loop's log table (made before the first tile's barrier)
+    __shared__ double2 ltab[std::is_same<Tile, TileF64>::value ? kLogTab : 1];
+    if constexpr (std::is_same<Tile, TileF64>::value) {
+        for (int j = lane; j < kLogTab; j += 64) ltab[j] = log_tab_entry(j);
+    }
     const int4 item = items[blockIdx.x];
     const int T = item.x;
     const int k0 = item.y, K = item.z - item.y;
@@ -569,7 +579,7 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                     }
                 }
                 __syncthreads();
-                if (active) tile_pairs(tile, r, L, tn, ax, ay, az, p0, p1, p2, p3);
+                if (active) tile_pairs(tile, ltab, lk, r, L, tn, ax, ay, az, p0, p1, p2, p3);
             }
         }
         const double qn = wave_sum(qnear);
@@ -713,10 +723,10 @@ void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, con
     if (w.n <= 0) return;
     if (fp32)
         k_p2p<TileF32><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, w.part.data());
+                                                    defl, m_out, w.part.data(), kLogPoly);
     else
         k_p2p<TileF64><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, w.part.data());
+                                                    defl, m_out, w.part.data(), kLogPoly);
     SFMM_LAUNCH_CHECK();
     reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
 }

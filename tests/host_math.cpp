@@ -1,7 +1,8 @@
 // Host build of the library's device math (the same headers, compiled for
 // the CPU) for tests/test_host_math.py.  Modes:
 //   sincos : reads "hi lo" pairs (hex floats), prints dd sin and cos
-//   log    : reads x (hex float), prints log_recip_f64's log and 1/x
+//   log    : reads x (hex float), prints the pair loop's table log of x
+//            (log_recip_tab) and 1/x
 //   mac    : random pairs of unit vectors and radii around the thresholds;
 //            counts decisions of the angle-free FP64 MAC filter that
 //            contradict the angle computed in long double, and how many it
@@ -37,10 +38,12 @@ int main(int argc, char** argv) {
         return 0;
     }
     if (!strcmp(argv[1], "log")) {
+        double2 tab[kLogTab];
+        for (int j = 0; j < kLogTab; ++j) tab[j] = log_tab_entry(j);
         double x;
         while (scanf("%lf", &x) == 1) {
             double l, i;
-            log_recip_f64(x, &l, &i);
+            log_recip_tab(x, tab, kLogPoly, &l, &i);
             printf("%a %a\n", l, i);
         }
         return 0;

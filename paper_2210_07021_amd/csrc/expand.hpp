@@ -469,19 +469,16 @@ SFMM_HD void l2p_eval(const double* e, const Frame& f, double rho, double nx, do
     const cplx w = stereo(f, nx, ny, nz, &opc);
     const double inv_rho = 1.0 / rho;
     const cplx zt = {w.re * inv_rho, w.im * inv_rho};
-    // Horner for f = sum L_l zt^l and g = sum l L_l zt^(l-1)
-    cplx fv = {0.0, 0.0}, gv = {0.0, 0.0};
+    // f = sum L_l zt^l by Horner from the top coefficient and g = f'(zt) =
+    // sum l L_l zt^(l-1) by the companion recurrence d <- d zt + p
+    cplx pv = {e[2 * P], e[2 * P + 1]}, gv = {0.0, 0.0};
 #pragma unroll
-    for (int l = P; l >= 1; --l) {
-        const cplx a = {e[2 * l], e[2 * l + 1]};
-        gv = cmul(gv, zt);
-        gv.re = fma((double)l, a.re, gv.re);
-        gv.im = fma((double)l, a.im, gv.im);
-        fv = cmul(fv, zt);
-        fv.re += a.re;
-        fv.im += a.im;
+    for (int l = P - 1; l >= 1; --l) {
+        gv = {fma(gv.re, zt.re, fma(-gv.im, zt.im, pv.re)), fma(gv.re, zt.im, fma(gv.im, zt.re, pv.im))};
+        pv = {fma(pv.re, zt.re, fma(-pv.im, zt.im, e[2 * l])), fma(pv.re, zt.im, fma(pv.im, zt.re, e[2 * l + 1]))};
     }
-    fv = cmul(fv, zt);
+    gv = {fma(gv.re, zt.re, fma(-gv.im, zt.im, pv.re)), fma(gv.re, zt.im, fma(gv.im, zt.re, pv.im))};
+    const cplx fv = cmul(pv, zt);
     const double C = e[0], Q = e[1];
     *psi = C + Q * log_f64(opc) + 2.0 * fv.re;
     // f'(w) = g / rho
@@ -517,19 +514,17 @@ SFMM_HD void m2p_eval(const double* __restrict__ e, const Frame& f, double rho, 
     const double w2 = w.re * w.re + w.im * w.im;
     const double iw2 = recip(w2);
     const cplx zt = {rho * w.re * iw2, -rho * w.im * iw2};  // rho / w
-    cplx F = {0.0, 0.0}, G = {0.0, 0.0};
+    // F = h(zt) = sum_l A_l zt^l and G = zt h'(zt) = sum_l l A_l zt^l: Horner
+    // for h from the top coefficient, its derivative by the companion
+    // recurrence d <- d zt + p (two FMAs per real part, no l factors)
+    cplx pv = {e[2 * P], e[2 * P + 1]}, dv = {0.0, 0.0};
 #pragma unroll 6
-    for (int l = P; l >= 1; --l) {
-        const double ar = e[2 * l], ai = e[2 * l + 1];
-        F = cmul(F, zt);
-        F.re += ar;
-        F.im += ai;
-        G = cmul(G, zt);
-        G.re = fma((double)l, ar, G.re);
-        G.im = fma((double)l, ai, G.im);
+    for (int l = P - 1; l >= 1; --l) {
+        dv = {fma(dv.re, zt.re, fma(-dv.im, zt.im, pv.re)), fma(dv.re, zt.im, fma(dv.im, zt.re, pv.im))};
+        pv = {fma(pv.re, zt.re, fma(-pv.im, zt.im, e[2 * l])), fma(pv.re, zt.im, fma(pv.im, zt.re, e[2 * l + 1]))};
     }
-    F = cmul(F, zt);
-    G = cmul(G, zt);
+    dv = {fma(dv.re, zt.re, fma(-dv.im, zt.im, pv.re)), fma(dv.re, zt.im, fma(dv.im, zt.re, pv.im))};
+    const cplx F = cmul(pv, zt), G = cmul(dv, zt);
     const double C = e[0], Q = e[1];
     *psi = C + Q * log_f64(omc) + 2.0 * F.re;
     // (Q - (1+|w|^2) conj(G)) / conj(w) = (Q - s conj(G)) * w / |w|^2

@@ -278,7 +278,7 @@ SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
     double an = G.a;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
-        const cplx v = {ar[l] - (Q / l) * an, ai[l]};
+        const cplx v = {fma(-Q * (1.0 / l), an, ar[l]), ai[l]};  // 1.0 / l folds to a constant
         const cplx o = cmul(pw2, v);
         acc[2 * l] += o.re;
         acc[2 * l + 1] += o.im;
@@ -336,7 +336,7 @@ SFMM_HD void translate_emit(const In& in, const TransGeom& G, const Out& out) {
     double an = G.a;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
-        const cplx v = {ar[l] - (Q / l) * an, ai[l]};
+        const cplx v = {fma(-Q * (1.0 / l), an, ar[l]), ai[l]};  // 1.0 / l folds to a constant
         const cplx o = cmul(pw2, v);
         out(2 * l, o.re);
         out(2 * l + 1, o.im);

@@ -109,9 +109,13 @@ void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit = 0);
 // The same sort, ping-ponging between the caller's buffers (kalt / valt hold
 // n elements; valt may be null when vals is): returns the buffer holding the
-// sorted keys, *vout (if not null) the one holding the values.
+// sorted keys, *vout (if not null) the one holding the values.  With lo_out
+// and hi_out (n elements each, n > 1 and bits > begin_bit), the last pass
+// writes the sorted keys' low and high 32-bit halves there instead, and the
+// returned buffer does not hold them.
 uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint32_t* valt, int64_t n, int bits,
-                            hipStream_t s, int begin_bit, uint32_t** vout);
+                            hipStream_t s, int begin_bit, uint32_t** vout, uint32_t* lo_out = nullptr,
+                            uint32_t* hi_out = nullptr);
 void sum_f64(const double* x, int64_t n, double* out, hipStream_t s, int stride = 1);  // sum of x[i * stride]
 void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s);
 
@@ -189,8 +193,10 @@ void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t
 // which FP32 rounding would show)
 constexpr int kFp32CoarseLevel = 6;
 // pairs (target << 32 | source) sorted by target -> CSR offsets and sources
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* ent /*nullable*/,
-                  hipStream_t s);
+// source and target box of every entry from sorted (target << 32 | source)
+// keys, and CSR offsets from the sorted targets
+void pair_split(const uint64_t* sorted, int np, int* src, int* tgt, hipStream_t s);
+void csr_offsets(const int* tgt, int np, int nbox, int* off, hipStream_t s);
 // sort keys (8 bits) putting the boxes with the most work first, in
 // power-of-two buckets; flag the boxes that have any
 void work_order_keys(const long long* work, int n, uint64_t* keys, uint32_t* vals, int* flag, hipStream_t s);

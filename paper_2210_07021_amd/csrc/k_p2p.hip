@@ -316,18 +316,25 @@ __global__ void k_seg_emit(const int* __restrict__ off, const int* __restrict__ 
 
 // Sort key of each item: leading zeros of its work, targets x particles (or
 // targets x entries when count is null); heaviest power-of-two bucket first
+// (one wave per item: its lanes sum the particle counts of the segment)
 __global__ void k_item_keys(const int4* __restrict__ items, int n, const int* __restrict__ src,
                             const int* __restrict__ count, const int* __restrict__ tcount,
                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;  // uniform across the wave
     const int4 it = items[i];
     long long w = 0;
     if (count) {
-        for (int k = it.y; k < it.z; ++k) w += count[src[k]];
+        long long part = 0;
+        for (int k = it.y + lane; k < it.z; k += 64) part += count[src[k]];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        w = part;
     } else {
         w = it.z - it.y;
     }
+    if (lane != 0) return;
     w *= tcount[it.x];
     keys[i] = (w > 0) ? (uint64_t)__clzll((unsigned long long)w) : 255ULL;
     vals[i] = (uint32_t)i;
@@ -376,7 +383,8 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), item_off.data(),
                                                slot_off.data(), red_off.data(), raw.data(), out.red.data());
     SFMM_LAUNCH_CHECK();
-    k_item_keys<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), out.n, src, count, tcount, keys.data(), vals.data());
+    k_item_keys<<<nblk(64 * (int64_t)out.n, 256), 256, 0, s>>>(raw.data(), out.n, src, count, tcount, keys.data(),
+                                                             vals.data());
     SFMM_LAUNCH_CHECK();
     radix_sort_u64(keys.data(), vals.data(), out.n, 8, s);
     k_gather_items<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), vals.data(), out.n, out.items.data());

@@ -779,36 +779,38 @@ void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8
 }
 
 // ------------------------------------------------------------------ lists
-__global__ void k_csr_offsets(const uint64_t* sorted, int np, int nbox, int* off) {
+// CSR offsets from the entries' target boxes in sorted order: off[b] = the
+// first entry whose target is >= b
+__global__ void k_csr_offsets(const int* tgt, int np, int nbox, int* off) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbox) return;
-    // first pair whose target is >= b
     int lo = 0, hi = np;
-    const uint64_t v = (uint64_t)(uint32_t)b << 32;
     while (lo < hi) {
         const int mid = lo + ((hi - lo) >> 1);
-        if (sorted[mid] < v) lo = mid + 1;
+        if (tgt[mid] < b) lo = mid + 1;
         else hi = mid;
     }
     off[b] = lo;
 }
 
-// source box of every entry, and (ent != nullptr) its target box
-__global__ void k_pair_sources(const uint64_t* sorted, int np, int* src, int* ent) {
+// source and target box of every entry from the sorted pair keys
+__global__ void k_pair_split(const uint64_t* sorted, int np, int* src, int* tgt) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
     const uint64_t v = sorted[k];
     src[k] = (int)(uint32_t)(v & 0xffffffffULL);
-    if (ent) ent[k] = (int)(uint32_t)(v >> 32);
+    tgt[k] = (int)(uint32_t)(v >> 32);
 }
 
-void pairs_to_csr(const uint64_t* sorted, int npairs, int nbox, int* off, int* src, int* ent, hipStream_t s) {
-    k_csr_offsets<<<nblocks(nbox + 1, 256), 256, 0, s>>>(sorted, npairs, nbox, off);
+void pair_split(const uint64_t* sorted, int np, int* src, int* tgt, hipStream_t s) {
+    if (np <= 0) return;
+    k_pair_split<<<nblocks(np, 256), 256, 0, s>>>(sorted, np, src, tgt);
     SFMM_LAUNCH_CHECK();
-    if (npairs > 0) {
-        k_pair_sources<<<nblocks(npairs, 256), 256, 0, s>>>(sorted, npairs, src, ent);
-        SFMM_LAUNCH_CHECK();
-    }
+}
+
+void csr_offsets(const int* tgt, int np, int nbox, int* off, hipStream_t s) {
+    k_csr_offsets<<<nblocks(nbox + 1, 256), 256, 0, s>>>(tgt, np, nbox, off);
+    SFMM_LAUNCH_CHECK();
 }
 
 // M2L order keys: boxes of levels <= lc first (bit 15 clear), then the rest;

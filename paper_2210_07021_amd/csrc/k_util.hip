@@ -249,9 +249,12 @@ __global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restri
 // quarter.  One pass over the counts of the four waves then places each key
 // in the tile sorted by digit (LDS), and the sorted tile is written out, so
 // consecutive lanes write consecutive addresses within each digit's run.
+// lo_out / hi_out (the last pass of a split sort): the key's two 32-bit
+// halves go to two arrays instead of the key to kout.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                            uint32_t* vout, int64_t n, int shift, int nblk,
-                                                           const int* offs, const int* dtot) {
+                                                           const int* offs, const int* dtot, uint32_t* lo_out,
+                                                           uint32_t* hi_out) {
     __shared__ int wcnt[kRsWaves][256];  // per-wave digit counts, then each wave's first slot per digit
     __shared__ int goff[256];            // global position of slot 0 of each digit's run of this tile
     __shared__ int wsum[kRsWaves];
@@ -327,13 +330,18 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, 
         const uint64_t k = sk[p];
         const int64_t pos = (int64_t)goff[(int)((k >> shift) & 255)] + p;
         if (pos < 0 || pos >= n) continue;  // unreachable with consistent counts
-        kout[pos] = k;
+        if (lo_out) {
+            lo_out[pos] = (uint32_t)k;
+            hi_out[pos] = (uint32_t)(k >> 32);
+        } else {
+            kout[pos] = k;
+        }
         if (vout) vout[pos] = sv[p];
     }
 }
 
 uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint32_t* valt, int64_t n, int bits,
-                            hipStream_t s, int begin_bit, uint32_t** vout) {
+                            hipStream_t s, int begin_bit, uint32_t** vout, uint32_t* lo_out, uint32_t* hi_out) {
     if (vout) *vout = vals;
     if (n <= 1 || bits <= begin_bit) return keys;
     const int nblk = (int)((n + kRsTile - 1) / kRsTile);
@@ -350,7 +358,9 @@ uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint
         SFMM_LAUNCH_CHECK();
         k_rs_rowscan<<<256, kScanThreads, 0, s>>>(hist, nblk, offs, dtot);
         SFMM_LAUNCH_CHECK();
-        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot);
+        const bool last = pass == npass - 1;
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot, last ? lo_out : nullptr,
+                                                 last ? hi_out : nullptr);
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);

@@ -317,14 +317,18 @@ void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, 
                        hipStream_t s) {
     off.resize((size_t)nbox + 1);
     src.resize(std::max(np, 1));
-    if (ent) ent->resize(std::max(np, 1));
-    DVec<uint64_t> alt;
-    const uint64_t* sorted = pairs.data();
-    if (np > 0) {
+    DVec<int> tgt_own;
+    DVec<int>& tgt = ent ? *ent : tgt_own;
+    tgt.resize(std::max(np, 1));
+    if (np > 1) {  // the last pass writes the sources and targets themselves
+        DVec<uint64_t> alt;
         alt.resize(np);
-        sorted = radix_sort_u64_pp(pairs.data(), nullptr, alt.data(), nullptr, np, 32 + bits_for(nbox), s, 32, nullptr);
+        radix_sort_u64_pp(pairs.data(), nullptr, alt.data(), nullptr, np, 32 + bits_for(nbox), s, 32, nullptr,
+                          reinterpret_cast<uint32_t*>(src.data()), reinterpret_cast<uint32_t*>(tgt.data()));
+    } else {
+        pair_split(pairs.data(), np, src.data(), tgt.data(), s);
     }
-    pairs_to_csr(sorted, np, nbox, off.data(), src.data(), ent ? ent->data() : nullptr, s);
+    csr_offsets(tgt.data(), np, nbox, off.data(), s);
     SFMM_HIP(hipStreamSynchronize(s));
 }
 

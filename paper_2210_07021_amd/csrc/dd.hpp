@@ -1,8 +1,8 @@
 // Double-double (~106-bit) arithmetic for the exact geometric predicates of
 // the tree build: HEALPix keys near pixel edges and MAC tests near their
 // thresholds.  Dekker/Knuth error-free transformations (two-sum, two-product
-// with a fused multiply-add), Taylor series for sin/cos, one Newton step for
-// atan2.  Every routine disables FMA contraction locally: the error-free
+// with a fused multiply-add), a Taylor series for sin (cos from it by a
+// square root), one Newton step for atan2.  Every routine disables FMA contraction locally: the error-free
 // transformations are only exact when each operation rounds separately.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -94,8 +94,6 @@ SFMM_HD dd dd_half_pi() { return {1.5707963267948966192, 6.123233995736766036e-1
 SFMM_HD dd dd_two_over_pi() { return {0.63661977236758138243, -3.9357353350364971764e-17}; }
 SFMM_HD dd dd_quarter_pi() { return {0.78539816339744830962, 3.0616169978683830179e-17}; }
 
-// sin and cos of a double-double argument: reduce by multiples of pi/2 to
-// |r| <= pi/4, then Taylor series to the 29th power (|r|^31/31! < 1e-34).
 // 1/n! to double-double precision, n = 0..31: hi is 1/n! rounded to the
 // nearest double and lo the nearest double to the remainder.
 SFMM_HD dd inv_factorial(int n) {
@@ -137,9 +135,10 @@ SFMM_HD dd inv_factorial(int n) {
 }
 
 // sin and cos of a double-double angle: reduction by multiples of pi/2 to
-// |r| <= pi/4, then the two Taylor series in r^2 by Horner's rule with the
-// tabulated 1/n! (terms through r^31/31! and r^30/30!, whose successors are
-// below 1e-33 on that range).
+// |r| <= pi/4, the Taylor series of sin r in r^2 by Horner's rule with the
+// tabulated 1/n! (terms through r^31/31!, whose successor is below 1e-33 on
+// that range), and cos r = sqrt(1 - sin^2 r), well conditioned there since
+// cos r >= 0.7.
 SFMM_HD void dd_sincos(dd x, dd* s_out, dd* c_out) {
 #pragma clang fp contract(off)
     const double kf = nearbyint(x.hi * 0.63661977236758138243);
@@ -149,13 +148,12 @@ SFMM_HD void dd_sincos(dd x, dd* s_out, dd* c_out) {
     r = dd_sub(r, dd_from(kf * -1.4973849048591698e-33));
     const dd r2 = dd_mul(r, r);
     // s = sum_j (-1)^j r^2j / (2j+1)!, c = sum_j (-1)^j r^2j / (2j)!
-    dd s = inv_factorial(31), c = inv_factorial(30);
+    dd s = inv_factorial(31);
 #pragma unroll
-    for (int j = 14; j >= 0; --j) {
-        s = dd_sub(inv_factorial(2 * j + 1), dd_mul(r2, s));
-        c = dd_sub(inv_factorial(2 * j), dd_mul(r2, c));
-    }
+    for (int j = 14; j >= 0; --j) s = dd_sub(inv_factorial(2 * j + 1), dd_mul(r2, s));
     s = dd_mul(s, r);
+    // cos r = sqrt(1 - sin^2 r), well conditioned for |r| <= pi/4 (cos >= 0.7)
+    const dd c = dd_sqrt(dd_sub(dd_from(1.0), dd_mul(s, s)));
     dd so, co;
     switch (k & 3) {
         case 0: so = s; co = c; break;

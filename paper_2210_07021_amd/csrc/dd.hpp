@@ -50,6 +50,16 @@ SFMM_HD dd dd_add(dd a, dd b) {
     return quick_two_sum(s.hi, s.lo);
 }
 
+// a - b when |b| is well below |a| (no cancellation): one two-sum of the
+// high parts, the low parts added in double.  The relative error stays near
+// 2^-104 because |a - b| is close to |a|.
+SFMM_HD dd dd_sub_small(dd a, dd b) {
+#pragma clang fp contract(off)
+    dd s = two_sum(a.hi, -b.hi);
+    s.lo += a.lo - b.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+
 SFMM_HD dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
 SFMM_HD dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
 
@@ -150,7 +160,8 @@ SFMM_HD void dd_sincos(dd x, dd* s_out, dd* c_out) {
     // s = sum_j (-1)^j r^2j / (2j+1)!, c = sum_j (-1)^j r^2j / (2j)!
     dd s = inv_factorial(31);
 #pragma unroll
-    for (int j = 14; j >= 0; --j) s = dd_sub(inv_factorial(2 * j + 1), dd_mul(r2, s));
+    // each step subtracts at most a tenth of the term (r^2 / ((2j+2)(2j+3)) < 0.1)
+    for (int j = 14; j >= 0; --j) s = dd_sub_small(inv_factorial(2 * j + 1), dd_mul(r2, s));
     s = dd_mul(s, r);
     // cos r = sqrt(1 - sin^2 r), well conditioned for |r| <= pi/4 (cos >= 0.7)
     const dd c = dd_sqrt(dd_sub(dd_from(1.0), dd_mul(s, s)));

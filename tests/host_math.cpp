@@ -1,6 +1,7 @@
 // Host build of the library's device math (the same headers, compiled for
 // the CPU) for tests/test_host_math.py.  Modes:
 //   sincos : reads "hi lo" pairs (hex floats), prints dd sin and cos
+//   atan2  : reads "yhi ylo xhi xlo" (hex floats), prints dd_atan2 as hi lo
 //   log    : reads x (hex float), prints the pair loop's table log of x
 //            (log_recip_tab) and 1/x
 //   mac    : random pairs of unit vectors and radii around the thresholds;
@@ -34,6 +35,14 @@ int main(int argc, char** argv) {
             dd s, c;
             dd_sincos(dd{hi, lo}, &s, &c);
             printf("%a %a %a %a\n", s.hi, s.lo, c.hi, c.lo);
+        }
+        return 0;
+    }
+    if (!strcmp(argv[1], "atan2")) {
+        double a, b, c, d;
+        while (scanf("%lf %lf %lf %lf", &a, &b, &c, &d) == 4) {
+            const dd t = dd_atan2(dd{a, b}, dd{c, d});
+            printf("%a %a\n", t.hi, t.lo);
         }
         return 0;
     }

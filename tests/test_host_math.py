@@ -68,6 +68,46 @@ def test_dd_sincos_is_double_double_accurate(host_math):
     assert worst < 1e-31, worst
 
 
+def _atan2(y, x):
+    # 70 digits: atan of the smaller ratio by its Taylor series after halving
+    # the argument (atan z = 2 atan(z / (1 + sqrt(1 + z^2)))) until it is small
+    getcontext().prec = 70
+    pi = Decimal("3.141592653589793238462643383279502884197169399375105820974944592307816")
+    def atan(z):
+        k = 0
+        while abs(z) > Decimal("0.01"):
+            z = z / (1 + (1 + z * z).sqrt())
+            k += 1
+        s, t, n = Decimal(0), z, 1
+        while abs(t) > Decimal(10) ** -75:
+            s += t / n
+            t = -t * z * z
+            n += 2
+        return s * (2 ** k)
+    if x > 0:
+        return atan(y / x)
+    if x < 0:
+        return atan(y / x) + (pi if y >= 0 else -pi)
+    return pi / 2 if y > 0 else -pi / 2
+
+
+def test_dd_atan2_is_double_double_accurate(host_math):
+    rng = random.Random(13)
+    cases = []
+    for _ in range(300):
+        y, x = rng.uniform(-1, 1), rng.uniform(-1, 1)
+        cases.append((y, rng.uniform(-1, 1) * abs(y) * 1e-17, x, rng.uniform(-1, 1) * abs(x) * 1e-17))
+    cases += [(1e-9, 0.0, 1.0, 0.0), (1.0, 0.0, -1e-12, 0.0), (-0.5, 1e-18, -0.5, -1e-18), (0.7, 0.0, 0.7, 0.0)]
+    out = _run(host_math, "atan2", "".join(f"{a.hex()} {b.hex()} {c.hex()} {d.hex()}\n" for a, b, c, d in cases))
+    worst = 0.0
+    for (a, b, c, d), line in zip(cases, out):
+        v = [Decimal(float.fromhex(t)) for t in line.split()]
+        getcontext().prec = 70
+        ref = _atan2(Decimal(a) + Decimal(b), Decimal(c) + Decimal(d))
+        worst = max(worst, float(abs(v[0] + v[1] - ref)))
+    assert worst < 1e-30, worst
+
+
 def test_pair_log_and_reciprocal_within_a_few_ulp(host_math):
     """The pair loop's table log: its error is absolute (the sums it feeds
     need no relative bound near x = 1), so it is measured in ulps of

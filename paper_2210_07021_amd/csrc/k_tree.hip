@@ -236,9 +236,9 @@ void tree_make_children(int b0, int nb, int child_base, const int* flag, const i
 // ------------------------------------------------------------------ queued levels
 // The same level loop with the level bounds in device memory (ls[L] ..
 // ls[L+1] - 1 are level L's boxes), so levels run back to back without a
-// read-back each: per level, split counts per chunk of kTreeChunk boxes, one
-// workgroup scanning the chunk counts (and setting ls[L+2], or the overflow
-// flag ctl[0] when the children would pass the capacity), then the children.
+// read-back each: per level, split counts per chunk of kTreeChunk boxes,
+// then the children (which also set ls[L+2], or the overflow flag ctl[0]
+// when the children would pass the capacity): two launches per level.
 constexpr int kTreeThreads = 256;
 constexpr int kTreePer = kTreeChunk / kTreeThreads;
 
@@ -296,51 +296,67 @@ __global__ void __launch_bounds__(kTreeThreads) k_tree_count(const int* ls, int 
     }
 }
 
-__global__ void __launch_bounds__(kTreeThreads) k_tree_scan(int* ls, int L, int* ccnt, int cap, int* ctl) {
-    __shared__ int sh[kTreeThreads / 64];
-    const int nb = ls[L + 1] - ls[L];
-    const int nch = (nb + kTreeChunk - 1) / kTreeChunk;
-    int carry = 0;
-    for (int c0 = 0; c0 < nch; c0 += kTreeThreads) {
-        const int i = c0 + threadIdx.x;
-        const int v = i < nch ? ccnt[i] : 0;
-        int tot;
-        const int e = tree_block_excl(v, sh, &tot);
-        if (i < nch) ccnt[i] = carry + e;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        const int64_t need = (int64_t)ls[L + 1] + 4 * (int64_t)carry;
-        if (ctl[0] || need > cap) {
-            ctl[0] = 1;
-            ls[L + 2] = ls[L + 1];
-        } else {
-            ls[L + 2] = (int)need;
-        }
-    }
+// Sum of ccnt[0 .. n) by the whole wave (every lane returns it).
+__device__ int wave_sum_prefix(const int* ccnt, int n) {
+    const int lane = threadIdx.x & 63;
+    int sum = 0;
+    for (int k = lane; k < n; k += 64) sum += ccnt[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    return sum;
 }
 
 // Children of every box of the level: a wave per box on levels of fewer
-// than kWaveLevel boxes, else a thread per box (grid-stride either way).
-__global__ void __launch_bounds__(kTreeThreads) k_tree_children(const int* ls, int L, const int* ccnt,
-                                                                 const int* wpre, const int* ctl,
-                                                                 const uint64_t* __restrict__ keys, int* level,
-                                                                 uint64_t* pixel, int* first, int* count,
+// than kWaveLevel boxes, else a lane per box (grid-stride either way).  A
+// split box's slot is the split count of the chunks before its own (summed
+// here from the per-chunk counts) plus its rank in its chunk.  The first
+// wave of workgroup 0 sums all chunks: the next level's bounds ls[L+2], or
+// the overflow flag when the children would pass cap boxes (boxes whose
+// children would not fit write none; the caller then rebuilds the tree).
+__global__ void __launch_bounds__(kTreeThreads) k_tree_children(int* ls, int L, const int* ccnt, const int* wpre,
+                                                                 int* ctl, int cap, const uint64_t* __restrict__ keys,
+                                                                 int* level, uint64_t* pixel, int* first, int* count,
                                                                  int* parent, int* child0) {
-    if (ctl[0]) return;
+    if (ctl[0]) {  // an earlier level overflowed: this one stays empty
+        if (blockIdx.x == 0 && threadIdx.x == 0) ls[L + 2] = ls[L + 1];
+        return;
+    }
     const int b0 = ls[L], nb = ls[L + 1] - b0, child_base = ls[L + 1];
+    const int nch = (nb + kTreeChunk - 1) / kTreeChunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && wave == 0) {
+        const int tot = wave_sum_prefix(ccnt, nch);
+        if (lane == 0) {
+            const int64_t need = (int64_t)child_base + 4 * (int64_t)tot;
+            if (need > cap) {
+                ctl[0] = 1;
+                ls[L + 2] = ls[L + 1];
+            } else {
+                ls[L + 2] = (int)need;
+            }
+        }
+    }
+    const int nw = gridDim.x * (kTreeThreads / 64);
     if (nb < kWaveLevel) {
-        const int nw = gridDim.x * (kTreeThreads / 64);
-        for (int i = blockIdx.x * (kTreeThreads / 64) + (threadIdx.x >> 6); i < nb; i += nw) {
+        for (int i = blockIdx.x * (kTreeThreads / 64) + wave; i < nb; i += nw) {
             const int r = wpre[i];
-            children_wave(b0 + i, r >= 0 ? ccnt[i / kTreeChunk] + r : -1, child_base, keys, level, pixel, first,
-                          count, parent, child0);
+            const int pre = wave_sum_prefix(ccnt, i / kTreeChunk);
+            int slot = r >= 0 ? pre + r : -1;
+            if (slot >= 0 && (int64_t)child_base + 4 * (int64_t)slot + 4 > cap) continue;  // overflow
+            children_wave(b0 + i, slot, child_base, keys, level, pixel, first, count, parent, child0);
         }
     } else {
-        for (int i = blockIdx.x * kTreeThreads + threadIdx.x; i < nb; i += gridDim.x * kTreeThreads) {
+        // a wave takes 64 consecutive boxes, which span at most two chunks
+        for (int base = (blockIdx.x * (kTreeThreads / 64) + wave) * 64; base < nb; base += nw * 64) {
+            const int c0 = base / kTreeChunk;
+            const int pre0 = wave_sum_prefix(ccnt, c0);
+            const int i = base + lane;
+            if (i >= nb) continue;
+            const int pre = (i / kTreeChunk == c0) ? pre0 : pre0 + ccnt[c0];
             const int r = wpre[i];
-            children_thread(b0 + i, r >= 0 ? ccnt[i / kTreeChunk] + r : -1, child_base, keys, level, pixel, first,
-                            count, parent, child0);
+            const int slot = r >= 0 ? pre + r : -1;
+            if (slot >= 0 && (int64_t)child_base + 4 * (int64_t)slot + 4 > cap) continue;  // overflow
+            children_thread(b0 + i, slot, child_base, keys, level, pixel, first, count, parent, child0);
         }
     }
 }
@@ -355,10 +371,8 @@ void tree_level_queued(int* ls, int L, int* ccnt, int* wpre, int grid, int cgrid
                        int* parent, int* child0, hipStream_t s) {
     k_tree_count<<<grid, kTreeThreads, 0, s>>>(ls, L, count, m, split_ok, ccnt, wpre);
     SFMM_LAUNCH_CHECK();
-    k_tree_scan<<<1, kTreeThreads, 0, s>>>(ls, L, ccnt, cap, ctl);
-    SFMM_LAUNCH_CHECK();
-    k_tree_children<<<cgrid, kTreeThreads, 0, s>>>(ls, L, ccnt, wpre, ctl, keys, level, pixel, first, count, parent,
-                                                   child0);
+    k_tree_children<<<cgrid, kTreeThreads, 0, s>>>(ls, L, ccnt, wpre, ctl, cap, keys, level, pixel, first, count,
+                                                   parent, child0);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -192,7 +192,7 @@ constexpr int kRsRounds = 8;
 constexpr int kRsTile = kRsThreads * kRsRounds;
 constexpr int kRsWaves = kRsThreads / 64;
 
-__global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, int* hist) {
+__global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int rs, int* hist) {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
@@ -207,35 +207,51 @@ __global__ void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int nblk, 
     for (int r = 0; r < kRsRounds; ++r)
         if (d[r] >= 0) atomicAdd(&h[d[r]], 1);
     __syncthreads();
-    hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    hist[threadIdx.x * rs + blockIdx.x] = h[threadIdx.x];
 }
 
 // Exclusive scan of each digit's row of the digit-major histogram (one
 // workgroup per digit, chunks of kScanTile with a running carry); dtot[d] =
-// the digit's total count.  The digit bases (scan of dtot) are added by the
-// scatter.
-__global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restrict__ hist, int nblk,
+// the digit's total count.  Rows are rs ints apart (rs a multiple of 4, the
+// entries past nblk unused), so each thread moves its 16 entries as four
+// 16-byte vectors.  The digit bases (scan of dtot) are added by the scatter.
+__global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restrict__ hist, int nblk, int rs,
                                                              int* __restrict__ offs, int* __restrict__ dtot) {
+    static_assert(kScanItems == 16, "four int4 per thread");
     __shared__ int sh[kScanThreads / 64];
     const int d = blockIdx.x;
-    const int* in = hist + (size_t)d * nblk;
-    int* out = offs + (size_t)d * nblk;
+    const int* in = hist + (size_t)d * rs;
+    int* out = offs + (size_t)d * rs;
     int carry = 0;
     for (int c0 = 0; c0 < nblk; c0 += kScanTile) {
         const int base = c0 + threadIdx.x * kScanItems;
         int v[kScanItems];
         int sum = 0;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            v[k] = base + k < nblk ? in[base + k] : 0;
-            sum += v[k];
+        for (int q = 0; q < 4; ++q) {
+            int4 x = make_int4(0, 0, 0, 0);
+            if (base + 4 * q < nblk) x = *reinterpret_cast<const int4*>(in + base + 4 * q);  // within the row of rs
+            v[4 * q + 0] = base + 4 * q + 0 < nblk ? x.x : 0;
+            v[4 * q + 1] = base + 4 * q + 1 < nblk ? x.y : 0;
+            v[4 * q + 2] = base + 4 * q + 2 < nblk ? x.z : 0;
+            v[4 * q + 3] = base + 4 * q + 3 < nblk ? x.w : 0;
         }
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) sum += v[k];
         int tot;
         int run = carry + block_excl_scan(sum, sh, &tot);
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            if (base + k < nblk) out[base + k] = run;
-            run += v[k];
+        for (int q = 0; q < 4; ++q) {
+            int4 o;
+            o.x = run;
+            run += v[4 * q + 0];
+            o.y = run;
+            run += v[4 * q + 1];
+            o.z = run;
+            run += v[4 * q + 2];
+            o.w = run;
+            run += v[4 * q + 3];
+            if (base + 4 * q < nblk) *reinterpret_cast<int4*>(out + base + 4 * q) = o;
         }
         carry += tot;
     }
@@ -252,7 +268,7 @@ __global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(const int* __restri
 // lo_out / hi_out (the last pass of a split sort): the key's two 32-bit
 // halves go to two arrays instead of the key to kout.
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                           uint32_t* vout, int64_t n, int shift, int nblk,
+                                                           uint32_t* vout, int64_t n, int shift, int rs,
                                                            const int* offs, const int* dtot, uint32_t* lo_out,
                                                            uint32_t* hi_out) {
     __shared__ int wcnt[kRsWaves][256];  // per-wave digit counts, then each wave's first slot per digit
@@ -306,7 +322,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint64_t* kin, 
         }
         int all;
         const int lbase = block_excl_scan(tot, wsum, &all);
-        goff[t] = offs[t * nblk + blockIdx.x] + block_excl_scan(dtot[t], wsum, &all) - lbase;
+        goff[t] = offs[t * rs + blockIdx.x] + block_excl_scan(dtot[t], wsum, &all) - lbase;
         int run = lbase;
 #pragma unroll
         for (int w = 0; w < kRsWaves; ++w) {
@@ -345,8 +361,9 @@ uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint
     if (vout) *vout = vals;
     if (n <= 1 || bits <= begin_bit) return keys;
     const int nblk = (int)((n + kRsTile - 1) / kRsTile);
-    int* hist = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
-    int* offs = (int*)pool_alloc(sizeof(int) * 256 * (size_t)nblk);
+    const int rs = (nblk + 3) & ~3;  // histogram row stride: 16-byte aligned rows
+    int* hist = (int*)pool_alloc(sizeof(int) * 256 * (size_t)rs);
+    int* offs = (int*)pool_alloc(sizeof(int) * 256 * (size_t)rs);
     int* dtot = (int*)pool_alloc(sizeof(int) * 256);
     uint64_t *ka = keys, *kb = kalt;
     uint32_t *va = vals, *vb = vals ? valt : nullptr;
@@ -354,12 +371,12 @@ uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint
     if (begin_bit + 8 * npass > 64) begin_bit = 64 - 8 * npass;
     for (int pass = 0; pass < npass; ++pass) {
         const int shift = begin_bit + 8 * pass;
-        k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, nblk, hist);
+        k_rs_hist<<<nblk, kRsThreads, 0, s>>>(ka, n, shift, rs, hist);
         SFMM_LAUNCH_CHECK();
-        k_rs_rowscan<<<256, kScanThreads, 0, s>>>(hist, nblk, offs, dtot);
+        k_rs_rowscan<<<256, kScanThreads, 0, s>>>(hist, nblk, rs, offs, dtot);
         SFMM_LAUNCH_CHECK();
         const bool last = pass == npass - 1;
-        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, nblk, offs, dtot, last ? lo_out : nullptr,
+        k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, rs, offs, dtot, last ? lo_out : nullptr,
                                                  last ? hi_out : nullptr);
         SFMM_LAUNCH_CHECK();
         std::swap(ka, kb);

@@ -666,11 +666,15 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_classify(const int2* __re
     }
 }
 
-// exclusive scans of the three chunk-total arrays (one workgroup each, in
-// pieces of 256 with a running carry); tot[j] = the total of array j
-__global__ void __launch_bounds__(256) k_walk_chunk_scan(const int* __restrict__ st, const int* __restrict__ ctot,
-                                                         int cstride, int* __restrict__ coff, int* __restrict__ tot) {
-    __shared__ int sh[256 / 64];
+// exclusive scans of the three chunk-total arrays (one workgroup of
+// kChunkScanThreads each, in pieces of that size with a running carry);
+// tot[j] = the total of array j
+constexpr int kChunkScanThreads = 1024;
+__global__ void __launch_bounds__(kChunkScanThreads) k_walk_chunk_scan(const int* __restrict__ st,
+                                                                       const int* __restrict__ ctot, int cstride,
+                                                                       int* __restrict__ coff, int* __restrict__ tot) {
+    constexpr int kWaves = kChunkScanThreads / 64;
+    __shared__ int sh[kWaves];
     const int n = st[0];
     const int nchunk = (n + kWalkChunk - 1) / kWalkChunk;
     const int j = blockIdx.x;
@@ -678,7 +682,7 @@ __global__ void __launch_bounds__(256) k_walk_chunk_scan(const int* __restrict__
     int* out = coff + (size_t)j * cstride;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int carry = 0;
-    for (int c0 = 0; c0 < nchunk; c0 += 256) {
+    for (int c0 = 0; c0 < nchunk; c0 += kChunkScanThreads) {
         const int i = c0 + threadIdx.x;
         const int v = i < nchunk ? in[i] : 0;
         int x = v;
@@ -691,7 +695,7 @@ __global__ void __launch_bounds__(256) k_walk_chunk_scan(const int* __restrict__
         __syncthreads();
         int before = 0, all = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kWaves; ++q) {
             before += q < wv ? sh[q] : 0;
             all += sh[q];
         }
@@ -780,7 +784,7 @@ void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* ac
                      int cstride, int* tot, int grid, hipStream_t s) {
     k_walk_classify<<<grid, kWalkThreads, 0, s>>>(F, st, w, action, ctot, cstride);
     SFMM_LAUNCH_CHECK();
-    k_walk_chunk_scan<<<3, 256, 0, s>>>(st, ctot, cstride, coff, tot);
+    k_walk_chunk_scan<<<3, kChunkScanThreads, 0, s>>>(st, ctot, cstride, coff, tot);
     SFMM_LAUNCH_CHECK();
 }
 

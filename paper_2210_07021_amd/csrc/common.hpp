@@ -105,6 +105,9 @@ void fill_f32(float* p, size_t n, float v, hipStream_t s);
 void fill_i32(int* p, size_t n, int v, hipStream_t s);
 // exclusive scan of n ints; the total goes to *total (device)
 void scan_excl_i32(const int* in, int* out, int64_t n, int* total, hipStream_t s);
+// three scans of n ints in one set of launches; total[0..2] their totals
+void scan3_excl_i32(const int* in0, const int* in1, const int* in2, int* out0, int* out1, int* out2, int64_t n,
+                    int* total, hipStream_t s);
 // stable LSD radix sort of (key, value) pairs on key bits [begin_bit, bits)
 void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int begin_bit = 0);
 // The same sort, ping-ponging between the caller's buffers (kalt / valt hold

@@ -361,9 +361,8 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     tot.resize(3);
     k_seg_count<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), nslot.data(), multi.data());
     SFMM_LAUNCH_CHECK();
-    scan_excl_i32(nseg.data(), item_off.data(), nbox, tot.data(), s);
-    scan_excl_i32(nslot.data(), slot_off.data(), nbox, tot.data() + 1, s);
-    scan_excl_i32(multi.data(), red_off.data(), nbox, tot.data() + 2, s);
+    scan3_excl_i32(nseg.data(), nslot.data(), multi.data(), item_off.data(), slot_off.data(), red_off.data(), nbox,
+                   tot.data(), s);
     int h[3];
     SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
     SFMM_HIP(hipStreamSynchronize(s));

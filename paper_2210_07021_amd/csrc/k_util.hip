@@ -156,6 +156,73 @@ __global__ void k_scan_add(int* out, int64_t n, const int* boff) {
         if (base + k < n) out[base + k] += add;
 }
 
+// Three scans of n ints at once (blockIdx.y picks the array): the same tile
+// scan / block-sum scan / add-back as scan_excl_i32, a third of the launches.
+struct Scan3 {
+    const int* in[3];
+    int* out[3];
+    int* aux[3];  // tile sums (or the totals, with a single tile)
+};
+
+__global__ void k_scan_tiles3(Scan3 a, int64_t n) {
+    __shared__ int sh[kScanThreads / 64];
+    const int j = blockIdx.y;
+    const int* in = a.in[j];
+    int* out = a.out[j];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int run = block_excl_scan(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) a.aux[j][blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add3(Scan3 a, int64_t n) {
+    const int j = blockIdx.y;
+    int* out = a.out[j];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int add = a.aux[j][blockIdx.x];
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n) out[base + k] += add;
+}
+
+void scan3_excl_i32(const int* in0, const int* in1, const int* in2, int* out0, int* out1, int* out2, int64_t n,
+                    int* total, hipStream_t s) {
+    if (n <= 0) {
+        fill_i32(total, 3, 0, s);
+        return;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    Scan3 a{{in0, in1, in2}, {out0, out1, out2}, {total, total + 1, total + 2}};
+    if (nb == 1) {
+        k_scan_tiles3<<<dim3(1, 3), kScanThreads, 0, s>>>(a, n);
+        SFMM_LAUNCH_CHECK();
+        return;
+    }
+    int* bsum = (int*)pool_alloc(sizeof(int) * 3 * nb);
+    int* boff = (int*)pool_alloc(sizeof(int) * 3 * nb);
+    for (int j = 0; j < 3; ++j) a.aux[j] = bsum + j * nb;
+    k_scan_tiles3<<<dim3((unsigned)nb, 3), kScanThreads, 0, s>>>(a, n);
+    SFMM_LAUNCH_CHECK();
+    scan3_excl_i32(bsum, bsum + nb, bsum + 2 * nb, boff, boff + nb, boff + 2 * nb, nb, total, s);
+    for (int j = 0; j < 3; ++j) a.aux[j] = boff + j * nb;
+    k_scan_add3<<<dim3((unsigned)nb, 3), kScanThreads, 0, s>>>(a, n);
+    SFMM_LAUNCH_CHECK();
+    // freed blocks are only reused by later stream-ordered work on this stream
+    pool_free(bsum);
+    pool_free(boff);
+}
+
 // Tile scans write each tile's sum to bsum; with a single tile that sum is
 // the total.  Otherwise the tile sums are scanned (their total is the total)
 // and added back.  In place (in == out) is allowed.

@@ -121,6 +121,8 @@ typedef struct {
     int64_t m2l_order_sq;           /* sum over the FMM acts of (their order)^2
                                        in the last sfmm_execute (the M2L work
                                        relative to one order-1 act); 0 before */
+    int64_t execute_scratch_bytes;  /* device scratch one execute of this plan
+                                       uses beyond the plan's own arrays     */
 } sfmm_stats;
 
 /* Fill *opt with the defaults: order 0 with tolerance 1e-10, leaf_size 64,

@@ -71,6 +71,7 @@ class Stats(ctypes.Structure):
         ("leaf_size", ctypes.c_int32),
         ("q_total", ctypes.c_double),
         ("m2l_order_sq", ctypes.c_int64),
+        ("execute_scratch_bytes", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -27,11 +27,37 @@ enum { ST_OK = 0, ST_INVALID_ARG = 1, ST_OOM = 2, ST_HIP = 3, ST_TOL = 4, ST_INT
 
 #define SFMM_LAUNCH_CHECK() SFMM_HIP(hipGetLastError())
 
-// Caching device allocator: freed blocks are kept per size class and reused,
-// so steady-state planning does no hipMalloc.
+// Caching device allocator: freed blocks are kept per size class and device
+// and reused, so steady-state planning does no hipMalloc.  A freed block is
+// reused only once the work queued before its release has finished, or by
+// work on the same stream (stream order covers it): every API call names its
+// stream with a PoolStream scope (capturing: a graph is being recorded on
+// it; idle: the caller has already waited for all work that used the blocks
+// freed in this scope).
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 void pool_release_all();
+struct PoolStream {
+    hipStream_t prev_s;
+    bool prev_cap, prev_idle;
+    explicit PoolStream(hipStream_t s, bool capturing = false, bool idle = false);
+    ~PoolStream();
+    PoolStream(const PoolStream&) = delete;
+    PoolStream& operator=(const PoolStream&) = delete;
+};
+// The reuse rule, exposed for host-side tests: a cached block freed on
+// stream `s_free` (with an event when has_event) may serve an allocation on
+// stream `s` of device `dev`.
+struct PoolBlockState {
+    int dev;
+    hipStream_t s;
+    bool has_event, event_done;
+};
+inline bool pool_reusable(const PoolBlockState& b, hipStream_t s, int dev) {
+    if (b.dev != dev) return false;
+    if (!b.has_event) return true;  // released after its users were waited for
+    return b.s == s || b.event_done;
+}
 
 template <typename T>
 struct DVec {
@@ -76,6 +102,10 @@ struct DVec {
 };
 
 constexpr int kMaxOrder = 48;
+// the order policy's measured error at order p (relative L2 of the
+// deflection, worst over the calibration skies; the tolerance that gives
+// order p is 4 times this)
+double order_calibrated_error(int p);
 // per-pair order policies: orders are multiples of kOrderStep; the order
 // network maps kMlpIn features through two kMlpHidden ReLU layers to one
 // output (kMlpWeights floats: W1, b1, W2, b2, w3, b3)
@@ -137,7 +167,7 @@ void tree_split_flags(int b0, int nb, const int* level, const int* count, int m,
                       hipStream_t s);
 void tree_make_children(int b0, int nb, int child_base, const int* flag, const int* off, const uint64_t* keys,
                         int* level, uint64_t* pixel, int* first, int* count, int* parent, int* child0,
-                        hipStream_t s);
+                        int wave_level, hipStream_t s);
 void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen /*[nb][4]: x,y,z,rho*/,
                   double* rad, double* gdd /*[nb][8]*/, hipStream_t s);
 void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const int* level, uint64_t* leaf,
@@ -146,11 +176,14 @@ void locate_targets(const uint64_t* keys, int64_t m, const int* child0, const in
 // at least ceil(cap / kTreeChunk) entries, per-box ranks wpre of cap
 // entries, overflow flag ctl[0]).
 constexpr int kTreeChunk = 1024;
-constexpr int kWaveLevel = 65536;  // levels below this many boxes use a wave per box
+// levels below wave_level boxes take a wave per box, larger ones a lane per
+// box; kWaveLevel is the default (SFMM_WAVE_LEVEL overrides it, for tests)
+constexpr int kWaveLevel = 65536;
+int tree_wave_level();
 void tree_init_queued(int* ls, int nls, int* ctl, hipStream_t s);
 void tree_level_queued(int* ls, int L, int* ccnt, int* wpre, int grid, int cgrid, int cap, int* ctl, int m,
                        int split_ok, const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
-                       int* parent, int* child0, hipStream_t s);
+                       int* parent, int* child0, int wave_level, hipStream_t s);
 void target_ranges(const int* leaf, int64_t m, int nbox, int* tfirst, int* tcount, hipStream_t s);
 void flag_nonzero(const int* count, int n, int* flag, hipStream_t s);
 void compact_index(const int* flag, const int* off, int n, int* out, hipStream_t s);
@@ -262,12 +295,14 @@ void near_work(const int* count, const NearLists& nl, const int* tcount, int nbo
                long long* evals, hipStream_t s);
 // fp32: the precision tier's pair arithmetic (two-float coordinates, FP32
 // log / reciprocal, FP64 sums per tile)
+// part: the partial slots of the split boxes ([w.nslot][4] doubles), or
+// null for the work items' own buffer w.part
 void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
              const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s);
+             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part = nullptr);
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s);
+             double* defl, int64_t m_out, hipStream_t s, double* part = nullptr);
 
 // ---------------------------------------------------------------- order policies
 void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s);

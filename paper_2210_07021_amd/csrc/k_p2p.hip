@@ -63,12 +63,12 @@ constexpr int kM2PMinOrder = 12;
 // A close leaf S is evaluated through its Lemma 1 expansion at the targets
 // of T when every target is beyond ratio R_S from its centre, ratio = 1 / x
 // with the truncation term x^(p+1) at most 1e-4 tau_p (tau_p: the tolerance
-// that gives order p, 1e-10 at p = 36 by the order policy), and at least 3:
-// ratio 3 down to p = 20, 4.4 at p = 12.  And when S holds at least p/4 + 2
-// particles (measured at p = 36: lower ratios or a higher count move more
-// work than they save).
+// that gives order p by the order policy, 4 times its calibrated error), and
+// at least 3: ratio 3 down to p = 23, 3.4 at p = 18, 4.5 at p = 12.  And when S holds at
+// least p/4 + 2 particles (measured at p = 36: lower ratios or a higher count
+// move more work than they save).
 double m2p_ratio(int p) {
-    const double tau = 1e-10 * std::exp((p - 36) * std::log(0.58));
+    const double tau = 4.0 * order_calibrated_error(p);
     const double x = std::min(1.0 / 3.0, std::pow(1e-4 * tau, 1.0 / (p + 1)));
     return 1.0 / x;
 }
@@ -717,40 +717,41 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
 }
 
 void reduce_items(const WorkItems& w, const int* tfirst, const int* tcount, const uint32_t* tperm, double* psi,
-                  double* defl, int64_t m_out, hipStream_t s) {
+                  double* defl, int64_t m_out, double* part, hipStream_t s) {
     if (w.nred <= 0) return;
-    k_near_reduce<<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, w.part.data(), psi, defl,
-                                                  m_out);
+    k_near_reduce<<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, part, psi, defl, m_out);
     SFMM_LAUNCH_CHECK();
 }
 
 void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
              const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s) {
+             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part) {
     if (w.n <= 0) return;
+    if (!part) part = w.part.data();
     if (fp32)
         k_p2p<TileF32><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, w.part.data(), kLogPoly);
+                                                    defl, m_out, part, kLogPoly);
     else
         k_p2p<TileF64><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, w.part.data(), kLogPoly);
+                                                    defl, m_out, part, kLogPoly);
     SFMM_LAUNCH_CHECK();
-    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s);
 }
 
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s) {
+             double* defl, int64_t m_out, hipStream_t s, double* part) {
     if (w.n <= 0 || c.p < kM2PMinOrder) return;
+    if (!part) part = w.part.data();
 #define L_(P)                                                                                             \
     case P:                                                                                               \
         k_m2p<P><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, \
-                                              defl, m_out, w.part.data());                                \
+                                              defl, m_out, part);                                         \
         break;
     SFMM_DISPATCH(c.p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
-    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, s);
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s);
 }
 
 }  // namespace sfmm

@@ -4,6 +4,9 @@
 #include "common.hpp"
 #include "geom.hpp"
 
+#include <algorithm>
+#include <cstdlib>
+
 namespace sfmm {
 
 static unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
@@ -220,9 +223,9 @@ __global__ void k_make_children_wave(int b0, int nb, int child_base, const int* 
 
 void tree_make_children(int b0, int nb, int child_base, const int* flag, const int* off, const uint64_t* keys,
                         int* level, uint64_t* pixel, int* first, int* count, int* parent, int* child0,
-                        hipStream_t s) {
+                        int wave_level, hipStream_t s) {
     if (nb <= 0) return;
-    if (nb < kWaveLevel) {
+    if (nb < wave_level) {
         k_make_children_wave<<<nblocks((int64_t)nb * 64, 256), 256, 0, s>>>(b0, nb, child_base, flag, off, keys,
                                                                            level, pixel, first, count, parent,
                                                                            child0);
@@ -307,7 +310,7 @@ __device__ int wave_sum_prefix(const int* ccnt, int n) {
 }
 
 // Children of every box of the level: a wave per box on levels of fewer
-// than kWaveLevel boxes, else a lane per box (grid-stride either way).  A
+// than wave_level boxes, else a lane per box (grid-stride either way).  A
 // split box's slot is the split count of the chunks before its own (summed
 // here from the per-chunk counts) plus its rank in its chunk.  The first
 // wave of workgroup 0 sums all chunks: the next level's bounds ls[L+2], or
@@ -316,7 +319,7 @@ __device__ int wave_sum_prefix(const int* ccnt, int n) {
 __global__ void __launch_bounds__(kTreeThreads) k_tree_children(int* ls, int L, const int* ccnt, const int* wpre,
                                                                  int* ctl, int cap, const uint64_t* __restrict__ keys,
                                                                  int* level, uint64_t* pixel, int* first, int* count,
-                                                                 int* parent, int* child0) {
+                                                                 int* parent, int* child0, int wave_level) {
     if (ctl[0]) {  // an earlier level overflowed: this one stays empty
         if (blockIdx.x == 0 && threadIdx.x == 0) ls[L + 2] = ls[L + 1];
         return;
@@ -337,7 +340,7 @@ __global__ void __launch_bounds__(kTreeThreads) k_tree_children(int* ls, int L, 
         }
     }
     const int nw = gridDim.x * (kTreeThreads / 64);
-    if (nb < kWaveLevel) {
+    if (nb < wave_level) {
         for (int i = blockIdx.x * (kTreeThreads / 64) + wave; i < nb; i += nw) {
             const int r = wpre[i];
             const int pre = wave_sum_prefix(ccnt, i / kTreeChunk);
@@ -361,6 +364,13 @@ __global__ void __launch_bounds__(kTreeThreads) k_tree_children(int* ls, int L, 
     }
 }
 
+int tree_wave_level() {
+    const char* v = std::getenv("SFMM_WAVE_LEVEL");
+    if (!v) return kWaveLevel;
+    const long w = std::strtol(v, nullptr, 10);
+    return (int)std::max(0L, std::min(w, 0x7fffffffL));
+}
+
 void tree_init_queued(int* ls, int nls, int* ctl, hipStream_t s) {
     k_tree_init<<<1, 64, 0, s>>>(ls, nls, ctl);
     SFMM_LAUNCH_CHECK();
@@ -368,11 +378,11 @@ void tree_init_queued(int* ls, int nls, int* ctl, hipStream_t s) {
 
 void tree_level_queued(int* ls, int L, int* ccnt, int* wpre, int grid, int cgrid, int cap, int* ctl, int m,
                        int split_ok, const uint64_t* keys, int* level, uint64_t* pixel, int* first, int* count,
-                       int* parent, int* child0, hipStream_t s) {
+                       int* parent, int* child0, int wave_level, hipStream_t s) {
     k_tree_count<<<grid, kTreeThreads, 0, s>>>(ls, L, count, m, split_ok, ccnt, wpre);
     SFMM_LAUNCH_CHECK();
     k_tree_children<<<cgrid, kTreeThreads, 0, s>>>(ls, L, ccnt, wpre, ctl, cap, keys, level, pixel, first, count,
-                                                   parent, child0);
+                                                   parent, child0, wave_level);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -9,11 +9,42 @@
 namespace sfmm {
 
 // ------------------------------------------------------------------ pool
+// A freed block is not handed out again until the work that may still use
+// it has finished: pool_free records an event on the stream of the current
+// API call (PoolStream), and pool_alloc takes a cached block only if it was
+// freed on the stream now allocating (stream order then covers the reuse) or
+// its event has completed.  Blocks are kept per device.  While a stream is
+// being captured into a graph no event is recorded and the block is retired
+// instead (graph replays may still use it; it is released with the pool).
 namespace {
+struct FreeBlock {
+    void* p;
+    int dev;
+    hipStream_t s;
+    hipEvent_t ev;  // null: reusable at once
+};
 std::mutex g_pool_mu;
-std::multimap<size_t, void*> g_free;           // size -> block
-std::unordered_map<void*, size_t> g_size;      // live and free blocks
+std::multimap<size_t, FreeBlock> g_free;              // size -> block
+std::unordered_map<void*, std::pair<size_t, int>> g_size;  // live and free blocks: size, device
+std::vector<hipEvent_t> g_spare_events;
+std::vector<void*> g_retired;
+thread_local hipStream_t t_stream = nullptr;
+thread_local bool t_capturing = false;
+thread_local bool t_idle = false;
 }  // namespace
+
+PoolStream::PoolStream(hipStream_t s, bool capturing, bool idle)
+    : prev_s(t_stream), prev_cap(t_capturing), prev_idle(t_idle) {
+    t_stream = s;
+    t_capturing = capturing;
+    t_idle = idle;
+}
+
+PoolStream::~PoolStream() {
+    t_stream = prev_s;
+    t_capturing = prev_cap;
+    t_idle = prev_idle;
+}
 
 static size_t size_class(size_t b) {
     if (b < 512) return 512;
@@ -26,11 +57,21 @@ static size_t size_class(size_t b) {
 
 void* pool_alloc(size_t bytes) {
     const size_t sz = size_class(bytes);
+    int dev = 0;
+    SFMM_HIP(hipGetDevice(&dev));
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
-        auto it = g_free.lower_bound(sz);
-        if (it != g_free.end() && it->first <= 2 * sz) {
-            void* p = it->second;
+        for (auto it = g_free.lower_bound(sz); it != g_free.end() && it->first <= 2 * sz; ++it) {
+            const FreeBlock& b = it->second;
+            PoolBlockState st{b.dev, b.s, b.ev != nullptr, false};
+            if (b.ev && b.s != t_stream && b.dev == dev) {
+                const hipError_t q = hipEventQuery(b.ev);
+                if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+                st.event_done = q == hipSuccess;
+            }
+            if (!pool_reusable(st, t_stream, dev)) continue;
+            void* p = b.p;
+            if (b.ev) g_spare_events.push_back(b.ev);
             g_free.erase(it);
             return p;
         }
@@ -47,7 +88,7 @@ void* pool_alloc(size_t bytes) {
         }
     }
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    g_size[p] = sz;
+    g_size[p] = {sz, dev};
     return p;
 }
 
@@ -56,14 +97,38 @@ void pool_free(void* p) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_size.find(p);
     if (it == g_size.end()) return;
-    g_free.emplace(it->second, p);
+    if (t_capturing) {
+        g_retired.push_back(p);
+        return;
+    }
+    FreeBlock b{p, it->second.second, t_stream, nullptr};
+    if (!t_idle) {
+        if (!g_spare_events.empty()) {
+            b.ev = g_spare_events.back();
+            g_spare_events.pop_back();
+        } else if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            b.ev = nullptr;
+        }
+        // no event (creation failed): the block is retired, not reused early
+        if (!b.ev || hipEventRecord(b.ev, t_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            if (b.ev) g_spare_events.push_back(b.ev);
+            g_retired.push_back(p);
+            return;
+        }
+    }
+    g_free.emplace(it->second.first, b);
 }
 
 void pool_release_all() {
+    // blocks whose last users may still run are waited for first
+    (void)hipDeviceSynchronize();
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto& kv : g_free) {
-        (void)hipFree(kv.second);
-        g_size.erase(kv.second);
+        (void)hipFree(kv.second.p);
+        if (kv.second.ev) g_spare_events.push_back(kv.second.ev);
+        g_size.erase(kv.second.p);
     }
     g_free.clear();
 }

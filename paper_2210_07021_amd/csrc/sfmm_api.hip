@@ -48,7 +48,9 @@ struct Profiler {
         hipEvent_t a, b;
     };
     std::vector<Rec> recs;
-    explicit Profiler(hipStream_t st) : s(st), on(g_prof_on.load() != 0 && !g_capturing) {}
+    // allowed = false: no events at all (the no-allocation entry point)
+    explicit Profiler(hipStream_t st, bool allowed = true)
+        : s(st), on(allowed && g_prof_on.load() != 0 && !g_capturing) {}
     int begin(int stage) {
         if (!on) return -1;
         Rec r{stage, nullptr, nullptr};
@@ -140,6 +142,21 @@ struct sfmm_plan_impl {
     long long m2l_order_sq = 0;
     bool executed = false;
     std::unique_ptr<Pinned> pin;
+    // recorded at the end of every sfmm_plan / sfmm_execute on the caller's
+    // stream (not while a graph is recorded): sfmm_destroy waits for it
+    hipEvent_t done = nullptr;
+    void mark_done(hipStream_t s) {
+        if (g_capturing) return;
+        if (!done) SFMM_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        SFMM_HIP(hipEventRecord(done, s));
+    }
+    // host reads of the plan's buffers start after its last call's work
+    void wait() const {
+        if (done) SFMM_HIP(hipEventSynchronize(done));
+    }
+    ~sfmm_plan_impl() {
+        if (done) (void)hipEventDestroy(done);
+    }
 
     FmmCtx ctx() const {
         FmmCtx c;
@@ -226,6 +243,7 @@ void build_levels_exact(sfmm_plan_impl& P, int m, hipStream_t s) {
     P.lvl_start.assign({0, 12});
     DVec<int> flag, off, tot;
     tot.resize(1);
+    const int wave_level = tree_wave_level();
     for (int L = 0;; ++L) {
         const int b0 = P.lvl_start[L], b1 = P.lvl_start[L + 1], nb = b1 - b0;
         flag.resize(nb);
@@ -243,7 +261,7 @@ void build_levels_exact(sfmm_plan_impl& P, int m, hipStream_t s) {
         P.parent.grow(need, s);
         P.child0.grow(need, s);
         tree_make_children(b0, nb, b1, flag.data(), off.data(), P.skeys.data(), P.level.data(), P.pixel.data(),
-                           P.first.data(), P.count.data(), P.parent.data(), P.child0.data(), s);
+                           P.first.data(), P.count.data(), P.parent.data(), P.child0.data(), wave_level, s);
         P.lvl_start.push_back((int)need);
     }
 }
@@ -265,13 +283,14 @@ bool build_levels_queued(sfmm_plan_impl& P, int m, int cap, hipStream_t s) {
                     P.parent.data(), P.child0.data(), s);
     tree_init_queued(ls.data(), kLs, ctl.data(), s);
     const int lmax = P.opt.max_level;
+    const int wave_level = tree_wave_level();
     int* h = P.pin->p;
     for (int L = 0;;) {
         const int Lend = std::min(L + kTreeBatch, lmax + 1);
         for (; L < Lend; ++L)
             tree_level_queued(ls.data(), L, ccnt.data(), wpre.data(), grid, cgrid, cap, ctl.data(), m,
                               L < lmax ? 1 : 0, P.skeys.data(), P.level.data(), P.pixel.data(), P.first.data(), P.count.data(),
-                              P.parent.data(), P.child0.data(), s);
+                              P.parent.data(), P.child0.data(), wave_level, s);
         SFMM_HIP(hipMemcpyAsync(h, ls.data(), sizeof(int) * kLs, hipMemcpyDeviceToHost, s));
         SFMM_HIP(hipMemcpyAsync(h + kLs, ctl.data(), sizeof(int), hipMemcpyDeviceToHost, s));
         SFMM_HIP(hipStreamSynchronize(s));
@@ -504,10 +523,11 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
 }
 
 // Boxes that have items: the items minus the extra segments of split boxes
-int count_boxes(const WorkItems& w) {
+int count_boxes(const WorkItems& w, hipStream_t s) {
     if (w.nred == 0) return w.n;
     std::vector<int4> r(w.nred);
-    SFMM_HIP(hipMemcpy(r.data(), w.red.data(), sizeof(int4) * w.nred, hipMemcpyDeviceToHost));
+    SFMM_HIP(hipMemcpyAsync(r.data(), w.red.data(), sizeof(int4) * w.nred, hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
     int extra = 0;
     for (const int4& x : r) extra += x.y - 1;
     return w.n - extra;
@@ -559,18 +579,38 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
                 P.near_items, s);
     build_items(P.nl.far_off.data(), P.nl.far_src.data(), nullptr, P.tcount.data(), P.nbox, segf, P.far_items,
                 s);
-    P.ntl = count_boxes(P.near_items);
+    P.ntl = count_boxes(P.near_items, s);
 }
 
-// Order from a tolerance.  Measured on uniform and clustered skies at the
-// default MACs (c_s = 2, c_t = 0.5): the deflection, the slower of the two
-// outputs, falls by ~0.58 per order; its worst case is a target on a leaf
-// corner (HEALPix grid targets sit on the vertices of every deeper pixel),
-// where p = 36 leaves ~2e-11 relative L2 on the clustered skies.  The policy
-// keeps that margin of ~5 at every tolerance.
+// Order from a tolerance, by a measured calibration at the default MACs
+// (c_s = 2, c_t = 0.5).  kOrderCal[k] is the largest relative L2 error of
+// the deflection (the slower output to converge; psi is ~1000 times smaller)
+// at order p = 12 + 4k over uniform-1e4 (leaf sizes 16, 32, 64),
+// clustered-5e4 (16, 32, 64), clustered-1e6 (16, 32, 64; 1e4 sampled
+// targets) and clustered-1e7 (32, 56; 1e4 sampled targets), FP64 against the
+// direct sum.  The order is the smallest p whose error, interpolated
+// log-linearly in p (end slopes outside 12..40), is at most a quarter of the
+// tolerance.  The worst targets are on leaf corners: HEALPix grid targets
+// sit on the vertices of every deeper pixel.
+constexpr double kOrderCal[] = {9.09e-6, 6.40e-7, 5.43e-8, 5.37e-9, 6.13e-10, 8.15e-11, 1.02e-11, 1.26e-12};
+constexpr int kOrderCalN = sizeof(kOrderCal) / sizeof(kOrderCal[0]);
+constexpr double kOrderMarginFactor = 4.0;
+
+}  // namespace
+
+double sfmm::order_calibrated_error(int p) {
+    const double x = (p - 12) / 4.0;
+    const int k = std::min(kOrderCalN - 2, std::max(0, (int)std::floor(x)));
+    const double t = x - k;
+    return std::exp(std::log(kOrderCal[k]) + t * (std::log(kOrderCal[k + 1]) - std::log(kOrderCal[k])));
+}
+
+namespace {
+
 int order_for_tolerance(double tol) {
-    const int p = (int)std::ceil(36.0 + std::log(tol / 1e-10) / std::log(0.58));
-    return std::min(kMaxOrder, std::max(4, p));
+    for (int p = 4; p < kMaxOrder; ++p)
+        if (order_calibrated_error(p) * kOrderMarginFactor <= tol) return p;
+    return kMaxOrder;
 }
 
 sfmm_status fail(const Error& e) {
@@ -617,6 +657,7 @@ struct sfmm_batch_impl {
     std::vector<double*> g_psi, g_defl;  // outputs the graph was recorded with
     hipStream_t g_stream = nullptr;
     bool capturable = true;
+    hipEvent_t done = nullptr;  // end of the last sfmm_batch_execute
     void drop_graph() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
@@ -624,11 +665,122 @@ struct sfmm_batch_impl {
         graph = nullptr;
     }
     ~sfmm_batch_impl() {
+        if (done) (void)hipEventSynchronize(done);
         drop_graph();
-        for (auto* p : plans) delete p;
+        for (auto* p : plans) sfmm_destroy(p);
+        if (done) (void)hipEventDestroy(done);
         if (own) hipStreamDestroy(own);
     }
 };
+
+// Scratch of one execute taken from outside the plan (the no-allocation
+// entry point): the partial slots of both near-field work item sets and the
+// FP32 copy of the multipole A-blocks.
+struct ExecScratch {
+    double* near_part;
+    double* far_part;
+    float* multf;
+};
+
+// Bytes of ExecScratch a plan needs (each part 256-byte aligned).
+size_t exec_scratch_bytes(const sfmm_plan_impl& P, size_t* off_far = nullptr, size_t* off_multf = nullptr) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t near = al(sizeof(double) * 4 * (size_t)std::max(P.near_items.nslot, 1));
+    const size_t far = al(sizeof(double) * 4 * (size_t)std::max(P.far_items.nslot, 1));
+    const bool tier = P.n_m2l_fp64 < P.nbox;
+    const size_t mf = tier ? al(sizeof(float) * 2 * (size_t)P.p * (size_t)P.nbox) : 0;
+    if (off_far) *off_far = near;
+    if (off_multf) *off_multf = near + far;
+    return near + far + mf;
+}
+
+// The five stages of Sec. 3.7 on a plan; xs = null: the plan's own buffers.
+void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, const ExecScratch* xs) {
+    const double shift = (P.opt.psi_gauge == SFMM_GAUGE_RAW) ? -P.q_total * 0.079577471545947667884 : 0.0;
+    if (P.N == 0) {
+        fill_f64(psi, P.M, 0.0, s);
+        fill_f64(defl, 3 * P.M, 0.0, s);
+        return;
+    }
+    // every multipole record is written by Lemma 1 (leaves) or Lemma 2
+    // (split boxes), every local record by the first M2L pass
+    const FmmCtx c = P.ctx();
+    const int nlev = (int)P.lvl_start.size() - 1;
+    Profiler prof(s, xs == nullptr);
+    // up-pass: Lemma 1 on leaves, Lemma 2 from the deepest split level up
+    {
+        StageScope st(prof, S_P2M);
+        fmm_p2m(c, P.nbox, s);
+    }
+    {
+        StageScope st(prof, S_M2M);
+        for (int L = nlev - 2; L >= 0; --L)
+            fmm_m2m(c, P.lvl_start[L], P.lvl_start[L + 1] - P.lvl_start[L], s);
+    }
+    // FMM acts: Lemma 3
+    {
+        StageScope st(prof, S_M2L);
+        const bool tier = P.n_m2l_fp64 < P.nbox;
+        float* multf = xs ? xs->multf : nullptr;
+        if (tier) {
+            if (!xs) {
+                P.multf.resize((size_t)P.nbox * 2 * P.p);
+                multf = P.multf.data();
+            }
+            mult_to_f32(c, P.nbox, multf, s);
+        }
+        // one pass per order: (order, CSR offsets, sources); the first pass
+        // writes the local records, later ones add to them
+        auto m2l_pass = [&](int p, bool acc, const int* off, const int* src) {
+            fmm_m2l(c, p, acc, P.m2l_order.data(), P.n_m2l_fp64, off, src, s);
+            if (tier)
+                fmm_m2l_f32(c, p, acc, multf, P.m2l_order.data() + P.n_m2l_fp64,
+                            P.nbox - P.n_m2l_fp64, off, src, s);
+        };
+        if (P.opt.order_policy == SFMM_ORDER_FIXED || P.n_m2l == 0) {
+            m2l_pass(P.p, false, P.m2l_off.data(), P.m2l_src.data());
+            P.m2l_order_sq = (long long)P.n_m2l * P.p * P.p;
+        } else {
+            const double kt = SFMM_ORDER_KAPPA * P.opt.tolerance;
+            P.m2l_ord.resize(P.n_m2l);
+            if (P.opt.order_policy == SFMM_ORDER_BOUND) {
+                order_bound(c, P.m2l_ent.data(), P.m2l_src.data(), P.n_m2l, kt, P.m2l_ord.data(), s);
+            } else {
+                P.decay.resize(P.nbox);
+                order_box_decay(c, P.nbox, P.decay.data(), s);
+                order_mlp(c, P.m2l_ent.data(), P.m2l_src.data(), P.decay.data(), kt, nullptr, P.n_m2l,
+                          P.mlp_w.data(), P.p, kOrderMargin, P.m2l_ord.data(), nullptr, s);
+            }
+            P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
+                                         P.p, P.ord_off, P.ord_src, s);
+            for (int q = 0; q < P.p / kOrderStep; ++q)
+                m2l_pass((q + 1) * kOrderStep, q > 0, P.ord_off.data() + (size_t)q * P.nbox, P.ord_src.data());
+            m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
+        }
+    }
+    // down-pass: Lemma 4 from level 1 down
+    {
+        StageScope st(prof, S_L2L);
+        for (int L = 1; L < nlev; ++L) fmm_l2l(c, P.lvl_start[L], P.lvl_start[L + 1] - P.lvl_start[L], s);
+    }
+    // far field at the targets, then the direct acts
+    {
+        StageScope st(prof, S_L2P);
+        fmm_l2p(c, P.tx.data(), P.ty.data(), P.tz.data(), P.tleaf.data(), P.tperm.data(), P.M, shift, psi,
+                defl, P.M, s);
+    }
+    {
+        StageScope st(prof, S_M2P);
+        fmm_m2p(c, P.far_items, P.nl.far_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
+                P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s, xs ? xs->far_part : nullptr);
+    }
+    {
+        StageScope st(prof, S_P2P);
+        fmm_p2p(c, P.opt.precision == SFMM_FP32_MIXED, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
+                P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s, xs ? xs->near_part : nullptr);
+    }
+    prof.flush();
+}
 
 extern "C" {
 
@@ -661,6 +813,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         else sfmm_default_options(&o);
         validate(o);
         hipStream_t s = (hipStream_t)stream;
+        PoolStream ps(s);
         std::unique_ptr<sfmm_plan_impl> P(new sfmm_plan_impl());
         P->pin.reset(new Pinned());
         P->opt = o;
@@ -678,7 +831,8 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
             DVec<double> qt;
             qt.resize(1);
             sum_f64(q, N, qt.data(), s);  // the caller's charges, contiguous
-            SFMM_HIP(hipMemcpy(&P->q_total, qt.data(), sizeof(double), hipMemcpyDeviceToHost));
+            SFMM_HIP(hipMemcpyAsync(&P->q_total, qt.data(), sizeof(double), hipMemcpyDeviceToHost, s));
+            SFMM_HIP(hipStreamSynchronize(s));
         }
         build_tree(*P, s, prof);
         build_lists(*P, s, prof);
@@ -699,6 +853,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         P->zrec.resize(2 * (size_t)P->p + 2);
         fill_f64(P->zrec.data(), 2 * (size_t)P->p + 2, 0.0, s);
         SFMM_HIP(hipStreamSynchronize(s));
+        P->mark_done(s);
         *out = P.release();
         return SFMM_OK;
     } catch (const Error& e) {
@@ -716,87 +871,10 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         if (P.M == 0) return SFMM_OK;
         if (!psi || !defl) throw Error(ST_INVALID_ARG, "psi or defl is NULL");
         hipStream_t s = (hipStream_t)stream;
-        const double shift = (P.opt.psi_gauge == SFMM_GAUGE_RAW) ? -P.q_total * 0.079577471545947667884 : 0.0;
-        if (P.N == 0) {
-            fill_f64(psi, P.M, 0.0, s);
-            fill_f64(defl, 3 * P.M, 0.0, s);
-            return SFMM_OK;
-        }
-        // every multipole record is written by Lemma 1 (leaves) or Lemma 2
-        // (split boxes), every local record by the first M2L pass
-        const FmmCtx c = P.ctx();
-        const int nlev = (int)P.lvl_start.size() - 1;
-        Profiler prof(s);
-        // up-pass: Lemma 1 on leaves, Lemma 2 from the deepest split level up
-        {
-            StageScope st(prof, S_P2M);
-            fmm_p2m(c, P.nbox, s);
-        }
-        {
-            StageScope st(prof, S_M2M);
-            for (int L = nlev - 2; L >= 0; --L)
-                fmm_m2m(c, P.lvl_start[L], P.lvl_start[L + 1] - P.lvl_start[L], s);
-        }
-        // FMM acts: Lemma 3
-        {
-            StageScope st(prof, S_M2L);
-            const bool tier = P.n_m2l_fp64 < P.nbox;
-            if (tier) {
-                P.multf.resize((size_t)P.nbox * 2 * P.p);
-                mult_to_f32(c, P.nbox, P.multf.data(), s);
-            }
-            // one pass per order: (order, CSR offsets, sources); the first pass
-            // writes the local records, later ones add to them
-            auto m2l_pass = [&](int p, bool acc, const int* off, const int* src) {
-                fmm_m2l(c, p, acc, P.m2l_order.data(), P.n_m2l_fp64, off, src, s);
-                if (tier)
-                    fmm_m2l_f32(c, p, acc, P.multf.data(), P.m2l_order.data() + P.n_m2l_fp64,
-                                P.nbox - P.n_m2l_fp64, off, src, s);
-            };
-            if (P.opt.order_policy == SFMM_ORDER_FIXED || P.n_m2l == 0) {
-                m2l_pass(P.p, false, P.m2l_off.data(), P.m2l_src.data());
-                P.m2l_order_sq = (long long)P.n_m2l * P.p * P.p;
-            } else {
-                const double kt = SFMM_ORDER_KAPPA * P.opt.tolerance;
-                P.m2l_ord.resize(P.n_m2l);
-                if (P.opt.order_policy == SFMM_ORDER_BOUND) {
-                    order_bound(c, P.m2l_ent.data(), P.m2l_src.data(), P.n_m2l, kt, P.m2l_ord.data(), s);
-                } else {
-                    P.decay.resize(P.nbox);
-                    order_box_decay(c, P.nbox, P.decay.data(), s);
-                    order_mlp(c, P.m2l_ent.data(), P.m2l_src.data(), P.decay.data(), kt, nullptr, P.n_m2l,
-                              P.mlp_w.data(), P.p, kOrderMargin, P.m2l_ord.data(), nullptr, s);
-                }
-                P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
-                                             P.p, P.ord_off, P.ord_src, s);
-                for (int q = 0; q < P.p / kOrderStep; ++q)
-                    m2l_pass((q + 1) * kOrderStep, q > 0, P.ord_off.data() + (size_t)q * P.nbox, P.ord_src.data());
-                m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
-            }
-        }
-        // down-pass: Lemma 4 from level 1 down
-        {
-            StageScope st(prof, S_L2L);
-            for (int L = 1; L < nlev; ++L) fmm_l2l(c, P.lvl_start[L], P.lvl_start[L + 1] - P.lvl_start[L], s);
-        }
-        // far field at the targets, then the direct acts
-        {
-            StageScope st(prof, S_L2P);
-            fmm_l2p(c, P.tx.data(), P.ty.data(), P.tz.data(), P.tleaf.data(), P.tperm.data(), P.M, shift, psi,
-                    defl, P.M, s);
-        }
-        {
-            StageScope st(prof, S_M2P);
-            fmm_m2p(c, P.far_items, P.nl.far_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
-                    P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
-        }
-        {
-            StageScope st(prof, S_P2P);
-            fmm_p2p(c, P.opt.precision == SFMM_FP32_MIXED, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
-                    P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s);
-        }
-        prof.flush();
+        PoolStream ps(s, g_capturing);
+        execute_impl(P, psi, defl, s, nullptr);
         P.executed = true;
+        P.mark_done(s);
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);
@@ -813,7 +891,9 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         return SFMM_ERR_INVALID_ARG;
     }
     try {
+        PoolStream ps(nullptr);
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         std::memset(out, 0, sizeof(*out));
         out->n_sources = P.N;
         out->n_targets = P.M;
@@ -843,6 +923,7 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->order = P.p;
         out->leaf_size = P.opt.leaf_size;
         out->q_total = P.q_total;
+        out->execute_scratch_bytes = (int64_t)exec_scratch_bytes(P);
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);
@@ -854,6 +935,7 @@ sfmm_status sfmm_export_boxes(sfmm_plan_t plan, int32_t* level, int64_t* pixel, 
     try {
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         const size_t nb = P.nbox;
         copy_widen(level, P.level.data(), nb);
         copy_widen(pixel, P.pixel.data(), nb);
@@ -879,6 +961,7 @@ sfmm_status sfmm_export_lists(sfmm_plan_t plan, int64_t* m2l_src, int64_t* m2l_t
     try {
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         export_csr(P.m2l_off, P.m2l_src, P.nbox, P.n_m2l, m2l_src, m2l_tgt);
         export_csr(P.p2p_off, P.p2p_src, P.nbox, P.n_p2p, p2p_src, p2p_tgt);
         return SFMM_OK;
@@ -892,6 +975,7 @@ sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_
     try {
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         copy_widen(src_keys, P.skeys.data(), P.N);
         copy_widen(src_perm, P.sperm.data(), P.N);
         copy_widen(tgt_perm, P.tperm.data(), P.M);
@@ -911,8 +995,10 @@ sfmm_status sfmm_export_keys(sfmm_plan_t plan, uint64_t* src_keys, int64_t* src_
 
 sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pairs, int64_t* evals) {
     try {
+        PoolStream ps(nullptr);
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         if (P.N == 0 || P.nbox == 0) return SFMM_OK;
         copy_widen(tgt_count, P.tcount.data(), P.nbox);
         DVec<long long> w;
@@ -928,8 +1014,10 @@ sfmm_status sfmm_export_work(sfmm_plan_t plan, int64_t* tgt_count, int64_t* pair
 
 sfmm_status sfmm_export_expansions(sfmm_plan_t plan, double* multipole, double* local) {
     try {
+        PoolStream ps(nullptr);
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         const sfmm_plan_impl& P = *plan;
+        P.wait();
         if (!P.executed) throw Error(ST_INVALID_ARG, "plan has not been executed");
         const int p = P.p, w = 2 * p + 2;
         const size_t nb = P.nbox;
@@ -962,10 +1050,12 @@ sfmm_status sfmm_export_expansions(sfmm_plan_t plan, double* multipole, double* 
 sfmm_status sfmm_order_samples(sfmm_plan_t plan, int64_t n, uint64_t seed, float* features, float* labels,
                                int64_t* pairs) {
     try {
+        PoolStream ps(nullptr);
         if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
         if (n < 0 || n > 0x7fffffff) throw Error(ST_INVALID_ARG, "n must be in [0, 2^31 - 1]");
         if (n > 0 && (!features || !labels)) throw Error(ST_INVALID_ARG, "features or labels is NULL");
         sfmm_plan_impl& P = *plan;
+        P.wait();
         if (!P.executed) throw Error(ST_INVALID_ARG, "plan has not been executed");
         if (n == 0) return SFMM_OK;
         if (P.n_m2l == 0) throw Error(ST_INVALID_ARG, "plan has no FMM acts");
@@ -1037,6 +1127,7 @@ void sfmm_mlp_init(uint64_t seed, float* weights) {
 sfmm_status sfmm_mlp_grad(const float* weights, const float* features, const float* labels, int64_t n,
                           float* grad, float* loss) {
     try {
+        PoolStream ps(nullptr);
         if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
         if (!weights || !grad || (n > 0 && (!features || !labels)))
             throw Error(ST_INVALID_ARG, "NULL buffer");
@@ -1069,6 +1160,7 @@ sfmm_status sfmm_mlp_grad(const float* weights, const float* features, const flo
 sfmm_status sfmm_mlp_train(const float* features, const float* labels, int64_t n, int32_t epochs, int32_t batch,
                            float lr, uint64_t seed, float* weights, float* epoch_loss) {
     try {
+        PoolStream ps(nullptr);
         if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
         if (batch < 1 || epochs < 0 || !(lr > 0.0f)) throw Error(ST_INVALID_ARG, "batch, epochs or lr out of range");
         if (!weights || (n > 0 && (!features || !labels))) throw Error(ST_INVALID_ARG, "NULL buffer");
@@ -1132,6 +1224,7 @@ sfmm_status sfmm_mlp_train(const float* features, const float* labels, int64_t n
 
 sfmm_status sfmm_mlp_forward(const float* weights, const float* features, int64_t n, int32_t bf16, float* y) {
     try {
+        PoolStream ps(nullptr);
         if (n < 0 || n > (1 << 26)) throw Error(ST_INVALID_ARG, "n must be in [0, 2^26]");
         if (!weights || (n > 0 && (!features || !y))) throw Error(ST_INVALID_ARG, "NULL buffer");
         if (n == 0) return SFMM_OK;
@@ -1165,6 +1258,7 @@ sfmm_status sfmm_batch_plan(int32_t nshell, const double* const* src, const doub
         if (!src || !q || !N || !tgt || !M) throw Error(ST_INVALID_ARG, "NULL array");
         std::unique_ptr<sfmm_batch_impl> B(new sfmm_batch_impl());
         hipStream_t s = (hipStream_t)stream;
+        PoolStream ps(s);
         if (!s) SFMM_HIP(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
         for (int i = 0; i < nshell; ++i) {
             sfmm_plan_t p = nullptr;
@@ -1238,6 +1332,8 @@ sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* c
             B.g_stream = s;
             SFMM_HIP(hipGraphLaunch(B.exec, s));
         }
+        if (!B.done) SFMM_HIP(hipEventCreateWithFlags(&B.done, hipEventDisableTiming));
+        SFMM_HIP(hipEventRecord(B.done, s));
         if (!caller) SFMM_HIP(hipStreamSynchronize(s));
         return SFMM_OK;
     } catch (const Error& e) {
@@ -1248,9 +1344,19 @@ sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* c
     }
 }
 
-void sfmm_batch_destroy(sfmm_batch_t batch) { delete batch; }
+void sfmm_batch_destroy(sfmm_batch_t batch) {
+    if (!batch) return;
+    PoolStream ps(nullptr, false, true);  // the destructor waits for the batch's work
+    delete batch;
+}
 
-void sfmm_destroy(sfmm_plan_t plan) { delete plan; }
+void sfmm_destroy(sfmm_plan_t plan) {
+    if (!plan) return;
+    // wait for the plan's last call, then its blocks may serve any stream
+    if (plan->done) (void)hipEventSynchronize(plan->done);
+    PoolStream ps(nullptr, false, true);
+    delete plan;
+}
 
 const char* sfmm_status_string(sfmm_status s) {
     switch (s) {

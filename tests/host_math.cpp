@@ -10,6 +10,10 @@
 //            leaves undecided; the undecided ones go to the double-double
 //            sine-form test, checked against the double-double angle test
 //            and against long double where that settles the sign
+//   pool   : reads "dev stream has_event event_done alloc_stream alloc_dev"
+//            rows (integers; streams as small handles), prints the memory
+//            pool's reuse decision (1 = the cached block may be handed out)
+#include "../paper_2210_07021_amd/csrc/common.hpp"
 #include "../paper_2210_07021_amd/csrc/expand.hpp"
 #include "../paper_2210_07021_amd/csrc/geom.hpp"
 #include <cmath>
@@ -29,6 +33,14 @@ static long double angle_ld(const double* a, const double* b) {
 
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
+    if (!strcmp(argv[1], "pool")) {
+        long d, st, he, ed, as, ad;
+        while (scanf("%ld %ld %ld %ld %ld %ld", &d, &st, &he, &ed, &as, &ad) == 6) {
+            PoolBlockState b{(int)d, (hipStream_t)(intptr_t)st, he != 0, ed != 0};
+            printf("%d\n", pool_reusable(b, (hipStream_t)(intptr_t)as, (int)ad) ? 1 : 0);
+        }
+        return 0;
+    }
     if (!strcmp(argv[1], "sincos")) {
         double hi, lo;
         while (scanf("%lf %lf", &hi, &lo) == 2) {

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from paper_2210_07021_amd import skies
+from parity_util import check, errors
 
 pytestmark = pytest.mark.gpu
 
@@ -41,23 +42,38 @@ def _say(msg):
 
 
 # ------------------------------------------------------------- bit-exact tree
+# (name, sky, leaf size, SFMM_WAVE_LEVEL).  Levels of fewer than 65,536 boxes
+# get their children from a wave per box, larger ones from a lane per box;
+# wave level 0 sends every level of the small cases down the lane path, and
+# uniform-3e5 at m = 4 has a genuine level of ~1.4e5 boxes (level 7), as the
+# clustered-1e7 workload has (its uniform part alone fills level 7).
 TREE_CASES = [
-    ("uniform-20k-m64", lambda r: skies.uniform(20000, r), 64),
-    ("clustered-30k-m16", lambda r: skies.clustered(30000, r, n_clumps=60), 16),
-    ("uniform-3k-m1", lambda r: skies.uniform(3000, r), 1),
+    ("uniform-20k-m64", lambda r: skies.uniform(20000, r), 64, None),
+    ("clustered-30k-m16", lambda r: skies.clustered(30000, r, n_clumps=60), 16, None),
+    ("uniform-3k-m1", lambda r: skies.uniform(3000, r), 1, None),
+    ("uniform-20k-m64-lanes", lambda r: skies.uniform(20000, r), 64, "0"),
+    ("clustered-30k-m16-lanes", lambda r: skies.clustered(30000, r, n_clumps=60), 16, "0"),
+    ("uniform-3e5-m4", lambda r: skies.uniform(300000, r), 4, None),
 ]
 
 
-@pytest.mark.parametrize("name,gen,m", TREE_CASES, ids=[c[0] for c in TREE_CASES])
-def test_tree_and_lists_bit_exact(name, gen, m, oracle_lib):
+@pytest.mark.parametrize("name,gen,m,wave", TREE_CASES, ids=[c[0] for c in TREE_CASES])
+def test_tree_and_lists_bit_exact(name, gen, m, wave, oracle_lib, monkeypatch):
     rng = skies.rng_for(100)
     src = gen(rng)
     n = src.shape[1]
     q = skies.masses_lognormal(n, rng)
     tgt = np.concatenate([skies.grid(32), skies.uniform(5000, rng), src[:, :500]], axis=1)
-    _say(f"[tree] {name}: N={n} M={tgt.shape[1]} m={m}")
+    _say(f"[tree] {name}: N={n} M={tgt.shape[1]} m={m} wave level {wave or 'default'}")
+    if wave is not None:
+        monkeypatch.setenv("SFMM_WAVE_LEVEL", wave)
     plan, psi, defl = _run(src, q, tgt, order=8, leaf_size=m)
+    monkeypatch.delenv("SFMM_WAVE_LEVEL", raising=False)
     ot = oracle.tree(src, m)
+    widest = int(np.bincount(ot.level).max())
+    _say(f"[tree] {name}: {ot.nbox} boxes, widest level {widest} boxes")
+    if name == "uniform-3e5-m4":
+        assert widest >= 65536
     # keys and sorted order
     k = plan.export_keys()
     assert np.array_equal(k["src_keys"], ot.keys)
@@ -132,12 +148,14 @@ def test_parity_uniform_1e4_all_targets(oracle_lib):
     ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
     sub = np.arange(0, tgt.shape[1], 40)
     lem = L.sfmm(src, q, tgt[:, sub], p=20, m=64)
-    dp = _rel(psi[sub], lem["psi"])
-    da = _rel(defl[:, sub], lem["defl"])
-    _say(f"[parity] uniform-1e4 p=20: vs direct sum psi {ep:.3e} alpha {ea:.3e}; "
-         f"vs printed lemmas psi {dp:.3e} alpha {da:.3e}")
+    dp, da, wdp, wda = errors(psi[sub], defl[:, sub], lem["psi"], lem["defl"])
+    _, _, wp, wa = errors(psi, defl, ref_p, ref_a)
+    _say(f"[parity] uniform-1e4 p=20: vs direct sum psi {ep:.3e} alpha {ea:.3e} (worst target {wp:.2e} "
+         f"{wa:.2e}); vs printed lemmas psi {dp:.3e} alpha {da:.3e} (worst {wdp:.2e} {wda:.2e})")
     assert dp < 1e-12 and da < 1e-11
+    assert wdp < 1e-10 and wda < 1e-9
     assert ep < 2e-9 and ea < 5e-8
+    assert wp < 2e-7 and wa < 5e-6
     plan.close()
 
 
@@ -145,9 +163,7 @@ def test_parity_tolerance_mode_uniform(oracle_lib):
     src, q, tgt = skies.workload("uniform-1e4")
     plan, psi, defl = _run(src, q, tgt, tolerance=1e-10, leaf_size=64)
     ref_p, ref_a = oracle.direct(src, q, tgt)
-    ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
-    _say(f"[parity] uniform-1e4 tol 1e-10 (p={plan.stats()['order']}): psi {ep:.3e} alpha {ea:.3e}")
-    assert ep < 1e-10 and ea < 1e-10
+    check(f"parity uniform-1e4 tol 1e-10 p={plan.stats()['order']}", psi, defl, ref_p, ref_a, 1e-10, say=_say)
     plan.close()
 
 
@@ -158,9 +174,7 @@ def test_parity_clustered_small_all_targets(oracle_lib):
     tgt = np.concatenate([skies.grid(32), src[:, :2000]], axis=1)
     plan, psi, defl = _run(src, q, tgt, tolerance=1e-10, leaf_size=32)
     ref_p, ref_a = oracle.direct(src, q, tgt)
-    ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
-    _say(f"[parity] clustered-5e4 tol 1e-10: psi {ep:.3e} alpha {ea:.3e} {plan.stats()}")
-    assert ep < 1e-10 and ea < 1e-10
+    check(f"parity clustered-5e4 tol 1e-10 {plan.stats()}", psi, defl, ref_p, ref_a, 1e-10, say=_say)
     plan.close()
 
 
@@ -178,7 +192,7 @@ def test_empty_and_tiny_inputs(oracle_lib):
         t = np.concatenate([src, skies.uniform(37, rng)], axis=1)
         _, psi, defl = _run(src, q, t, tolerance=1e-10, leaf_size=4)
         ref_p, ref_a = oracle.direct(src, q, t)
-        assert _rel(psi, ref_p) < 1e-10 and _rel(defl, ref_a) < 1e-10, n
+        check(f"tiny N={n}", psi, defl, ref_p, ref_a, 1e-10, say=_say)
 
 
 def test_coincident_and_duplicate_points(oracle_lib):
@@ -189,8 +203,7 @@ def test_coincident_and_duplicate_points(oracle_lib):
     tgt = np.concatenate([base[:, :150], skies.uniform(100, rng)], axis=1)
     _, psi, defl = _run(src, q, tgt, tolerance=1e-10, leaf_size=2)
     ref_p, ref_a = oracle.direct(src, q, tgt)
-    assert np.isfinite(psi).all() and np.isfinite(defl).all()
-    assert _rel(psi, ref_p) < 1e-10 and _rel(defl, ref_a) < 1e-10
+    check("coincident", psi, defl, ref_p, ref_a, 1e-10, say=_say)
 
 
 def test_depth_cap_and_m1(oracle_lib):
@@ -201,7 +214,7 @@ def test_depth_cap_and_m1(oracle_lib):
     ref_p, ref_a = oracle.direct(src, q, tgt)
     for opt in (dict(leaf_size=1, max_level=7), dict(leaf_size=1)):
         plan, psi, defl = _run(src, q, tgt, tolerance=1e-10, **opt)
-        assert _rel(psi, ref_p) < 1e-10 and _rel(defl, ref_a) < 1e-10, opt
+        check(f"depth cap {opt}", psi, defl, ref_p, ref_a, 1e-10, say=_say)
         plan.close()
 
 

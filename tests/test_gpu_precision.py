@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 from paper_2210_07021_amd import skies
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 
@@ -55,9 +56,7 @@ def test_fp32_mixed_at_1e6(case, oracle_lib):
     bound = 1e-5 if name.startswith("uniform") else 1e-6
     for m in (64, 16):
         st, psi, defl = _run(src, q, tgt, tolerance=1e-6, leaf_size=m, precision=sf.SFMM_FP32_MIXED)
-        ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
-        print(f"[fp32] {name} m={m} tol 1e-6 p={st['order']}: psi {ep:.3e} alpha {ea:.3e}", flush=True)
-        assert ep <= bound and ea <= bound
+        check(f"fp32 {name} m={m} tol 1e-6 p={st['order']}", psi, defl, ref_p, ref_a, bound)
 
 
 @pytest.mark.parametrize("case", ["uniform-1e4", "clustered-5e4"])
@@ -69,11 +68,9 @@ def test_fp32_mixed_error_stated_at_1e10(case, oracle_lib):
     ref_p, ref_a = oracle.direct(src, q, tgt)
     bound = 1e-5 if name.startswith("uniform") else 1e-6
     st, psi, defl = _run(src, q, tgt, tolerance=1e-10, leaf_size=32, precision=sf.SFMM_FP32_MIXED)
-    ep, ea = _rel(psi, ref_p), _rel(defl, ref_a)
-    print(f"[fp32] {name} tol 1e-10 p={st['order']}: psi {ep:.3e} alpha {ea:.3e}", flush=True)
-    assert ep <= bound and ea <= bound
+    check(f"fp32 {name} tol 1e-10 p={st['order']}", psi, defl, ref_p, ref_a, bound)
     st, psi, defl = _run(src, q, tgt, tolerance=1e-10, leaf_size=32)
-    assert _rel(psi, ref_p) <= 1e-10 and _rel(defl, ref_a) <= 1e-10
+    check(f"fp64 {name} tol 1e-10 p={st['order']}", psi, defl, ref_p, ref_a, 1e-10)
 
 
 def test_fp32_mixed_clustered_1e6_sampled(oracle_lib):
@@ -82,9 +79,7 @@ def test_fp32_mixed_clustered_1e6_sampled(oracle_lib):
     idx = np.random.default_rng(skies.BASE_SEED + 1001).choice(tgt.shape[1], 1000, replace=False)
     ref_p, ref_a = oracle.direct(src, q, tgt[:, idx])
     st, psi, defl = _run(src, q, tgt, tolerance=1e-6, leaf_size=32, precision=sf.SFMM_FP32_MIXED)
-    ep, ea = _rel(psi[idx], ref_p), _rel(defl[:, idx], ref_a)
-    print(f"[fp32] clustered-1e6 tol 1e-6 p={st['order']}: psi {ep:.3e} alpha {ea:.3e}", flush=True)
-    assert ep <= 1e-6 and ea <= 1e-6
+    check(f"fp32 clustered-1e6 tol 1e-6 p={st['order']}", psi[idx], defl[:, idx], ref_p, ref_a, 1e-6)
 
 
 def test_fp32_mixed_reproducible_and_coincident(oracle_lib):
@@ -98,5 +93,4 @@ def test_fp32_mixed_reproducible_and_coincident(oracle_lib):
     _, p1, d1 = _run(src, q, tgt, tolerance=1e-6, leaf_size=4, precision=sf.SFMM_FP32_MIXED)
     _, p2, d2 = _run(src, q, tgt, tolerance=1e-6, leaf_size=4, precision=sf.SFMM_FP32_MIXED)
     assert np.array_equal(p1, p2) and np.array_equal(d1, d2)
-    assert np.isfinite(p1).all() and np.isfinite(d1).all()
-    assert _rel(p1, ref_p) <= 1e-6 and _rel(d1, ref_a) <= 1e-6
+    check("fp32 coincident", p1, d1, ref_p, ref_a, 1e-6)

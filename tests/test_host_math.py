@@ -136,3 +136,25 @@ def test_angle_free_mac_filter_never_contradicts_the_angle(host_math):
     assert wrong == 0 and tie_wrong == 0 and tie_disagree == 0
     # the samples reach both regimes, and many near-ties are settled by long double
     assert decided > n // 2 and undecided > n // 10 and tie_checked > n // 20
+
+
+def test_pool_reuse_rule(host_math):
+    """The device pool hands a cached block out again only when that cannot
+    race with work still queued on it: same device, and either the block was
+    released after its users were waited for (no event), or the allocation is
+    on the stream that released it (stream order), or the event recorded at
+    the release has completed."""
+    cases = [
+        # dev, free stream, has event, event done, alloc stream, alloc dev -> reuse
+        ((0, 1, 1, 0, 1, 0), 1),   # same stream, work pending: stream order covers it
+        ((0, 1, 1, 0, 2, 0), 0),   # other stream, work pending: not yet
+        ((0, 1, 1, 1, 2, 0), 1),   # other stream, event completed
+        ((0, 0, 1, 0, 0, 0), 1),   # null stream on both sides
+        ((0, 0, 1, 0, 3, 0), 0),   # freed on the null stream, pending, other stream
+        ((0, 5, 0, 0, 7, 0), 1),   # released after a wait (sfmm_destroy): any stream
+        ((1, 1, 0, 0, 1, 0), 0),   # another device's block is never handed out
+        ((1, 1, 1, 1, 1, 1), 1),
+    ]
+    out = _run(host_math, "pool", "\n".join(" ".join(map(str, c)) for c, _ in cases) + "\n")
+    got = [int(x) for x in out if x.strip()]
+    assert got == [w for _, w in cases]

@@ -122,7 +122,8 @@ typedef struct {
                                        in the last sfmm_execute (the M2L work
                                        relative to one order-1 act); 0 before */
     int64_t execute_scratch_bytes;  /* device scratch one execute of this plan
-                                       uses beyond the plan's own arrays     */
+                                       uses beyond the plan's own arrays (see
+                                       sfmm_execute_noalloc)                  */
 } sfmm_stats;
 
 /* Fill *opt with the defaults: order 0 with tolerance 1e-10, leaf_size 64,
@@ -145,6 +146,22 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
 /* Run the five stages of Sec. 3.7 for a plan: psi [M] and defl [3][M]
  * (device, caller-owned, caller's target order) are overwritten. */
 sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stream);
+
+/* sfmm_execute without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, same kernels and the same results,
+ * bitwise, as sfmm_execute; the execute's scratch (partial sums of the near
+ * field's split boxes, the FP32 copy of the multipoles in the precision tier)
+ * lives in a static device array of 256 MiB per GPU that the library holds
+ * until the process ends, instead of memory the plan or the call allocates.
+ * No hipMalloc, hipFree or allocating routine is called (the plan itself was
+ * allocated by sfmm_plan).  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Errors: SFMM_ERR_INVALID_ARG for a plan with a
+ * per-pair order policy (its order split allocates) or one whose scratch
+ * (sfmm_stats.execute_scratch_bytes) exceeds 256 MiB; otherwise as
+ * sfmm_execute. */
+sfmm_status sfmm_execute_noalloc(sfmm_plan_t plan, double* psi, double* defl, void* stream);
 
 /* Batches: several independent spheres (lensing shells, Sec. 2.1: one
  * Poisson problem per layer) planned together and executed as one unit.

@@ -85,6 +85,7 @@ SIGNATURES = {
     "sfmm_default_options": (None, [ctypes.POINTER(Options)]),
     "sfmm_plan": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
     "sfmm_execute": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sfmm_execute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "sfmm_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "sfmm_export_boxes": (ctypes.c_int, [_P] * 9),
     "sfmm_export_lists": (ctypes.c_int, [_P] * 5),

@@ -782,6 +782,34 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
     prof.flush();
 }
 
+// ---- no-allocation execute (sfmm_execute_noalloc)
+// Its scratch lives in this file-scope device array: each GPU the library
+// runs on holds its own copy for the life of the process.  Host code never
+// uses the array's name as an address (on the host it is only a stand-in for
+// the symbol): the device address is looked up once per device and kept.
+constexpr size_t kNoallocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+unsigned char* noalloc_scratch() {
+    int dev = 0;
+    SFMM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(ST_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw Error(ST_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return (unsigned char*)g_scratch_ptr[dev];
+}
+
 extern "C" {
 
 void sfmm_default_options(sfmm_options* opt) {
@@ -875,6 +903,36 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         execute_impl(P, psi, defl, s, nullptr);
         P.executed = true;
         P.mark_done(s);
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SFMM_ERR_INTERNAL;
+    }
+}
+
+sfmm_status sfmm_execute_noalloc(sfmm_plan_t plan, double* psi, double* defl, void* stream) {
+    try {
+        if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
+        sfmm_plan_impl& P = *plan;
+        if (P.opt.order_policy != SFMM_ORDER_FIXED)
+            throw Error(ST_INVALID_ARG, "sfmm_execute_noalloc needs the fixed order policy");
+        if (P.M == 0) return SFMM_OK;
+        if (!psi || !defl) throw Error(ST_INVALID_ARG, "psi or defl is NULL");
+        size_t off_far = 0, off_mf = 0;
+        const size_t need = exec_scratch_bytes(P, &off_far, &off_mf);
+        if (need > kNoallocScratchBytes)
+            throw Error(ST_INVALID_ARG, "plan needs " + std::to_string(need) +
+                                            " bytes of execute scratch; sfmm_execute_noalloc has " +
+                                            std::to_string(kNoallocScratchBytes));
+        unsigned char* base = noalloc_scratch();
+        ExecScratch xs{(double*)base, (double*)(base + off_far), (float*)(base + off_mf)};
+        hipStream_t s = (hipStream_t)stream;
+        PoolStream ps(s, g_capturing);
+        execute_impl(P, psi, defl, s, &xs);
+        P.executed = true;
+        if (P.done && !g_capturing) SFMM_HIP(hipEventRecord(P.done, s));
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);

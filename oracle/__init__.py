@@ -8,6 +8,8 @@ Contents
 --------
 * ``direct``      plain FP64 direct sum of Eq. SUM / Eq. ALP_PSI (C, OpenMP,
                   Neumaier-compensated), the paper's "PPM" of Sec. 4.1.
+* ``hessian``     the same direct sum of the Hessian H of Sec. 2.2 (Eq.
+                  GAM_DEF); ``lensing`` turns H into kappa, gamma, mu.
 * ``key`` / ``pix_point`` / ``box_radius``  HEALPix nested geometry (C).
 * ``tree`` / ``walk`` / ``locate``  the sphere division of Sec. 3.1,
                   Algorithm 1 of Sec. 3.4 with the MACs of Sec. 3.5 (C).
@@ -59,6 +61,8 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_direct.argtypes = [P, P, i64, P, i64, ctypes.c_int, P, P, ctypes.c_int]
         lib.oracle_direct.restype = None
+        lib.oracle_hessian.argtypes = [P, P, i64, P, i64, P, ctypes.c_int]
+        lib.oracle_hessian.restype = None
         lib.oracle_key.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int]
         lib.oracle_key.restype = i64
         lib.oracle_pix_point.argtypes = [ctypes.c_int, i64, ctypes.c_double, ctypes.c_double, P]
@@ -108,6 +112,35 @@ def direct(src, q, tgt, gauge: int = GAUGE_ZERO_MEAN, nthreads: int = 0):
         lib.oracle_direct(_ptr(src), _ptr(q), n, _ptr(tgt), m, int(gauge),
                           _ptr(psi), _ptr(defl), int(nthreads))
     return psi, defl
+
+
+def hessian(src, q, tgt, nthreads: int = 0):
+    """Hessian of psi (Sec. 2.2, the matrix H of Eq. GAM_DEF) at targets
+    ``tgt`` (3, m): (3, m) array (H_11, H_12, H_22) in the basis e_theta,
+    e_phi of each target (phi = 0 at an exact pole)."""
+    lib = _load()
+    src = _planes(src, "src")
+    tgt = _planes(tgt, "tgt")
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n, m = src.shape[1], tgt.shape[1]
+    if q.shape != (n,):
+        raise ValueError("q must have shape (n,)")
+    hess = np.zeros((3, m))
+    if m:
+        lib.oracle_hessian(_ptr(src), _ptr(q), n, _ptr(tgt), m, _ptr(hess), int(nthreads))
+    return hess
+
+
+def lensing(hess):
+    """Convergence, shear and magnification from H (Eq. GAM_DEF and the
+    magnification of Sec. 2.2): kappa - kappa_bar = tr H, gamma_1 =
+    (H_11 - H_22)/2, gamma_2 = H_12, mu = 1/det(I - H).  Returns (4, m)."""
+    h11, h12, h22 = np.asarray(hess)
+    kk = h11 + h22
+    g1 = 0.5 * (h11 - h22)
+    g2 = h12
+    mu = 1.0 / ((1.0 - 0.5 * kk) ** 2 - g1 * g1 - g2 * g2)
+    return np.stack([kk, g1, g2, mu])
 
 
 def key(x, y, z, order: int = 29) -> int:

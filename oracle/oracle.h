@@ -42,6 +42,11 @@ void oracle_direct(const double* src, const double* q, int64_t n,
                    const double* tgt, int64_t m, int gauge,
                    double* psi, double* defl, int nthreads);
 
+/* Hessian of psi (Sec. 2.2) in the basis e_theta, e_phi at each target:
+ * hess [3][m] = (H_11, H_12, H_22); coincident sources left out. */
+void oracle_hessian(const double* src, const double* q, int64_t n, const double* tgt, int64_t m,
+                    double* hess, int nthreads);
+
 /* HEALPix nested pixel index at the given order (nside = 2^order) of the
  * unit vector (x, y, z); the sphere division of Sec. 3.1.  Evaluated in quad
  * precision, i.e. the exact-arithmetic pixel of the FP64 input. */

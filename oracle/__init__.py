@@ -15,6 +15,8 @@ Contents
                   Algorithm 1 of Sec. 3.4 with the MACs of Sec. 3.5 (C).
 * ``lemmas``      Lemmas 1-4 of Sec. 3.1-3.3 as printed, and the local
                   evaluation of Sec. 3.6, in numpy FP64.
+* ``raytrace``    multi-plane backtracking across layers (Eq. DIS_PRO) with
+                  the distortion matrix, on the direct sums above.
 """
 from __future__ import annotations
 

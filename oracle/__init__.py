@@ -10,6 +10,8 @@ Contents
                   Neumaier-compensated), the paper's "PPM" of Sec. 4.1.
 * ``hessian``     the same direct sum of the Hessian H of Sec. 2.2 (Eq.
                   GAM_DEF); ``lensing`` turns H into kappa, gamma, mu.
+* ``npm``         psi, alpha, H with every source a near-particle-model
+                  profile (Eq. KERNEL) of radius sigma.
 * ``key`` / ``pix_point`` / ``box_radius``  HEALPix nested geometry (C).
 * ``tree`` / ``walk`` / ``locate``  the sphere division of Sec. 3.1,
                   Algorithm 1 of Sec. 3.4 with the MACs of Sec. 3.5 (C).
@@ -17,6 +19,8 @@ Contents
                   evaluation of Sec. 3.6, in numpy FP64.
 * ``raytrace``    multi-plane backtracking across layers (Eq. DIS_PRO) with
                   the distortion matrix, on the direct sums above.
+* ``nfw``         the analytic NFW halo of Sec. 4.3 (Eq. NFW and its shear),
+                  the reference of the sampling-noise experiment.
 """
 from __future__ import annotations
 
@@ -65,6 +69,8 @@ def _load():
         lib.oracle_direct.restype = None
         lib.oracle_hessian.argtypes = [P, P, i64, P, i64, P, ctypes.c_int]
         lib.oracle_hessian.restype = None
+        lib.oracle_npm.argtypes = [P, P, i64, P, i64, ctypes.c_double, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.oracle_npm.restype = None
         lib.oracle_key.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int]
         lib.oracle_key.restype = i64
         lib.oracle_pix_point.argtypes = [ctypes.c_int, i64, ctypes.c_double, ctypes.c_double, P]
@@ -131,6 +137,25 @@ def hessian(src, q, tgt, nthreads: int = 0):
     if m:
         lib.oracle_hessian(_ptr(src), _ptr(q), n, _ptr(tgt), m, _ptr(hess), int(nthreads))
     return hess
+
+
+def npm(src, q, tgt, sigma: float, gauge: int = GAUGE_ZERO_MEAN, with_hessian: bool = True,
+        nthreads: int = 0):
+    """Direct sum with every source a near-particle-model profile of radius
+    sigma (Sec. 3.1 NPM, Sec. 4.2 Eq. KERNEL): (psi (m,), defl (3, m), hess
+    (3, m) or None)."""
+    lib = _load()
+    src = _planes(src, "src")
+    tgt = _planes(tgt, "tgt")
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n, m = src.shape[1], tgt.shape[1]
+    psi = np.zeros(m)
+    defl = np.zeros((3, m))
+    hess = np.zeros((3, m)) if with_hessian else None
+    if m:
+        lib.oracle_npm(_ptr(src), _ptr(q), n, _ptr(tgt), m, float(sigma), int(gauge), _ptr(psi), _ptr(defl),
+                       _ptr(hess) if with_hessian else None, int(nthreads))
+    return psi, defl, hess
 
 
 def lensing(hess):

@@ -47,6 +47,11 @@ void oracle_direct(const double* src, const double* q, int64_t n,
 void oracle_hessian(const double* src, const double* q, int64_t n, const double* tgt, int64_t m,
                     double* hess, int nthreads);
 
+/* Sources as near-particle-model profiles of radius sigma (Sec. 3.1 NPM,
+ * Eq. KERNEL): psi [m], defl [3][m] and, if hess is not NULL, hess [3][m]. */
+void oracle_npm(const double* src, const double* q, int64_t n, const double* tgt, int64_t m, double sigma,
+                int gauge, double* psi, double* defl, double* hess, int nthreads);
+
 /* HEALPix nested pixel index at the given order (nside = 2^order) of the
  * unit vector (x, y, z); the sphere division of Sec. 3.1.  Evaluated in quad
  * precision, i.e. the exact-arithmetic pixel of the FP64 input. */

@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--order", type=int, default=0, help="fixed order instead of the tolerance")
     ap.add_argument("--leaf-size", type=int, default=56)  # the fastest of a leaf-size sweep on clustered-1e7
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--accuracy-targets", type=int, default=10000,
+                    help="size of the seeded target subset the oracle checks (untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-tier (FP32 mixed) leg")
     ap.add_argument("--fp32-tolerance", type=float, default=1e-6)
@@ -204,6 +206,9 @@ def main():
                          "tolerance": args.fp32_tolerance, "order": s32["order"], "dtype": "f32+f64",
                          "m2l_work_vs_fixed": s32["m2l_order_sq"] / max(1, s32["n_m2l"] * s32["order"] ** 2),
                          "stages_ms": {k: round(v, 4) for k, v in st32.items()}}
+            if extra == "learned":
+                legs[leg]["judge"] = {"targets": s32["judge_targets"], "psi_rel_l2": s32["judge_psi"],
+                                      "alpha_rel_l2": s32["judge_alpha"], "fell_back": bool(s32["fell_back"])}
 
     p = stats["order"]
     work = {
@@ -243,38 +248,46 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        rng = np.random.default_rng(skies.BASE_SEED + 1002)
         psi_h = psi.cpu().numpy()
         defl_h = defl.cpu().numpy()
-        # two probes: the first pays the thread start-up, the second sets the rate
-        k = 8
-        for _ in range(2):
-            idx = rng.choice(M, size=k, replace=False)
-            t = time.perf_counter()
-            oracle.direct(src_h, q_h, tgt_h[:, idx])
-            t_probe = time.perf_counter() - t
-            k0, k = k, int(min(M, max(8, k * 0.1 * args.cpu_seconds / max(t_probe, 1e-6))))
-        k = int(min(M, max(8, k0 * args.cpu_seconds / max(t_probe, 1e-6))))
-        idx = rng.choice(M, size=k, replace=False)
-        log(f"[bench] cpu baseline: oracle on {k} sampled targets (probe {t_probe:.2f}s for {k0})")
+        # the seeded 1e4-target subset of the accuracy claim (the same subset
+        # as the full-size parity tests); its first k targets, timed alone,
+        # are the CPU baseline (a bounded sample of about cpu_seconds)
+        sub = np.random.default_rng(skies.BASE_SEED + 1001).choice(M, size=min(M, args.accuracy_targets),
+                                                                  replace=False)
         t = time.perf_counter()
-        ref_p, ref_a = oracle.direct(src_h, q_h, tgt_h[:, idx])
+        oracle.direct(src_h, q_h, tgt_h[:, sub[:8]])  # thread start-up and a rate probe
+        t_probe = time.perf_counter() - t
+        k = int(min(len(sub), max(8, 8 * args.cpu_seconds / max(t_probe, 1e-6))))
+        log(f"[bench] cpu baseline: oracle on {k} of the {len(sub)} seeded targets")
+        t = time.perf_counter()
+        ref_p1, ref_a1 = oracle.direct(src_h, q_h, tgt_h[:, sub[:k]])
         t_cpu = time.perf_counter() - t
         cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
         result["cpu_baseline"] = {"value": k / t_cpu, "unit": "targets/s", "cores": cores, "kind": "oracle",
                                   "sample": f"{k} seeded targets of the same workload, all {N} sources, "
                                             f"{t_cpu:.1f}s"}
-        result["accuracy"] = {
-            "psi_rel_l2": float(np.linalg.norm(psi_h[idx] - ref_p) / np.linalg.norm(ref_p)),
-            "alpha_rel_l2": float(np.linalg.norm(defl_h[:, idx] - ref_a) / np.linalg.norm(ref_a)),
-            "targets": k}
+        if k < len(sub):
+            log(f"[bench] accuracy: oracle on the other {len(sub) - k} targets (untimed)")
+            ref_p2, ref_a2 = oracle.direct(src_h, q_h, tgt_h[:, sub[k:]])
+            ref_p = np.concatenate([ref_p1, ref_p2])
+            ref_a = np.concatenate([ref_a1, ref_a2], axis=1)
+        else:
+            ref_p, ref_a = ref_p1, ref_a1
+
+        def accuracy(ph, dh):
+            # relative L2 error, and the worst target over the rms of the reference
+            dp = ph[sub] - ref_p
+            da = np.linalg.norm(dh[:, sub] - ref_a, axis=0)
+            rms_a = np.sqrt(np.mean(np.sum(ref_a * ref_a, axis=0)))
+            return {"psi_rel_l2": float(np.linalg.norm(dp) / np.linalg.norm(ref_p)),
+                    "alpha_rel_l2": float(np.linalg.norm(da) / np.linalg.norm(ref_a)),
+                    "psi_worst_target": float(np.abs(dp).max() / np.sqrt(np.mean(ref_p * ref_p))),
+                    "alpha_worst_target": float(da.max() / rms_a), "targets": int(len(sub))}
+
+        result["accuracy"] = accuracy(psi_h, defl_h)
         for leg, (p32, d32) in (outs.items() if legs else []):
-            p32 = p32.cpu().numpy()
-            d32 = d32.cpu().numpy()
-            legs[leg]["accuracy"] = {
-                "psi_rel_l2": float(np.linalg.norm(p32[idx] - ref_p) / np.linalg.norm(ref_p)),
-                "alpha_rel_l2": float(np.linalg.norm(d32[:, idx] - ref_a) / np.linalg.norm(ref_a)),
-                "targets": k}
+            legs[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
     print(json.dumps(result), flush=True)
 
 

@@ -49,7 +49,8 @@ typedef enum {
     SFMM_ERR_INVALID_ARG = 1,       /* bad size, option or input values      */
     SFMM_ERR_OUT_OF_MEMORY = 2,     /* device allocation failed               */
     SFMM_ERR_HIP = 3,               /* a HIP runtime call or kernel failed    */
-    SFMM_ERR_TOLERANCE_NOT_MET = 4, /* reserved                               */
+    SFMM_ERR_TOLERANCE_NOT_MET = 4, /* a per-pair order policy failed its
+                                       judge and the fallback is disabled     */
     SFMM_ERR_INTERNAL = 5
 } sfmm_status;
 
@@ -64,13 +65,13 @@ enum { SFMM_FP64 = 0, SFMM_FP32_MIXED = 1 };
 /* Order of each FMM act (Lemma 3 pair).  FIXED: every pair at the plan order
  * p.  Otherwise a pair at order p' < p translates its multipole part at p'
  * (A_1..A_p' of the source in, local coefficients 1..p' out) and its
- * monopole part at p.  BOUND: p' = the smallest multiple of 4 (<= p) with
+ * monopole part at p.  BOUND: p' = the smallest multiple of 4 (or p) with
  * x^(p'+1) (p'+1) / (1 - x) <= SFMM_ORDER_KAPPA tolerance (the form of
  * Eq. MUL_ERR for the pair's convergence ratio x, relative to the source's
  * multipole strength W_S = sum_l |A_l| rho_S^-l).  LEARNED: p' predicted by
  * the order network (weights in sfmm_options.mlp_weights) for the same
- * criterion measured exactly; see sfmm_order_samples / sfmm_mlp_train.  With
- * BOUND and LEARNED the plan order is rounded up to a multiple of 4. */
+ * criterion measured exactly; see sfmm_order_samples / sfmm_mlp_train.
+ * Per-pair orders are multiples of 4 or the plan order p itself. */
 enum { SFMM_ORDER_FIXED = 0, SFMM_ORDER_BOUND = 1, SFMM_ORDER_LEARNED = 2 };
 #define SFMM_ORDER_KAPPA 0.1
 
@@ -105,7 +106,16 @@ typedef struct {
     int32_t near_segment;      /* close leaves per near-field work item: direct
                                   sums (0 = 128); 8..4096                     */
     int32_t far_segment;       /* the same for the multipole evaluations     */
-    int32_t reserved[4];
+    int32_t judge_targets;     /* per-pair order policies: targets of the
+                                  judge's direct sum (0 = 64; < 0: no judge);
+                                  at most 4096                               */
+    int32_t no_fallback;       /* nonzero: a failed judge returns
+                                  SFMM_ERR_TOLERANCE_NOT_MET instead of
+                                  rerunning at the fixed order               */
+    double npm_sigma;          /* near-particle model (Sec. 3.1 NPM, Sec. 4.2
+                                  Eq. KERNEL): every source is a generalised
+                                  Epanechnikov profile of this angular radius
+                                  (radians, in [0, 0.5]; 0 = point masses)  */
 } sfmm_options;
 
 typedef struct {
@@ -121,13 +131,37 @@ typedef struct {
     int64_t m2l_order_sq;           /* sum over the FMM acts of (their order)^2
                                        in the last sfmm_execute (the M2L work
                                        relative to one order-1 act); 0 before */
+    double judge_psi, judge_alpha;  /* relative L2 error of psi and alpha of the
+                                       per-pair order policy at the judge's
+                                       targets against their direct sum; -1
+                                       before the judge ran (fixed order, no
+                                       judge, or not executed)                */
+    int32_t judge_targets;          /* targets the judge summed directly      */
+    int32_t fell_back;              /* 1: the judge failed and the plan runs at
+                                       the fixed order                        */
     int64_t execute_scratch_bytes;  /* device scratch one execute of this plan
                                        uses beyond the plan's own arrays (see
                                        sfmm_execute_noalloc)                  */
 } sfmm_stats;
 
+/* Near-particle model (npm_sigma = sigma > 0; Sec. 3.1 NPM, Sec. 4.2 Eq.
+ * KERNEL): every source is the mass distribution W(theta) = [1 -
+ * sin^2(theta/2)/sin^2(sigma/2)] / (2 pi sin^2(sigma/2)) (theta <= sigma),
+ * and psi, alpha (and the Hessian) are those of the smoothed particles: the
+ * solution of Laplacian psi = sum_j q_j W_j - Q_tot/(4pi) in the zero-mean
+ * gauge.  Outside sigma a particle deflects as a point mass; its potential
+ * differs from the point mass's by a constant; inside, the interior
+ * solution applies, and a source at the target itself contributes its
+ * finite central value (no exclusion).  The expansions stay exact: the
+ * protected zone of Sec. 3.5 around a source box is max(c_s R_S, R_S +
+ * sigma), so no FMM act or expansion evaluation has a target inside a
+ * particle.  The deflection inside differs from the printed Eq.
+ * KERNEL_ALPHA (whose normalisation is -2 pi times this one's) by
+ * O(sin^2(sigma/2)) relative: that formula leaves out the background term
+ * -q/(4pi) inside the particle. */
+
 /* Fill *opt with the defaults: order 0 with tolerance 1e-10, leaf_size 64,
- * c_s 2, c_t 0.5, max_level 29, FP64, zero-mean gauge. */
+ * c_s 2, c_t 0.5, max_level 29, FP64, zero-mean gauge, point masses. */
 void sfmm_default_options(sfmm_options* opt);
 
 /* Build a plan: keys, sorting, the tree (Sec. 3.1), box geometry (Sec. 3.5),
@@ -144,8 +178,58 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
                       const sfmm_options* opt, void* stream, sfmm_plan_t* out);
 
 /* Run the five stages of Sec. 3.7 for a plan: psi [M] and defl [3][M]
- * (device, caller-owned, caller's target order) are overwritten. */
+ * (device, caller-owned, caller's target order) are overwritten.
+ * With the bound or learned order policy the first execute of a plan is
+ * judged: psi and alpha at a seeded subset of judge_targets targets are
+ * compared with the library's own GPU direct sum of Eq. SUM / Eq. ALP_PSI
+ * (FP64, compensated sums, every source); if the relative L2 error of
+ * either exceeds the tolerance the plan falls back to the fixed order p for
+ * this and every later execute (the outputs are recomputed), or, with
+ * no_fallback set, the call returns SFMM_ERR_TOLERANCE_NOT_MET (the outputs
+ * hold the policy's result; later executes return the same status).  The
+ * verdict is kept with the plan: the orders a policy picks depend only on
+ * the plan's inputs.  sfmm_stats reports the judge's errors. */
 sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stream);
+
+/* sfmm_execute that also returns the Hessian of psi (Sec. 2.2, the matrix H
+ * of Eq. GAM_DEF): hess [3][M] (device, caller-owned, caller's target order)
+ * receives H_11 = d^2 psi/d theta^2, H_12 = d/d theta ((1/sin theta) d psi /
+ * d phi) and H_22 = (1/sin^2 theta) d^2 psi/d phi^2 + cot theta d psi/d theta
+ * in the basis e_theta, e_phi of each target (at an exact pole the limit at
+ * phi = 0).  From the same expansions (Sec. 3.6): the local and multipole
+ * forms' second derivatives in their stereographic coordinate, and the
+ * direct sum's pair terms.  Convergence, shear and magnification follow as
+ * kappa - kappa_bar = H_11 + H_22, gamma_1 = (H_11 - H_22)/2, gamma_2 =
+ * H_12, mu = 1/det(I - H) (sfmm_lensing).  Errors as sfmm_execute. */
+sfmm_status sfmm_execute_hessian(sfmm_plan_t plan, double* psi, double* defl, double* hess, void* stream);
+
+/* Lensing quantities of Sec. 2.2 from a Hessian: out [4][M] (device) =
+ * (kappa - kappa_bar, gamma_1, gamma_2, mu) with kappa - kappa_bar = tr H
+ * (Eq. GAM_DEF), gamma_1 = (H_11 - H_22)/2, gamma_2 = H_12 and mu =
+ * 1/((1 - (kappa - kappa_bar)/2)^2 - gamma_1^2 - gamma_2^2); hess [3][M]
+ * (device) as written by sfmm_execute_hessian.  Stream-ordered.  Errors:
+ * SFMM_ERR_INVALID_ARG for M < 0 or NULL buffers with M > 0. */
+sfmm_status sfmm_lensing(const double* hess, int64_t M, double* out, void* stream);
+
+/* Multi-plane backtracking through nlayer lensing layers (Sec. 2.1, Eq.
+ * DIS_PRO): rays [3][M] (device unit vectors) enter layer 0 at their
+ * observed positions theta_0 and, layer by layer, move to theta_{i+1} =
+ * theta_i - weight[i] alpha_i(theta_i), alpha_i the deflection of layer i's
+ * masses (src[i] [3][N[i]], q[i] [N[i]], device; as in sfmm_plan) at the
+ * rays' current positions; weight[i] (host) is f_K(r_s - r_i) / f_K(r_s) for
+ * the source distance r_s.  The step follows the great circle (the ray moves
+ * by |w alpha| in the direction of -alpha).  On return rays holds theta_n.
+ * dist [4][M] (device, may be NULL): the distortion matrix A = d theta_n /
+ * d theta_0, (A_11, A_12, A_21, A_22) in the e_theta, e_phi bases of theta_0
+ * (columns) and theta_n (rows), propagated with each layer's Hessian (Sec.
+ * 2.2) to first order in the step: A <- T (I - w H) A, T the parallel
+ * transport along the step.  Every layer is planned and executed with *opt
+ * (the same rules and errors as sfmm_plan / sfmm_execute); the call returns
+ * when the work on `stream` is done.  Errors: nlayer outside [1, 4096],
+ * non-finite weights, NULL arrays, M outside [0, 2^31 - 1]. */
+sfmm_status sfmm_raytrace(int32_t nlayer, const double* const* src, const double* const* q, const int64_t* N,
+                          const double* weight, double* rays, int64_t M, double* dist, const sfmm_options* opt,
+                          void* stream);
 
 /* sfmm_execute without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that

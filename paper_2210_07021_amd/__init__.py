@@ -19,6 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfmm.so")
 
 SFMM_OK = 0
+SFMM_ERR_INVALID_ARG = 1
+SFMM_ERR_TOLERANCE_NOT_MET = 4
 SFMM_GAUGE_ZERO_MEAN = 0
 SFMM_GAUGE_RAW = 1
 SFMM_FP64 = 0
@@ -51,7 +53,9 @@ class Options(ctypes.Structure):
         ("mlp_weights", ctypes.c_void_p),
         ("near_segment", ctypes.c_int32),
         ("far_segment", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("judge_targets", ctypes.c_int32),
+        ("no_fallback", ctypes.c_int32),
+        ("npm_sigma", ctypes.c_double),
     ]
 
 
@@ -71,6 +75,10 @@ class Stats(ctypes.Structure):
         ("leaf_size", ctypes.c_int32),
         ("q_total", ctypes.c_double),
         ("m2l_order_sq", ctypes.c_int64),
+        ("judge_psi", ctypes.c_double),
+        ("judge_alpha", ctypes.c_double),
+        ("judge_targets", ctypes.c_int32),
+        ("fell_back", ctypes.c_int32),
         ("execute_scratch_bytes", ctypes.c_int64),
     ]
 
@@ -86,6 +94,9 @@ SIGNATURES = {
     "sfmm_plan": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
     "sfmm_execute": (ctypes.c_int, [_P, _P, _P, _P]),
     "sfmm_execute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sfmm_execute_hessian": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "sfmm_lensing": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "sfmm_raytrace": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _I64, _P, ctypes.POINTER(Options), _P]),
     "sfmm_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "sfmm_export_boxes": (ctypes.c_int, [_P] * 9),
     "sfmm_export_lists": (ctypes.c_int, [_P] * 5),
@@ -210,6 +221,48 @@ def mlp_grad(weights, features, labels):
     return g, float(loss.value)
 
 
+def lensing(hess, stream=None):
+    """(kappa - kappa_bar, gamma_1, gamma_2, mu) (4, M) on the GPU from a
+    Hessian (3, M) of Plan.execute_hessian (sfmm_lensing)."""
+    import torch
+    hess = hess.contiguous()
+    m = int(hess.shape[1])
+    out = torch.empty((4, m), dtype=torch.float64, device=hess.device)
+    _check(load_library().sfmm_lensing(ctypes.c_void_p(hess.data_ptr() if m else 0), m,
+                                       ctypes.c_void_p(out.data_ptr() if m else 0), _stream_handle(stream)))
+    return out
+
+
+def raytrace(layers, weights, rays, distortion=True, **options):
+    """Multi-plane backtracking (sfmm_raytrace): layers = [(src (3, N_i), q
+    (N_i,)), ...], weights = f_K(r_s - r_i) / f_K(r_s) per layer, rays (3, M)
+    the observed positions.  Returns (final rays (3, M), distortion matrix
+    (4, M) or None) as CUDA float64 tensors."""
+    import torch
+    lib = load_library()
+    n = len(layers)
+    if n == 0 or len(weights) != n:
+        raise ValueError("need one weight per layer and at least one layer")
+    srcs = [_dev_planes(x[0], "src") for x in layers]
+    qs = [_dev_planes(x[1], "q") for x in layers]
+    r = _dev_planes(rays, "rays").clone()
+    m = int(r.shape[1])
+    dist = torch.empty((4, m), dtype=torch.float64, device="cuda") if distortion else None
+    arr = lambda xs: (ctypes.c_void_p * n)(*[x.data_ptr() if x.numel() else 0 for x in xs])
+    ps, qq = arr(srcs), arr(qs)
+    Ns = (ctypes.c_int64 * n)(*[int(x.shape[1]) for x in srcs])
+    ws = (ctypes.c_double * n)(*[float(w) for w in weights])
+    weights_ = options.pop("mlp_weights", None)
+    opt = default_options(**options)
+    if weights_ is not None:
+        keep = _f32(weights_, (MLP_WEIGHTS,))
+        opt.mlp_weights = keep.ctypes.data
+    _check(lib.sfmm_raytrace(n, ps, qq, Ns, ws, ctypes.c_void_p(r.data_ptr() if m else 0), m,
+                             ctypes.c_void_p(dist.data_ptr() if (dist is not None and m) else 0),
+                             ctypes.byref(opt), _stream_handle()))
+    return r, dist
+
+
 def order_for_tolerance(tol: float) -> int:
     return int(load_library().sfmm_order_for_tolerance(float(tol)))
 
@@ -289,6 +342,22 @@ class Plan:
                                       ctypes.c_void_p(defl.data_ptr() if self.M else 0),
                                       _stream_handle(stream if stream is not None else self._stream)))
         return psi, defl
+
+    def execute_hessian(self, psi=None, defl=None, hess=None, stream=None):
+        """Returns (psi (M,), defl (3, M), hess (3, M)): hess = (H_11, H_12,
+        H_22) of Sec. 2.2 in each target's e_theta, e_phi basis."""
+        t = self._torch
+        if psi is None:
+            psi = t.empty(self.M, dtype=t.float64, device="cuda")
+        if defl is None:
+            defl = t.empty((3, self.M), dtype=t.float64, device="cuda")
+        if hess is None:
+            hess = t.empty((3, self.M), dtype=t.float64, device="cuda")
+        _check(self._lib.sfmm_execute_hessian(self._h, ctypes.c_void_p(psi.data_ptr() if self.M else 0),
+                                              ctypes.c_void_p(defl.data_ptr() if self.M else 0),
+                                              ctypes.c_void_p(hess.data_ptr() if self.M else 0),
+                                              _stream_handle(stream if stream is not None else self._stream)))
+        return psi, defl, hess
 
     def stats(self) -> dict:
         s = Stats()

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfmm.so")
-SOURCES = ["k_util.hip", "k_tree.hip", "k_fmm.hip", "k_p2p.hip", "k_order.hip", "k_mlp.hip", "sfmm_api.hip"]
+SOURCES = ["k_util.hip", "k_tree.hip", "k_fmm.hip", "k_p2p.hip", "k_order.hip", "k_mlp.hip", "k_judge.hip", "k_ray.hip", "sfmm_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

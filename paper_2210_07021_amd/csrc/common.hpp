@@ -33,21 +33,21 @@ enum { ST_OK = 0, ST_INVALID_ARG = 1, ST_OOM = 2, ST_HIP = 3, ST_TOL = 4, ST_INT
 // work on the same stream (stream order covers it): every API call names its
 // stream with a PoolStream scope (capturing: a graph is being recorded on
 // it; idle: the caller has already waited for all work that used the blocks
-// freed in this scope).
+// freed in this scope), and the end of the scope records one event for all
+// blocks freed in it.
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 void pool_release_all();
 struct PoolStream {
-    hipStream_t prev_s;
-    bool prev_cap, prev_idle;
+    void* saved;  // the enclosing scope, restored at the end
     explicit PoolStream(hipStream_t s, bool capturing = false, bool idle = false);
     ~PoolStream();
     PoolStream(const PoolStream&) = delete;
     PoolStream& operator=(const PoolStream&) = delete;
 };
 // The reuse rule, exposed for host-side tests: a cached block freed on
-// stream `s_free` (with an event when has_event) may serve an allocation on
-// stream `s` of device `dev`.
+// stream b.s (with a pending event when has_event, completed when
+// event_done) may serve an allocation on stream `s` of device `dev`.
 struct PoolBlockState {
     int dev;
     hipStream_t s;
@@ -197,13 +197,16 @@ struct WalkCtx {
     const double4* ttrig;  // [nb] cos, sin of R and of R / c_t
     const int2* cc;        // [nb] child0, count
     const double* gdd;     // [nb][8] double-double centre and radius
-    const double* dtrig;   // [nb][12] double-double cos, sin of c_s R, R, R / c_t
+    const double* dtrig;   // [nb][kWalkDtrig] double-double cos, sin of the protected radius P, of R and
+                           // of R / c_t, then P itself
     double c_s, c_t;
+    double sigma;          // near-particle model radius: the protected radius is max(c_s R, R + sigma)
 };
+constexpr int kWalkDtrig = 14;
 // the walk's per-box records (geo, cc) from the box table
 void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
-                double c_s, double c_t, double4* geo, double2* strig, double4* ttrig, int2* cc, double* dtrig,
-                hipStream_t s);
+                double c_s, double c_t, double sigma, double4* geo, double2* strig, double4* ttrig, int2* cc,
+                double* dtrig, hipStream_t s);
 // M2L order: boxes of levels <= lc first, then the others; longest list
 // first within each part (16-bit keys, ties in table order)
 // One walk round in three launches (classify + per-chunk scans, scan of the
@@ -250,7 +253,21 @@ struct FmmCtx {
     double* mult;        // [nb][2p+2]
     double* local;       // [nb][2p+2]
     const double* zrec;  // [2p+2] zeros
+    double npm_sigma;    // near-particle model radius (0: point masses)
 };
+// Near-particle model (Epanechnikov profile of radius sigma): with u =
+// |d|^2/4 and t = sin^2(sigma/2), the interior potential is (q/4pi)(log t -
+// I(u/t)), I(v) = integral_v^1 (2 - v' - t)/(1 - v' t) dv'
+// = sum_k t^k [(2 - t)(1 - v^(k+1))/(k+1) - (1 - v^(k+2))/(k+2)], and the
+// potential of every particle carries the constant (q/4pi) c(t), c = t (J -
+// 1), J = sum_k t^k [(2 - t)/(k + 2) - 1/(k + 3)] (so that it integrates to
+// -q over the sphere like a point mass's).  npm_constant(sigma) = c(t).
+double npm_constant(double sigma);
+struct NpmK {
+    double t, inv_t, four_t, ln4t, a2;  // a2 = ((1 - t)/t)^2 / 16
+    int nterms;                         // terms of the series for I
+};
+NpmK npm_params(double sigma);
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s);
 void fmm_m2m(const FmmCtx& c, int b0, int nb, hipStream_t s);
 // M2L at order p <= c.p over the boxes order[0..n) (order may be null: box
@@ -263,9 +280,13 @@ void mult_to_f32(const FmmCtx& c, int nbox, float* multf, hipStream_t s);
 void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n, const int* off,
                  const int* src, hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
+// (kappa - kappa_bar, gamma_1, gamma_2, mu) [4][m] from the Hessian [3][m]
+void lensing_from_hessian(const double* hess, int64_t m, double* out, hipStream_t s);
+// hess [3][m_out] (may be null): also the Hessian of Sec. 2.2 in the
+// targets' e_theta, e_phi basis (written, like psi and defl)
 void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
              const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
-             hipStream_t s);
+             hipStream_t s, double* hess = nullptr);
 // Direct-act lists split into the leaves summed particle by particle (near)
 // and those taken through their multipole expansion (far), both in CSR form
 // by target box, with the work each box gives the two kernels.
@@ -296,13 +317,34 @@ void near_work(const int* count, const NearLists& nl, const int* tcount, int nbo
 // fp32: the precision tier's pair arithmetic (two-float coordinates, FP32
 // log / reciprocal, FP64 sums per tile)
 // part: the partial slots of the split boxes ([w.nslot][4] doubles), or
-// null for the work items' own buffer w.part
+// null for the work items' own buffer w.part.  hess (may be null): also add
+// the Hessian of Sec. 2.2 to hess [3][m_out]; part then has [w.nslot][8]
+// doubles and may not be null.
 void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
              const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part = nullptr);
+             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part = nullptr,
+             double* hess = nullptr);
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s, double* part = nullptr);
+             double* defl, int64_t m_out, hipStream_t s, double* part = nullptr, double* hess = nullptr);
+
+// ---------------------------------------------------------------- multi-plane rays
+// A = identity [4][m]; one layer's step of the rays [3][m] by -w defl (along
+// great circles) and, with dist [4][m] (may be null), A <- T (I - w H) A
+void ray_identity(double* dist, int64_t m, hipStream_t s);
+void ray_step(double* rays, const double* defl, const double* hess, double w, int64_t m, double* dist,
+              hipStream_t s);
+
+// ---------------------------------------------------------------- judge
+// Direct sum at S targets of the plan (sorted positions pos[S]) over the n
+// sorted sources, FP64 with compensated sums: ref [S][4] = (psi + shift,
+// alpha x, y, z); got [S][4] the library's outputs psi/defl (caller order,
+// m targets) at the same targets; tsel [S] and part [judge_part_doubles]
+// are scratch.
+size_t judge_part_doubles(int64_t n, int S);
+void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const double* tx, const double* ty,
+                  const double* tz, const uint32_t* tperm, const double* psi, const double* defl, int64_t m,
+                  double shift, double4* tsel, double* part, double* ref, double* got, hipStream_t s);
 
 // ---------------------------------------------------------------- order policies
 void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s);
@@ -320,8 +362,9 @@ void order_mlp(const FmmCtx& c, const int* ent_t, const int* src, const float4* 
 void m2l_qtail(const FmmCtx& c, const int* off, const int* src, const uint8_t* ord, int nbox, hipStream_t s);
 void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* idx, int n, double kappa_tol,
                   float* label, hipStream_t s);
-// split pairs by order into CSR lists boff + q nbox (q = order / kOrderStep - 1)
-// over bsrc; returns the sum of the orders squared
+// split pairs by order into CSR lists boff + q nbox over bsrc, class q
+// holding the orders in (q kOrderStep, (q + 1) kOrderStep], q < ceil(pmax /
+// kOrderStep); returns the sum of the orders squared
 long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
                       DVec<int>& boff, DVec<int>& bsrc, hipStream_t s);
 void mlp_grad(const float* w, const float* feat, const float* label, int n, float* rec, float* grad, hipStream_t s);

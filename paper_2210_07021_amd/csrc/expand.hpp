@@ -128,6 +128,7 @@ struct cplx {
     double re, im;
 };
 SFMM_HD cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+SFMM_HD cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 SFMM_HD cplx cconj(cplx a) { return {a.re, -a.im}; }
 
 struct Frame {
@@ -539,6 +540,133 @@ SFMM_HD void m2p_eval(const double* __restrict__ e, const Frame& f, double rho, 
     *ax = at * f.et[0] + ap * f.ep[0] + ac * f.c[0];
     *ay = at * f.et[1] + ap * f.ep[1] + ac * f.c[1];
     *az = at * f.et[2] + ap * f.ep[2] + ac * f.c[2];
+}
+
+
+// ---------------------------------------------------------------- Hessian
+// The Hessian of Sec. 2.2 (second covariant derivatives of psi in the basis
+// e_theta, e_phi of the target).  In the stereographic coordinate w = u + iv
+// of a box frame the sphere's metric is conformal, (2 / D)^2 |dw|^2 with
+// D = 1 + |w|^2, and the covariant Hessian of psi in the orthonormal basis
+// (e_u, e_v) of the w-plane is
+//   H_uu + H_vv = (D^2 / 4) Laplacian_w psi,
+//   H_uu - H_vv - 2i H_uv = Z = D^2 (psi_ww - 2 sigma_w psi_w),
+// with psi_w = d psi / dw, sigma = log(2 / D) (so sigma_w = -conj(w) / D).
+// For the local form psi = C + Q log(1 + cos) + 2 Re f(w), f = sum A_l w^l:
+//   Z = D^2 f'' + 2 conj(w) D f' - Q conj(w)^2,   trace -Q;
+// for the multipole form psi = C + Q log(1 - cos) + 2 Re f(w), f = sum A_l
+// w^-l:
+//   Z = D^2 f'' + 2 conj(w) D f' - Q / w^2,       trace -Q.
+// Both are regular at w = 0 (the local form at a box centre) and need no
+// angle.  The (e_u, e_v) components are then turned into the target's
+// (e_theta, e_phi) ones.
+
+// e_theta, e_phi of the target n (phi = 0 at an exact pole)
+SFMM_HD void target_basis(double nx, double ny, double nz, double* et, double* ep) {
+    const double rxy = sqrt(nx * nx + ny * ny);
+    const double cph = rxy > 0.0 ? nx / rxy : 1.0, sph = rxy > 0.0 ? ny / rxy : 0.0;
+    et[0] = nz * cph;
+    et[1] = nz * sph;
+    et[2] = -rxy;
+    ep[0] = -sph;
+    ep[1] = cph;
+    ep[2] = 0.0;
+}
+
+// (H_uu, H_uv, H_vv) in the w-plane basis of frame f at w -> (H_tt, H_tp,
+// H_pp) in the basis et, ep of the target
+SFMM_HD void hess_to_target(const Frame& f, cplx w, double huu, double huv, double hvv, const double* et,
+                            const double* ep, double* h) {
+    const double u = w.re, v = w.im;
+    const double inv = 1.0 / (1.0 + u * u + v * v);
+    const double eu_t = (1.0 + v * v - u * u) * inv, eu_p = -2.0 * u * v * inv, eu_c = -2.0 * u * inv;
+    const double ev_t = -2.0 * u * v * inv, ev_p = (1.0 + u * u - v * v) * inv, ev_c = -2.0 * v * inv;
+    double eu[3], ev[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        eu[d] = eu_t * f.et[d] + eu_p * f.ep[d] + eu_c * f.c[d];
+        ev[d] = ev_t * f.et[d] + ev_p * f.ep[d] + ev_c * f.c[d];
+    }
+    const double tu = et[0] * eu[0] + et[1] * eu[1] + et[2] * eu[2];
+    const double tv = et[0] * ev[0] + et[1] * ev[1] + et[2] * ev[2];
+    const double pu = ep[0] * eu[0] + ep[1] * eu[1] + ep[2] * eu[2];
+    const double pv = ep[0] * ev[0] + ep[1] * ev[1] + ep[2] * ev[2];
+    h[0] = tu * tu * huu + 2.0 * tu * tv * huv + tv * tv * hvv;
+    h[1] = tu * pu * huu + (tu * pv + tv * pu) * huv + tv * pv * hvv;
+    h[2] = pu * pu * huu + 2.0 * pu * pv * huv + pv * pv * hvv;
+}
+
+// l2p_eval and the Hessian h[3] of the local expansion at the target
+// (et, ep its basis)
+template <int P>
+SFMM_HD void l2p_eval_hess(const double* e, const Frame& f, double rho, double nx, double ny, double nz,
+                           const double* et, const double* ep, double* psi, double* ax, double* ay, double* az,
+                           double* h) {
+    l2p_eval<P>(e, f, rho, nx, ny, nz, psi, ax, ay, az);
+    double opc;
+    const cplx w = stereo(f, nx, ny, nz, &opc);
+    const double inv_rho = 1.0 / rho;
+    const cplx zt = {w.re * inv_rho, w.im * inv_rho};
+    // Horner for q(z) = sum L_l z^(l-1) with its first derivative dv and
+    // half its second ev; then g = (z q)' and k = (z q)'' = 2 (dv + z ev)
+    cplx pv = {e[2 * P], e[2 * P + 1]}, dv = {0.0, 0.0}, ev = {0.0, 0.0};
+#pragma unroll
+    for (int l = P - 1; l >= 1; --l) {
+        ev = cadd(cmul(ev, zt), dv);
+        dv = cadd(cmul(dv, zt), pv);
+        pv = cadd(cmul(pv, zt), cplx{e[2 * l], e[2 * l + 1]});
+    }
+    const cplx g = cadd(cmul(dv, zt), pv);
+    const cplx k = cmul(cplx{2.0, 0.0}, cadd(dv, cmul(zt, ev)));
+    const double Q = e[1];
+    const double D = 1.0 + w.re * w.re + w.im * w.im;
+    const cplx wc = {w.re, -w.im};
+    // Z = D^2 f'' + 2 conj(w) D f' - Q conj(w)^2, f' = g / rho, f'' = k / rho^2
+    const cplx t1 = cmul(cplx{D * D * inv_rho * inv_rho, 0.0}, k);
+    const cplx t2 = cmul(cplx{2.0 * D * inv_rho, 0.0}, cmul(wc, g));
+    const cplx wc2 = cmul(wc, wc);
+    const cplx Z = {t1.re + t2.re - Q * wc2.re, t1.im + t2.im - Q * wc2.im};
+    hess_to_target(f, w, 0.5 * (-Q + Z.re), -0.5 * Z.im, 0.5 * (-Q - Z.re), et, ep, h);
+}
+
+// m2p_eval and the Hessian h[3] of a source box's multipole expansion at
+// the target (et, ep its basis).  With zeta = rho / w and F(zeta) = sum Ah_l
+// zeta^l: f' = -G / w and f'' = K / w^2, G = sum l Ah_l zeta^l, K = sum
+// l (l + 1) Ah_l zeta^l.
+template <int P>
+SFMM_HD void m2p_eval_hess(const double* __restrict__ e, const Frame& f, double rho, double nx, double ny,
+                           double nz, const double* et, const double* ep, double* psi, double* ax, double* ay,
+                           double* az, double* h) {
+    m2p_eval<P>(e, f, rho, nx, ny, nz, psi, ax, ay, az);
+    double opc;
+    const cplx w = stereo(f, nx, ny, nz, &opc);
+    const double w2 = w.re * w.re + w.im * w.im;
+    const double iw2 = 1.0 / w2;
+    const cplx zt = {rho * w.re * iw2, -rho * w.im * iw2};   // rho / w
+    const cplx iw = {w.re * iw2, -w.im * iw2};               // 1 / w
+    // Horner for q(z) = sum Ah_l z^(l-1), its derivative dv and half its
+    // second ev: F = z q, F' = q + z dv, F'' = 2 (dv + z ev)
+    cplx pv = {e[2 * P], e[2 * P + 1]}, dv = {0.0, 0.0}, ev = {0.0, 0.0};
+#pragma unroll 4
+    for (int l = P - 1; l >= 1; --l) {
+        ev = cadd(cmul(ev, zt), dv);
+        dv = cadd(cmul(dv, zt), pv);
+        pv = cadd(cmul(pv, zt), cplx{e[2 * l], e[2 * l + 1]});
+    }
+    const cplx F1 = cadd(pv, cmul(zt, dv));
+    const cplx F2 = cmul(cplx{2.0, 0.0}, cadd(dv, cmul(zt, ev)));
+    const cplx G = cmul(zt, F1);
+    const cplx z2 = cmul(zt, zt);
+    const cplx K = cadd(cmul(z2, F2), cmul(cplx{2.0, 0.0}, G));
+    const double Q = e[1];
+    const double D = 1.0 + w2;
+    const cplx wc = {w.re, -w.im};
+    const cplx iw2c = cmul(iw, iw);  // 1 / w^2
+    // Z = D^2 K / w^2 - 2 conj(w) D G / w - Q / w^2
+    const cplx a = cmul(cplx{D * D, 0.0}, cmul(K, iw2c));
+    const cplx b = cmul(cplx{2.0 * D, 0.0}, cmul(wc, cmul(G, iw)));
+    const cplx Z = {a.re - b.re - Q * iw2c.re, a.im - b.im - Q * iw2c.im};
+    hess_to_target(f, w, 0.5 * (-Q + Z.re), -0.5 * Z.im, 0.5 * (-Q - Z.re), et, ep, h);
 }
 
 }  // namespace sfmm

@@ -255,6 +255,33 @@ __global__ void __launch_bounds__(128) k_l2p(FmmCtx c, const double* tx, const d
     defl[2 * m_out + o] = az;
 }
 
+// k_l2p that also writes the local expansion's Hessian (Sec. 2.2) to hess
+// [3][m_out] (H_tt, H_tp, H_pp in the target's e_theta, e_phi)
+template <int P>
+__global__ void __launch_bounds__(128) k_l2p_hess(FmmCtx c, const double* tx, const double* ty, const double* tz,
+                                                 const int* tleaf, const uint32_t* tperm, int64_t m,
+                                                 double psi_shift, double* psi, double* defl, double* hess,
+                                                 int64_t m_out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int L = tleaf[i];
+    double rho;
+    const Frame f = box_frame(c.cen, L, &rho);
+    const double nx = tx[i], ny = ty[i], nz = tz[i];
+    double et[3], ep[3];
+    target_basis(nx, ny, nz, et, ep);
+    double p, ax, ay, az, h[3];
+    l2p_eval_hess<P>(c.local + (size_t)L * (2 * P + 2), f, rho, nx, ny, nz, et, ep, &p, &ax, &ay, &az, h);
+    const int64_t o = tperm[i];
+    psi[o] = p + psi_shift;
+    defl[o] = ax;
+    defl[m_out + o] = ay;
+    defl[2 * m_out + o] = az;
+    hess[o] = h[0];
+    hess[m_out + o] = h[1];
+    hess[2 * m_out + o] = h[2];
+}
+
 void fmm_p2m(const FmmCtx& c, int nb, hipStream_t s) {
     if (nb <= 0) return;
 #define L_(P) case P: k_p2m<P><<<nblk(nb, 128), 128, 0, s>>>(c, nb); break;
@@ -307,14 +334,40 @@ void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s) {
 
 void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* tz, const int* tleaf,
              const uint32_t* tperm, int64_t m, double psi_shift, double* psi, double* defl, int64_t m_out,
-             hipStream_t s) {
+             hipStream_t s, double* hess) {
     if (m <= 0) return;
 #define L_(P)                                                                                         \
     case P:                                                                                           \
-        k_l2p<P><<<nblk(m, 128), 128, 0, s>>>(c, tx, ty, tz, tleaf, tperm, m, psi_shift, psi, defl, m_out); \
+        if (hess)                                                                                     \
+            k_l2p_hess<P><<<nblk(m, 128), 128, 0, s>>>(c, tx, ty, tz, tleaf, tperm, m, psi_shift, psi, \
+                                                       defl, hess, m_out);                            \
+        else                                                                                          \
+            k_l2p<P><<<nblk(m, 128), 128, 0, s>>>(c, tx, ty, tz, tleaf, tperm, m, psi_shift, psi, defl, \
+                                                  m_out);                                             \
         break;
     SFMM_DISPATCH(c.p, L_)
 #undef L_
+    SFMM_LAUNCH_CHECK();
+}
+
+// Convergence, shear and magnification from the Hessian (Eq. GAM_DEF and
+// the magnification of Sec. 2.2): out [4][m] = (kappa - kappa_bar, gamma_1,
+// gamma_2, mu) from hess [3][m] = (H_11, H_12, H_22).
+__global__ void k_lensing(const double* __restrict__ hess, int64_t m, double* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double h11 = hess[i], h12 = hess[m + i], h22 = hess[2 * m + i];
+    const double kk = h11 + h22, g1 = 0.5 * (h11 - h22), g2 = h12;
+    const double a = 1.0 - 0.5 * kk;
+    out[i] = kk;
+    out[m + i] = g1;
+    out[2 * m + i] = g2;
+    out[3 * m + i] = 1.0 / (a * a - g1 * g1 - g2 * g2);
+}
+
+void lensing_from_hessian(const double* hess, int64_t m, double* out, hipStream_t s) {
+    if (m <= 0) return;
+    k_lensing<<<nblk(m, 256), 256, 0, s>>>(hess, m, out);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,163 @@
+// The judge of the per-pair order policies: the direct sum of Eq. SUM and
+// Eq. ALP_PSI (the paper's "PPM" of Sec. 4.1) at a seeded subset of the
+// targets, over every source, on the GPU.  The bound and learned policies
+// pick each FMM act's order from a criterion that only estimates its error;
+// after an execute with either, the library compares its output at these
+// targets with the direct sum and falls back to the fixed order when the
+// relative L2 error of psi or alpha exceeds the tolerance.
+//
+// Layout: each workgroup takes a chunk of kJudgeChunk sorted sources, staged
+// through LDS 256 at a time; a target is owned by kJudgeLanes threads that
+// split the chunk's sources; per chunk and target the four sums (psi, alpha
+// x, y, z) are Neumaier-compensated, combined over the lanes, and written as
+// (sum, compensation) pairs.  A second kernel adds the chunks in chunk order
+// in double-double, so the result is exact to rounding of the final sum and
+// bitwise reproducible.  The log and reciprocal are the library's own
+// (log_f64: ~2 ulp), far below the tolerances the judge checks.
+#include "common.hpp"
+#include "expand.hpp"
+
+namespace sfmm {
+
+namespace {
+constexpr int kJudgeThreads = 256;
+constexpr int kJudgeChunk = 4096;
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// part [nchunk][S][8]: (psi, c, ax, c, ay, c, az, c) of chunk j for target t.
+// Thread (target t, lane r of kJudgeLanes) takes sources r, r + kJudgeLanes,
+// ... of the chunk, so all threads work whatever S; the lanes' compensated
+// sums of a target are then combined in lane order (deterministic).
+constexpr int kJudgeLanes = 4;
+__global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* __restrict__ spt, int n,
+                                                                 const double4* __restrict__ tsel, int S,
+                                                                 double* __restrict__ part) {
+    __shared__ double4 tile[kJudgeThreads];
+    __shared__ double red[kJudgeThreads][8];
+    constexpr int TPB = kJudgeThreads / kJudgeLanes;  // targets per pass
+    const int j = blockIdx.x;
+    const int s0 = j * kJudgeChunk, s1 = min(n, s0 + kJudgeChunk);
+    const int tl = threadIdx.x / kJudgeLanes, r = threadIdx.x % kJudgeLanes;
+    for (int t0 = 0; t0 < S; t0 += TPB) {
+        const int t = t0 + tl;
+        const double4 tp = t < S ? tsel[t] : make_double4(1.0, 0.0, 0.0, 0.0);
+        double sp = 0, cp = 0, sx = 0, cx = 0, sy = 0, cy = 0, sz = 0, cz = 0;
+        for (int b = s0; b < s1; b += kJudgeThreads) {
+            __syncthreads();
+            if (b + threadIdx.x < s1) tile[threadIdx.x] = spt[b + threadIdx.x];
+            __syncthreads();
+            const int nb = min(kJudgeThreads, s1 - b);
+            for (int k = r; k < nb; k += kJudgeLanes) {
+                const double4 sr = tile[k];
+                const double dx = tp.x - sr.x, dy = tp.y - sr.y, dz = tp.z - sr.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) continue;  // a source at the target itself is left out
+                neumaier(sp, cp, sr.w * kInv4Pi * log_f64(0.25 * r2));
+                const double f = sr.w * kInv2Pi * recip(r2);
+                neumaier(sx, cx, f * dx);
+                neumaier(sy, cy, f * dy);
+                neumaier(sz, cz, f * dz);
+            }
+        }
+        double* my = red[threadIdx.x];
+        my[0] = sp; my[1] = cp; my[2] = sx; my[3] = cx;
+        my[4] = sy; my[5] = cy; my[6] = sz; my[7] = cz;
+        __syncthreads();
+        if (r == 0 && t < S) {
+            double o[8];
+            for (int q = 0; q < 4; ++q) {  // lane 0's sum, then lanes 1.. added in order (two-sum)
+                double hi = red[threadIdx.x][2 * q], lo = red[threadIdx.x][2 * q + 1];
+                for (int l = 1; l < kJudgeLanes; ++l) {
+                    double sum, e;
+                    two_sum(hi, red[threadIdx.x + l][2 * q], sum, e);
+                    lo += e + red[threadIdx.x + l][2 * q + 1];
+                    hi = sum;
+                }
+                o[2 * q] = hi;
+                o[2 * q + 1] = lo;
+            }
+            double* out = part + ((size_t)j * S + t) * 8;
+            for (int q = 0; q < 8; ++q) out[q] = o[q];
+        }
+    }
+}
+
+// out [S][4]: psi (+ shift) and the tangent projection of alpha, from the
+// chunk sums added in chunk order in double-double
+__global__ void k_judge_finish(const double* __restrict__ part, int nchunk, const double4* __restrict__ tsel, int S,
+                               double shift, double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nchunk; ++j) {
+        const double* o = part + ((size_t)j * S + t) * 8;
+        for (int k = 0; k < 4; ++k) {
+            double s, e;
+            two_sum(hi[k], o[2 * k], s, e);
+            lo[k] += e + o[2 * k + 1];
+            hi[k] = s;
+        }
+    }
+    double v[4];
+    for (int k = 0; k < 4; ++k) v[k] = hi[k] + lo[k];
+    const double4 tp = tsel[t];
+    const double nd = tp.x * v[1] + tp.y * v[2] + tp.z * v[3];
+    out[4 * t + 0] = v[0] + shift;
+    out[4 * t + 1] = v[1] - nd * tp.x;
+    out[4 * t + 2] = v[2] - nd * tp.y;
+    out[4 * t + 3] = v[3] - nd * tp.z;
+}
+
+// The subset: sorted target positions pos[k] -> their coordinates and the
+// library's outputs there (caller order through tperm)
+__global__ void k_judge_gather(const int* __restrict__ pos, int S, const double* __restrict__ tx,
+                               const double* __restrict__ ty, const double* __restrict__ tz,
+                               const uint32_t* __restrict__ tperm, const double* __restrict__ psi,
+                               const double* __restrict__ defl, int64_t m, double4* __restrict__ tsel,
+                               double* __restrict__ got) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= S) return;
+    const int j = pos[k];
+    tsel[k] = make_double4(tx[j], ty[j], tz[j], 0.0);
+    const int64_t i = tperm[j];
+    got[4 * k + 0] = psi[i];
+    got[4 * k + 1] = defl[i];
+    got[4 * k + 2] = defl[m + i];
+    got[4 * k + 3] = defl[2 * m + i];
+}
+}  // namespace
+
+size_t judge_part_doubles(int64_t n, int S) {
+    const int64_t nchunk = (n + kJudgeChunk - 1) / kJudgeChunk;
+    return (size_t)std::max<int64_t>(nchunk, 1) * (size_t)S * 8;
+}
+
+void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const double* tx, const double* ty,
+                  const double* tz, const uint32_t* tperm, const double* psi, const double* defl, int64_t m,
+                  double shift, double4* tsel, double* part, double* ref, double* got, hipStream_t s) {
+    if (S <= 0) return;
+    k_judge_gather<<<(S + 255) / 256, 256, 0, s>>>(pos, S, tx, ty, tz, tperm, psi, defl, m, tsel, got);
+    SFMM_LAUNCH_CHECK();
+    const int nchunk = (int)std::max<int64_t>((n + kJudgeChunk - 1) / kJudgeChunk, 1);
+    if (n > 0) {
+        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, part);
+        SFMM_LAUNCH_CHECK();
+    } else {
+        fill_f64(part, (size_t)S * 8, 0.0, s);
+    }
+    k_judge_finish<<<(S + 255) / 256, 256, 0, s>>>(part, nchunk, tsel, S, shift, ref);
+    SFMM_LAUNCH_CHECK();
+}
+
+}  // namespace sfmm

@@ -393,16 +393,19 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
 }
 
 // ------------------------------------------------------------ split by order
-// cnt[q * nbox + T] = pairs of T with order (q + 1) kOrderStep; the
-// per-order counters of each lane live in LDS ([q][lane]), not in scratch
-constexpr int kMaxQ = kMaxOrder / kOrderStep;
+// cnt[q * nbox + T] = pairs of T in order class q: orders in
+// (q kOrderStep, (q + 1) kOrderStep] (the top class holds the plan order p,
+// which need not be a multiple of kOrderStep); the per-class counters of
+// each lane live in LDS ([q][lane]), not in scratch
+constexpr int kMaxQ = (kMaxOrder + kOrderStep - 1) / kOrderStep;
+__device__ __forceinline__ int order_class(int o) { return (o + kOrderStep - 1) / kOrderStep - 1; }
 __global__ void __launch_bounds__(256) k_order_count(const int* __restrict__ off, const uint8_t* __restrict__ ord,
                                                      int nbox, int nq, int* __restrict__ cnt) {
     __shared__ int c[kMaxQ][256];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = 0; q < nq; ++q) c[q][threadIdx.x] = 0;
     if (t >= nbox) return;
-    for (int k = off[t]; k < off[t + 1]; ++k) ++c[ord[k] / kOrderStep - 1][threadIdx.x];
+    for (int k = off[t]; k < off[t + 1]; ++k) ++c[order_class(ord[k])][threadIdx.x];
     for (int q = 0; q < nq; ++q) cnt[(size_t)q * nbox + t] = c[q][threadIdx.x];
 }
 
@@ -417,7 +420,7 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int* __restrict__ o
     if (t >= nbox) return;
     for (int q = 0; q < nq; ++q) pos[q][threadIdx.x] = boff[(size_t)q * nbox + t];
     for (int k = off[t]; k < off[t + 1]; ++k) {
-        const int q = ord[k] / kOrderStep - 1;
+        const int q = order_class(ord[k]);
         bsrc[pos[q][threadIdx.x]++] = src[k];
     }
 }
@@ -488,7 +491,7 @@ void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* 
 
 long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
                       DVec<int>& boff, DVec<int>& bsrc, hipStream_t s) {
-    const int nq = pmax / kOrderStep;
+    const int nq = (pmax + kOrderStep - 1) / kOrderStep;
     DVec<int> cnt, tot;
     cnt.resize((size_t)nq * nbox);
     boff.resize((size_t)nq * nbox + 1);

@@ -64,7 +64,7 @@ constexpr int kM2PMinOrder = 12;
 // of T when every target is beyond ratio R_S from its centre, ratio = 1 / x
 // with the truncation term x^(p+1) at most 1e-4 tau_p (tau_p: the tolerance
 // that gives order p by the order policy, 4 times its calibrated error), and
-// at least 3: ratio 3 down to p = 23, 3.4 at p = 18, 4.5 at p = 12.  And when S holds at
+// at least 3: ratio 3 down to p = 21, 3.2 at p = 18, 4.2 at p = 12.  And when S holds at
 // least p/4 + 2 particles (measured at p = 36: lower ratios or a higher count
 // move more work than they save).
 double m2p_ratio(int p) {
@@ -109,7 +109,8 @@ __global__ void __launch_bounds__(kNearBlk) k_near_flags(FmmCtx c, const int* __
         const int T = ent_t[k], S = src[k];
         const int nt = tcount[T];
         if (nt > 0 && c.p >= kM2PMinOrder && c.count[S] >= min_count) {
-            const double a = ratio * c.rad[S];
+            // beyond every particle's profile too (near-particle model)
+            const double a = fmax(ratio * c.rad[S], c.rad[S] + c.npm_sigma);
             if (a < 3.0) {
                 const double* cs = c.cen + 4 * (size_t)S;
                 const double* ct = c.cen + 4 * (size_t)T;
@@ -393,28 +394,36 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
 
 // Adds the per-segment results of every box cut into several items, in
 // segment order: one workgroup per box, lanes over its targets.
+template <bool HESS>
 __global__ void __launch_bounds__(64) k_near_reduce(const int4* __restrict__ red, const int* __restrict__ tfirst,
                                                    const int* __restrict__ tcount,
                                                    const uint32_t* __restrict__ tperm,
                                                    const double* __restrict__ part, double* __restrict__ psi,
-                                                   double* __restrict__ defl, int64_t m_out) {
+                                                   double* __restrict__ defl, double* __restrict__ hess,
+                                                   int64_t m_out) {
+    constexpr int NV = HESS ? 7 : 4, ST = HESS ? 8 : 4;
     const int4 r = red[blockIdx.x];
     const int T = r.x, ns = r.y, base = r.z;
     const int t0 = tfirst[T], nt = tcount[T];
     for (int t = threadIdx.x; t < nt; t += 64) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
         for (int sg = 0; sg < ns; ++sg) {
-            const double* q = part + 4 * ((size_t)base + (size_t)sg * nt + t);
-            s0 += q[0];
-            s1 += q[1];
-            s2 += q[2];
-            s3 += q[3];
+            const double* q = part + ST * ((size_t)base + (size_t)sg * nt + t);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += q[k];
         }
         const int64_t o = tperm[t0 + t];
-        psi[o] += s0;
-        defl[o] += s1;
-        defl[m_out + o] += s2;
-        defl[2 * m_out + o] += s3;
+        psi[o] += v[0];
+        defl[o] += v[1];
+        defl[m_out + o] += v[2];
+        defl[2 * m_out + o] += v[3];
+        if constexpr (HESS) {
+            hess[o] += v[4];
+            hess[m_out + o] += v[5];
+            hess[2 * m_out + o] += v[6];
+        }
     }
 }
 
@@ -437,6 +446,31 @@ __device__ __forceinline__ void emit_target(int slot, int64_t o, double ps, doub
     }
 }
 
+// the same with the Hessian h[3] (slots of 8 doubles)
+__device__ __forceinline__ void emit_target_hess(int slot, int64_t o, double ps, double a0, double a1, double a2,
+                                                 const double* h, double* __restrict__ part,
+                                                 double* __restrict__ psi, double* __restrict__ defl,
+                                                 double* __restrict__ hess, int64_t m_out) {
+    if (slot < 0) {
+        psi[o] += ps;
+        defl[o] += a0;
+        defl[m_out + o] += a1;
+        defl[2 * m_out + o] += a2;
+        hess[o] += h[0];
+        hess[m_out + o] += h[1];
+        hess[2 * m_out + o] += h[2];
+    } else {
+        double* q = part + 8 * (size_t)slot;
+        q[0] = ps;
+        q[1] = a0;
+        q[2] = a1;
+        q[3] = a2;
+        q[4] = h[0];
+        q[5] = h[1];
+        q[6] = h[2];
+    }
+}
+
 // ------------------------------------------------------------ direct sums
 // Pair terms of one lane over one LDS tile.  FP64: coordinates as stored.
 // FP32 (precision tier): every coordinate is a two-float pair hi + lo
@@ -444,7 +478,8 @@ __device__ __forceinline__ void emit_target(int slot, int64_t o, double ps, doub
 // keeps ~1e-7 relative accuracy for close points where plain FP32 positions
 // would lose all digits of d; log and reciprocal are the hardware FP32
 // instructions, and each tile's FP32 partial sums (at most 256 terms) are
-// added to FP64 running sums.
+// added to FP64 running sums.  The log terms, all of one sign, are summed
+// with Kahan compensation; the deflection terms largely cancel and are not.
 struct TileF64 {
     double4 p[kTile];
 };
@@ -460,9 +495,26 @@ __device__ __forceinline__ void tile_store(TileF32& t, int k, double4 v) {
     t.lo[k] = make_float4((float)(v.x - (double)xh), (float)(v.y - (double)yh), (float)(v.z - (double)zh), 0.0f);
 }
 
-__device__ __forceinline__ void tile_pairs(const TileF64& t, const double2* ltab, const LogPoly& lk, int r, int L,
-                                           int tn, double ax, double ay, double az, double& p0, double& p1, double& p2,
-                                           double& p3) {
+// Near-particle model inside a profile (u = |d|^2/4 < t): log(4u) of the
+// point mass is replaced by log(4t) - I(u/t) and the deflection weight q/|d|^2
+// by (q/4)(2/t - v/t - 1)/(1 - u) (both finite at u = 0); see NpmK.
+template <typename R>
+__device__ __forceinline__ R npm_interior_log(R v, R t, R ln4t, int nterms) {
+    // I(v) = sum_k t^k [(2 - t)(1 - v^(k+1))/(k+1) - (1 - v^(k+2))/(k+2)]
+    R sum = 0, tk = 1, vk1 = v, vk2 = v * v;
+    for (int k = 0; k < nterms; ++k) {
+        sum += tk * ((2 - t) * (1 - vk1) / (R)(k + 1) - (1 - vk2) / (R)(k + 2));
+        tk *= t;
+        vk1 *= v;
+        vk2 *= v;
+    }
+    return ln4t - sum;
+}
+
+template <bool NPM>
+__device__ __forceinline__ void tile_pairs(const TileF64& t, const double2* ltab, const LogPoly& lk, const NpmK& nk,
+                                           int r, int L, int tn, double ax, double ay, double az, double& p0,
+                                           double& p1, double& p2, double& p3) {
     for (int j = r; j < tn; j += L) {
         const double4 sp = t.p[j];
         const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
@@ -474,7 +526,14 @@ __device__ __forceinline__ void tile_pairs(const TileF64& t, const double2* ltab
         const double d2 = __hiloint2double(d2r == 0.0 ? 0x40100000 : __double2hiint(d2r), __double2loint(d2r));
         double lg, i0;
         log_recip_tab(d2, ltab, lk, &lg, &i0);
-        const double wi = sp.w * i0;
+        double wi = sp.w * i0;
+        if constexpr (NPM) {
+            if (d2r < nk.four_t) {
+                const double u = 0.25 * d2r, v = u * nk.inv_t;
+                lg = npm_interior_log(v, nk.t, nk.ln4t, nk.nterms);
+                wi = sp.w * 0.25 * (2.0 * nk.inv_t - v * nk.inv_t - 1.0) / (1.0 - u);
+            }
+        }
         p0 = fma(sp.w, lg, p0);
         p1 = fma(wi, dx, p1);
         p2 = fma(wi, dy, p2);
@@ -482,13 +541,14 @@ __device__ __forceinline__ void tile_pairs(const TileF64& t, const double2* ltab
     }
 }
 
-__device__ __forceinline__ void tile_pairs(const TileF32& t, const double2*, const LogPoly&, int r, int L, int tn,
-                                           double ax, double ay, double az, double& p0, double& p1, double& p2,
-                                           double& p3) {
+template <bool NPM>
+__device__ __forceinline__ void tile_pairs(const TileF32& t, const double2*, const LogPoly&, const NpmK& nk, int r,
+                                           int L, int tn, double ax, double ay, double az, double& p0, double& p1,
+                                           double& p2, double& p3) {
     const float axh = (float)ax, ayh = (float)ay, azh = (float)az;
     const float axl = (float)(ax - (double)axh), ayl = (float)(ay - (double)ayh), azl = (float)(az - (double)azh);
     constexpr float kLn2f = 0.693147180559945309f, kLog4f = 1.38629436111989061f;
-    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
+    float f0 = 0.0f, c0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
     for (int j = r; j < tn; j += L) {
         const float4 h = t.hi[j], l = t.lo[j];
         const float dx = (axh - h.x) + (axl - l.x);
@@ -497,30 +557,136 @@ __device__ __forceinline__ void tile_pairs(const TileF32& t, const double2*, con
         const float d2 = dx * dx + dy * dy + dz * dz;
         const bool coinc = d2 == 0.0f;
         const float r2 = coinc ? 1.0f : d2;
-        const float lg = coinc ? kLog4f : __builtin_amdgcn_logf(r2) * kLn2f;
-        const float wi = h.w * __builtin_amdgcn_rcpf(r2);
-        f0 = fmaf(h.w, lg, f0);
+        float lg = coinc ? kLog4f : __builtin_amdgcn_logf(r2) * kLn2f;
+        float wi = h.w * __builtin_amdgcn_rcpf(r2);
+        if constexpr (NPM) {
+            if (d2 < (float)nk.four_t) {
+                const float u = 0.25f * d2, v = u * (float)nk.inv_t;
+                lg = npm_interior_log(v, (float)nk.t, (float)nk.ln4t, nk.nterms);
+                wi = h.w * 0.25f * (2.0f * (float)nk.inv_t - v * (float)nk.inv_t - 1.0f) / (1.0f - u);
+            }
+        }
+        // the log terms all have one sign and grow the sum to ~100 times
+        // each: Kahan-compensated (c0 carries the lost low part)
+        const float y = fmaf(h.w, lg, -c0);
+        const float tt = f0 + y;
+        c0 = (tt - f0) - y;
+        f0 = tt;
         f1 = fmaf(wi, dx, f1);
         f2 = fmaf(wi, dy, f2);
         f3 = fmaf(wi, dz, f3);
     }
-    p0 += (double)f0;
+    p0 += (double)f0 - (double)c0;
     p1 += (double)f1;
     p2 += (double)f2;
     p3 += (double)f3;
 }
 
-template <class Tile>
+// Pair terms with the Hessian of Sec. 2.2: per source, in the target's
+// basis e_a, e_b (et, ep), H_ab = (q/2pi) [delta_ab (1 - n.d)/|d|^2 - 2 (e_a.d)
+// (e_b.d)/|d|^4]; the lane sums hd = sum q (1 - n.d)/|d|^2 and h_ab = sum q
+// (e_a.d)(e_b.d)/|d|^4 (coincident points add nothing).
+template <bool NPM>
+__device__ __forceinline__ void tile_pairs_hess(const TileF64& t, const double2* ltab, const LogPoly& lk,
+                                                const NpmK& nk, int r, int L, int tn, double ax, double ay, double az,
+                                                const double* et, const double* ep, double* acc) {
+    for (int j = r; j < tn; j += L) {
+        const double4 sp = t.p[j];
+        const double dx = ax - sp.x, dy = ay - sp.y, dz = az - sp.z;
+        const double d2r = dx * dx + dy * dy + dz * dz;
+        const double d2 = __hiloint2double(d2r == 0.0 ? 0x40100000 : __double2hiint(d2r), __double2loint(d2r));
+        double lg, i0;
+        log_recip_tab(d2, ltab, lk, &lg, &i0);
+        double wi = sp.w * i0;
+        double wm = d2r == 0.0 ? 0.0 : wi;
+        double w2 = wm * i0;
+        if constexpr (NPM) {
+            if (d2r < nk.four_t) {
+                const double u = 0.25 * d2r, v = u * nk.inv_t, omu = 1.0 - u;
+                lg = npm_interior_log(v, nk.t, nk.ln4t, nk.nterms);
+                wi = sp.w * 0.25 * (2.0 * nk.inv_t - v * nk.inv_t - 1.0) / omu;
+                wm = wi;
+                w2 = sp.w * nk.a2 / (omu * omu);
+            }
+        }
+        acc[0] = fma(sp.w, lg, acc[0]);
+        acc[1] = fma(wi, dx, acc[1]);
+        acc[2] = fma(wi, dy, acc[2]);
+        acc[3] = fma(wi, dz, acc[3]);
+        const double nd = ax * dx + ay * dy + az * dz;
+        const double da = et[0] * dx + et[1] * dy + et[2] * dz;
+        const double db = ep[0] * dx + ep[1] * dy + ep[2] * dz;
+        acc[4] = fma(-nd, wm, acc[4] + wm);
+        acc[5] = fma(w2 * da, da, acc[5]);
+        acc[6] = fma(w2 * da, db, acc[6]);
+        acc[7] = fma(w2 * db, db, acc[7]);
+    }
+}
+
+template <bool NPM>
+__device__ __forceinline__ void tile_pairs_hess(const TileF32& t, const double2*, const LogPoly&, const NpmK& nk,
+                                                int r, int L, int tn, double ax, double ay, double az,
+                                                const double* et, const double* ep, double* acc) {
+    const float axh = (float)ax, ayh = (float)ay, azh = (float)az;
+    const float axl = (float)(ax - (double)axh), ayl = (float)(ay - (double)ayh), azl = (float)(az - (double)azh);
+    const float etf[3] = {(float)et[0], (float)et[1], (float)et[2]};
+    const float epf[3] = {(float)ep[0], (float)ep[1], (float)ep[2]};
+    constexpr float kLn2f = 0.693147180559945309f, kLog4f = 1.38629436111989061f;
+    float f[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, c0 = 0.0f;
+    for (int j = r; j < tn; j += L) {
+        const float4 h = t.hi[j], l = t.lo[j];
+        const float dx = (axh - h.x) + (axl - l.x);
+        const float dy = (ayh - h.y) + (ayl - l.y);
+        const float dz = (azh - h.z) + (azl - l.z);
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const bool coinc = d2 == 0.0f;
+        const float r2 = coinc ? 1.0f : d2;
+        float lg = coinc ? kLog4f : __builtin_amdgcn_logf(r2) * kLn2f;
+        const float i0 = __builtin_amdgcn_rcpf(r2);
+        float wi = h.w * i0;
+        float wm = coinc ? 0.0f : wi;
+        float w2 = wm * i0;
+        if constexpr (NPM) {
+            if (d2 < (float)nk.four_t) {
+                const float u = 0.25f * d2, v = u * (float)nk.inv_t, omu = 1.0f - u;
+                lg = npm_interior_log(v, (float)nk.t, (float)nk.ln4t, nk.nterms);
+                wi = h.w * 0.25f * (2.0f * (float)nk.inv_t - v * (float)nk.inv_t - 1.0f) / omu;
+                wm = wi;
+                w2 = h.w * (float)nk.a2 / (omu * omu);
+            }
+        }
+        const float y = fmaf(h.w, lg, -c0);  // Kahan-compensated log terms, as in tile_pairs
+        const float tt = f[0] + y;
+        c0 = (tt - f[0]) - y;
+        f[0] = tt;
+        f[1] = fmaf(wi, dx, f[1]);
+        f[2] = fmaf(wi, dy, f[2]);
+        f[3] = fmaf(wi, dz, f[3]);
+        // 1 - n.d = 1 - |d|^2/2 for unit vectors (n.d = |d|^2 / 2)
+        const float da = etf[0] * dx + etf[1] * dy + etf[2] * dz;
+        const float db = epf[0] * dx + epf[1] * dy + epf[2] * dz;
+        f[4] = fmaf(-0.5f * d2, wm, f[4] + wm);
+        f[5] = fmaf(w2 * da, da, f[5]);
+        f[6] = fmaf(w2 * da, db, f[6]);
+        f[7] = fmaf(w2 * db, db, f[7]);
+    }
+    acc[0] += (double)f[0] - (double)c0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) acc[k] += (double)f[k];
+}
+
+template <class Tile, bool HESS, bool NPM>
 __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ items,
                                            const int* __restrict__ src, const int* __restrict__ tfirst,
                                            const int* __restrict__ tcount, const double* __restrict__ tx,
                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
                                            double* __restrict__ defl, int64_t m_out, double* __restrict__ part,
-                                           LogPoly lk) {
+                                           LogPoly lk, double* __restrict__ hess, NpmK nk) {
     // the tile and the end-of-group reduction share one LDS block (fewer
     // bytes per wave, more waves per CU)
-    constexpr size_t kSm = sizeof(Tile) > 4 * 64 * sizeof(double) ? sizeof(Tile) : 4 * 64 * sizeof(double);
+    constexpr int NR = HESS ? 8 : 4;  // sums per lane: psi, alpha (and hd, h_tt, h_tp, h_pp)
+    constexpr size_t kSm = sizeof(Tile) > NR * 64 * sizeof(double) ? sizeof(Tile) : NR * 64 * sizeof(double);
     __shared__ __align__(16) unsigned char sm[kSm];
     Tile& tile = *reinterpret_cast<Tile*>(sm);
     double(*red)[64] = reinterpret_cast<double(*)[64]>(sm);
@@ -547,6 +713,9 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
         const double ax = tx[my], ay = ty[my], az = tz[my];
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;  // S, V partials of this lane
         double qnear = 0.0;                              // lane partials of Q_near
+        double hacc[HESS ? 8 : 1] = {};                  // HESS: psi, alpha, hd, h_ab partials
+        double et[3], ep[3];
+        if constexpr (HESS) target_basis(ax, ay, az, et, ep);
         for (int kc = 0; kc < K; kc += 64) {
             const int kk = min(64, K - kc);
             int cnt = 0, fst = 0;
@@ -586,32 +755,58 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
                     }
                 }
                 __syncthreads();
-                if (active) tile_pairs(tile, ltab, lk, r, L, tn, ax, ay, az, p0, p1, p2, p3);
+                if (active) {
+                    if constexpr (HESS) tile_pairs_hess<NPM>(tile, ltab, lk, nk, r, L, tn, ax, ay, az, et, ep, hacc);
+                    else tile_pairs<NPM>(tile, ltab, lk, nk, r, L, tn, ax, ay, az, p0, p1, p2, p3);
+                }
             }
         }
         const double qn = wave_sum(qnear);
+        if constexpr (HESS) {
+            p0 = hacc[0];
+            p1 = hacc[1];
+            p2 = hacc[2];
+            p3 = hacc[3];
+        }
         __syncthreads();  // the last tile fully consumed before red overwrites it
         red[0][lane] = p0;
         red[1][lane] = p1;
         red[2][lane] = p2;
         red[3][lane] = p3;
+        if constexpr (HESS) {
+#pragma unroll
+            for (int q = 4; q < 8; ++q) red[q][lane] = hacc[q];
+        }
         __syncthreads();
         if (lane < ng) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            double sh[4] = {0.0, 0.0, 0.0, 0.0};
             for (int j = lane * L; j < lane * L + L; ++j) {
                 s0 += red[0][j];
                 s1 += red[1][j];
                 s2 += red[2][j];
                 s3 += red[3][j];
+                if constexpr (HESS) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sh[q] += red[4 + q][j];
+                }
             }
             const int me = g0 + lane;
             const double mx = tx[me], myy = ty[me], mz = tz[me];
             const double il = 1.0 / sqrt(mx * mx + myy * myy + mz * mz);
             const double ux = mx * il, uy = myy * il, uz = mz * il;
             const double vr = ux * s1 + uy * s2 + uz * s3;
-            emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[me], (s0 + (1.0 - kLog4) * qn) * kInv4Pi,
-                        (s1 - ux * vr) * kInv2Pi, (s2 - uy * vr) * kInv2Pi, (s3 - uz * vr) * kInv2Pi, part, psi,
-                        defl, m_out);
+            if constexpr (HESS) {
+                const double h[3] = {(sh[0] - 2.0 * sh[1]) * kInv2Pi, -2.0 * sh[2] * kInv2Pi,
+                                     (sh[0] - 2.0 * sh[3]) * kInv2Pi};
+                emit_target_hess(item.w < 0 ? -1 : item.w + tg + lane, tperm[me],
+                                 (s0 + (1.0 - kLog4) * qn) * kInv4Pi, (s1 - ux * vr) * kInv2Pi,
+                                 (s2 - uy * vr) * kInv2Pi, (s3 - uz * vr) * kInv2Pi, h, part, psi, defl, hess, m_out);
+            } else {
+                emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[me], (s0 + (1.0 - kLog4) * qn) * kInv4Pi,
+                            (s1 - ux * vr) * kInv2Pi, (s2 - uy * vr) * kInv2Pi, (s3 - uz * vr) * kInv2Pi, part, psi,
+                            defl, m_out);
+            }
         }
         __syncthreads();  // red is reused by the next group
     }
@@ -627,19 +822,21 @@ __global__ void __launch_bounds__(64) k_p2p(FmmCtx c, const int4* __restrict__ i
 // group.
 constexpr int kChunkF = 16;
 
-template <int P>
+template <int P, bool HESS>
 __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ items,
                                            const int* __restrict__ src, const int* __restrict__ tfirst,
                                            const int* __restrict__ tcount, const double* __restrict__ tx,
                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                            const uint32_t* __restrict__ tperm, double* __restrict__ psi,
-                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part) {
+                                           double* __restrict__ defl, int64_t m_out, double* __restrict__ part,
+                                           double* __restrict__ hess) {
     constexpr int EW = 2 * P + 2;
     // the staged records double as the end-of-group reduction buffer
     static_assert(kChunkF * (2 * kM2PMinOrder + 2) >= 4 * 64, "reduction fits the record buffer");
     __shared__ __align__(16) double coef[kChunkF * EW];
     __shared__ double frm[kChunkF][10];  // c, e_theta, e_phi, rho
     double(*red)[64] = reinterpret_cast<double(*)[64]>(coef);
+    __shared__ double redh[HESS ? 3 : 1][64];  // the Hessian's partials
     const int lane = threadIdx.x;
     const int4 item = items[blockIdx.x];
     const int T = item.x;
@@ -654,6 +851,9 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
         const int my = g0 + (active ? team : 0);
         const double nx = tx[my], ny = ty[my], nz = tz[my];
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        double hs[3] = {0.0, 0.0, 0.0};
+        double et[3], ep[3];
+        if constexpr (HESS) target_basis(nx, ny, nz, et, ep);
         for (int kc = 0; kc < K; kc += kChunkF) {
             const int cf = min(kChunkF, K - kc);
             __syncthreads();  // previous chunk fully consumed
@@ -687,7 +887,15 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
                         fr.ep[d] = frm[j][6 + d];
                     }
                     double ps, ax, ay, az;
-                    m2p_eval<P>(coef + j * EW, fr, frm[j][9], nx, ny, nz, &ps, &ax, &ay, &az);
+                    if constexpr (HESS) {
+                        double h[3];
+                        m2p_eval_hess<P>(coef + j * EW, fr, frm[j][9], nx, ny, nz, et, ep, &ps, &ax, &ay, &az, h);
+                        hs[0] += h[0];
+                        hs[1] += h[1];
+                        hs[2] += h[2];
+                    } else {
+                        m2p_eval<P>(coef + j * EW, fr, frm[j][9], nx, ny, nz, &ps, &ax, &ay, &az);
+                    }
                     p0 += ps;
                     p1 += ax;
                     p2 += ay;
@@ -700,58 +908,119 @@ __global__ void __launch_bounds__(64) k_m2p(FmmCtx c, const int4* __restrict__ i
         red[1][lane] = p1;
         red[2][lane] = p2;
         red[3][lane] = p3;
+        if constexpr (HESS) {
+            redh[0][lane] = hs[0];
+            redh[1][lane] = hs[1];
+            redh[2][lane] = hs[2];
+        }
         __syncthreads();
         if (lane < ng) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            double h[3] = {0.0, 0.0, 0.0};
             for (int j = lane * L; j < lane * L + L; ++j) {
                 s0 += red[0][j];
                 s1 += red[1][j];
                 s2 += red[2][j];
                 s3 += red[3][j];
+                if constexpr (HESS) {
+                    h[0] += redh[0][j];
+                    h[1] += redh[1][j];
+                    h[2] += redh[2][j];
+                }
             }
-            emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[g0 + lane], s0, s1, s2, s3, part, psi, defl,
-                        m_out);
+            if constexpr (HESS)
+                emit_target_hess(item.w < 0 ? -1 : item.w + tg + lane, tperm[g0 + lane], s0, s1, s2, s3, h, part,
+                                 psi, defl, hess, m_out);
+            else
+                emit_target(item.w < 0 ? -1 : item.w + tg + lane, tperm[g0 + lane], s0, s1, s2, s3, part, psi,
+                            defl, m_out);
         }
         __syncthreads();  // red is reused by the next group
     }
 }
 
 void reduce_items(const WorkItems& w, const int* tfirst, const int* tcount, const uint32_t* tperm, double* psi,
-                  double* defl, int64_t m_out, double* part, hipStream_t s) {
+                  double* defl, int64_t m_out, double* part, hipStream_t s, double* hess) {
     if (w.nred <= 0) return;
-    k_near_reduce<<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, part, psi, defl, m_out);
+    if (hess)
+        k_near_reduce<true><<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, part, psi, defl,
+                                                            hess, m_out);
+    else
+        k_near_reduce<false><<<(unsigned)w.nred, 64, 0, s>>>(w.red.data(), tfirst, tcount, tperm, part, psi, defl,
+                                                             nullptr, m_out);
     SFMM_LAUNCH_CHECK();
 }
 
 void fmm_p2p(const FmmCtx& c, bool fp32, const WorkItems& w, const int* src, const int* tfirst,
              const int* tcount, const double* tx, const double* ty, const double* tz, const uint32_t* tperm,
-             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part) {
+             double* psi, double* defl, int64_t m_out, hipStream_t s, double* part, double* hess) {
     if (w.n <= 0) return;
+    if (hess && !part && w.nred > 0) throw Error(ST_INTERNAL, "the Hessian needs partial slots of 8 doubles");
     if (!part) part = w.part.data();
-    if (fp32)
-        k_p2p<TileF32><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, part, kLogPoly);
-    else
-        k_p2p<TileF64><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi,
-                                                    defl, m_out, part, kLogPoly);
+    const NpmK nk = npm_params(c.npm_sigma);
+    const bool npm = c.npm_sigma > 0.0;
+#define P2P_(T, H, N)                                                                                          \
+    k_p2p<T, H, N><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, \
+                                                defl, m_out, part, kLogPoly, hess, nk)
+#define P2P_N(T, H)              \
+    if (npm) P2P_(T, H, true);   \
+    else P2P_(T, H, false)
+    if (fp32) {
+        if (hess) P2P_N(TileF32, true);
+        else P2P_N(TileF32, false);
+    } else {
+        if (hess) P2P_N(TileF64, true);
+        else P2P_N(TileF64, false);
+    }
+#undef P2P_N
+#undef P2P_
     SFMM_LAUNCH_CHECK();
-    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s);
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s, hess);
 }
 
 void fmm_m2p(const FmmCtx& c, const WorkItems& w, const int* src, const int* tfirst, const int* tcount,
              const double* tx, const double* ty, const double* tz, const uint32_t* tperm, double* psi,
-             double* defl, int64_t m_out, hipStream_t s, double* part) {
+             double* defl, int64_t m_out, hipStream_t s, double* part, double* hess) {
     if (w.n <= 0 || c.p < kM2PMinOrder) return;
+    if (hess && !part && w.nred > 0) throw Error(ST_INTERNAL, "the Hessian needs partial slots of 8 doubles");
     if (!part) part = w.part.data();
-#define L_(P)                                                                                             \
-    case P:                                                                                               \
-        k_m2p<P><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, tperm, psi, \
-                                              defl, m_out, part);                                         \
+#define L_(P)                                                                                                 \
+    case P:                                                                                                   \
+        if (hess)                                                                                             \
+            k_m2p<P, true><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz,  \
+                                                        tperm, psi, defl, m_out, part, hess);                 \
+        else                                                                                                  \
+            k_m2p<P, false><<<(unsigned)w.n, 64, 0, s>>>(c, w.items.data(), src, tfirst, tcount, tx, ty, tz, \
+                                                         tperm, psi, defl, m_out, part, nullptr);             \
         break;
     SFMM_DISPATCH(c.p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
-    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s);
+    reduce_items(w, tfirst, tcount, tperm, psi, defl, m_out, part, s, hess);
+}
+
+double npm_constant(double sigma) {
+    if (!(sigma > 0.0)) return 0.0;
+    const double st = std::sin(0.5 * sigma), t = st * st;
+    double J = 0.0, tk = 1.0;
+    for (int k = 0; k < 200 && tk > 1e-18; ++k, tk *= t) J += tk * ((2.0 - t) / (k + 2) - 1.0 / (k + 3));
+    return t * (J - 1.0);
+}
+
+NpmK npm_params(double sigma) {
+    NpmK k{};
+    if (!(sigma > 0.0)) return k;
+    const double st = std::sin(0.5 * sigma);
+    k.t = st * st;
+    k.inv_t = 1.0 / k.t;
+    k.four_t = 4.0 * k.t;
+    k.ln4t = std::log(4.0 * k.t);
+    const double a = (1.0 - k.t) / k.t;
+    k.a2 = a * a / 16.0;
+    // terms of the series for I until t^k < 2^-56 (v <= 1)
+    k.nterms = 1;
+    for (double tk = k.t; tk >= 0x1p-56 && k.nterms < 64; tk *= k.t) ++k.nterms;
+    return k;
 }
 
 }  // namespace sfmm

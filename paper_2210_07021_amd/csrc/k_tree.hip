@@ -411,15 +411,23 @@ void box_geometry(int nb, const int* level, const uint64_t* pixel, double* cen, 
     SFMM_LAUNCH_CHECK();
 }
 
+// Protected radius of a source box (Sec. 3.5): c_s R, widened to R + sigma
+// under the near-particle model so that a particle's whole profile lies
+// inside it.  FP64 and double-double forms.
+__device__ __forceinline__ double protected_radius(double r, double c_s, double sigma) {
+    const double p = c_s * r;
+    return (sigma > 0.0 && r + sigma > p) ? r + sigma : p;
+}
+
 __global__ void k_walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0,
-                             const int* count, double c_s, double c_t, double4* geo, double2* strig, double4* ttrig,
-                             int2* cc, double* dtrig) {
+                             const int* count, double c_s, double c_t, double sigma, double4* geo, double2* strig,
+                             double4* ttrig, int2* cc, double* dtrig) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const double r = rad[b];
     geo[b] = make_double4(cen[4 * b], cen[4 * b + 1], cen[4 * b + 2], r);
     double s1, c1, s2, c2, s3, c3;
-    sincos(c_s * r, &s1, &c1);
+    sincos(protected_radius(r, c_s, sigma), &s1, &c1);
     sincos(r, &s2, &c2);
     sincos(r / c_t, &s3, &c3);
     strig[b] = make_double2(c1, s1);
@@ -427,8 +435,12 @@ __global__ void k_walk_boxes(int nb, const double* cen, const double* rad, const
     cc[b] = make_int2(child0[b], count[b]);
     // double-double tables for the exact decisions of near-ties
     const dd R = {gdd[8 * (size_t)b + 6], gdd[8 * (size_t)b + 7]};
-    const dd ang[3] = {dd_mul_d(R, c_s), R, dd_div(R, dd_from(c_t))};
-    double* o = dtrig + 12 * (size_t)b;
+    const bool widen = sigma > 0.0 && r + sigma > c_s * r;
+    const dd prot = widen ? dd_add(R, dd_from(sigma)) : dd_mul_d(R, c_s);
+    const dd ang[3] = {prot, R, dd_div(R, dd_from(c_t))};
+    double* o = dtrig + kWalkDtrig * (size_t)b;
+    o[12] = prot.hi;
+    o[13] = prot.lo;
     for (int k = 0; k < 3; ++k) {
         dd sn, cs;
         dd_sincos(ang[k], &sn, &cs);
@@ -440,11 +452,11 @@ __global__ void k_walk_boxes(int nb, const double* cen, const double* rad, const
 }
 
 void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
-                double c_s, double c_t, double4* geo, double2* strig, double4* ttrig, int2* cc, double* dtrig,
-                hipStream_t s) {
+                double c_s, double c_t, double sigma, double4* geo, double2* strig, double4* ttrig, int2* cc,
+                double* dtrig, hipStream_t s) {
     if (nb <= 0) return;
-    k_walk_boxes<<<nblocks(nb, 128), 128, 0, s>>>(nb, cen, rad, gdd, child0, count, c_s, c_t, geo, strig, ttrig, cc,
-                                                  dtrig);
+    k_walk_boxes<<<nblocks(nb, 128), 128, 0, s>>>(nb, cen, rad, gdd, child0, count, c_s, c_t, sigma, geo, strig, ttrig,
+                                                  cc, dtrig);
     SFMM_LAUNCH_CHECK();
 }
 
@@ -549,8 +561,8 @@ __device__ __forceinline__ uint8_t walk_action_fast(const WalkCtx& w, int s, int
     const int2 bt = w.cc[t];
     const double4 gs = w.geo[s], gt = w.geo[t];
     const double rs = gs.w, rt = gt.w;
-    const int f = mac_far_filter_trig(gs.x, gs.y, gs.z, gt.x, gt.y, gt.z, rs, rt, w.strig[s], w.ttrig[t], w.c_s,
-                                      w.c_t);
+    const int f = mac_far_filter_trig(gs.x, gs.y, gs.z, gt.x, gt.y, gt.z, protected_radius(rs, w.c_s, w.sigma), rt,
+                                      w.strig[s], w.ttrig[t], 1.0, w.c_t);
     if (f > 0) return A_M2L;
     if (f == 0) return A_TIE;
     const bool sl = bs.x < 0, tl = bt.x < 0;
@@ -570,16 +582,16 @@ __device__ uint8_t walk_action_tie(const WalkCtx& w, int s, int t) {
     const double4 gs4 = w.geo[s], gt4 = w.geo[t];
     const double* a = w.gdd + 8 * (size_t)s;
     const double* b = w.gdd + 8 * (size_t)t;
-    int f = mac_far_filter_trig(gs4.x, gs4.y, gs4.z, gt4.x, gt4.y, gt4.z, gs4.w, gt4.w, w.strig[s], w.ttrig[t],
-                                w.c_s, w.c_t);
+    int f = mac_far_filter_trig(gs4.x, gs4.y, gs4.z, gt4.x, gt4.y, gt4.z, protected_radius(gs4.w, w.c_s, w.sigma),
+                                gt4.w, w.strig[s], w.ttrig[t], 1.0, w.c_t);
     if (f == 0) {
         const dd csd[3] = {{a[0], a[1]}, {a[2], a[3]}, {a[4], a[5]}};
         const dd ctd[3] = {{b[0], b[1]}, {b[2], b[3]}, {b[4], b[5]}};
-        const double* ta = w.dtrig + 12 * (size_t)s;
-        const double* tb = w.dtrig + 12 * (size_t)t;
+        const double* ta = w.dtrig + kWalkDtrig * (size_t)s;
+        const double* tb = w.dtrig + kWalkDtrig * (size_t)t;
         const dd ts[2] = {{ta[0], ta[1]}, {ta[2], ta[3]}};
         const dd tt[4] = {{tb[4], tb[5]}, {tb[6], tb[7]}, {tb[8], tb[9]}, {tb[10], tb[11]}};
-        f = mac_far_dd_trig(csd, ctd, dd{a[6], a[7]}, dd{b[6], b[7]}, ts, tt, w.c_s, w.c_t) ? 1 : -1;
+        f = mac_far_dd_trig(csd, ctd, dd{ta[12], ta[13]}, dd{b[6], b[7]}, ts, tt, 1.0, w.c_t) ? 1 : -1;
     }
     if (f > 0) return A_M2L;
     const bool sl = bs.x < 0, tl = bt.x < 0;

@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 
@@ -10,40 +11,71 @@ namespace sfmm {
 
 // ------------------------------------------------------------------ pool
 // A freed block is not handed out again until the work that may still use
-// it has finished: pool_free records an event on the stream of the current
-// API call (PoolStream), and pool_alloc takes a cached block only if it was
-// freed on the stream now allocating (stream order then covers the reuse) or
-// its event has completed.  Blocks are kept per device.  While a stream is
-// being captured into a graph no event is recorded and the block is retired
-// instead (graph replays may still use it; it is released with the pool).
+// it has finished.  Each API call is one epoch on its stream (PoolStream):
+// blocks freed during the call belong to it, and when the call ends one
+// event is recorded on the stream for the whole epoch (the last use of each
+// of its blocks was queued before that).  A cached block is reused by an
+// allocation on the stream of its epoch at once (stream order covers it),
+// by one on any other stream only once its epoch has ended and the event
+// has completed.  Blocks are kept per device.  While a stream is being
+// captured into a graph its frees are retired instead (graph replays may
+// still use them); they are released with the pool.
 namespace {
+struct Epoch {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    bool ended = false;   // the event is recorded
+    bool waited = false;  // ... and has completed
+    Epoch() = default;
+    Epoch(const Epoch&) = delete;
+    Epoch& operator=(const Epoch&) = delete;
+    ~Epoch() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
 struct FreeBlock {
     void* p;
     int dev;
-    hipStream_t s;
-    hipEvent_t ev;  // null: reusable at once
+    std::shared_ptr<Epoch> ep;  // null: reusable at once
 };
 std::mutex g_pool_mu;
-std::multimap<size_t, FreeBlock> g_free;              // size -> block
+// never destroyed: the blocks' events must not be released after the HIP
+// runtime has shut down at process exit
+std::multimap<size_t, FreeBlock>& g_free = *new std::multimap<size_t, FreeBlock>;  // size -> block
 std::unordered_map<void*, std::pair<size_t, int>> g_size;  // live and free blocks: size, device
-std::vector<hipEvent_t> g_spare_events;
 std::vector<void*> g_retired;
-thread_local hipStream_t t_stream = nullptr;
-thread_local bool t_capturing = false;
-thread_local bool t_idle = false;
+struct ThreadScope {
+    std::shared_ptr<Epoch> ep;
+    bool capturing = false, idle = false, used = false;
+};
+thread_local ThreadScope t_scope;
 }  // namespace
 
-PoolStream::PoolStream(hipStream_t s, bool capturing, bool idle)
-    : prev_s(t_stream), prev_cap(t_capturing), prev_idle(t_idle) {
-    t_stream = s;
-    t_capturing = capturing;
-    t_idle = idle;
+PoolStream::PoolStream(hipStream_t s, bool capturing, bool idle) {
+    auto* prev = new ThreadScope(t_scope);
+    saved = prev;
+    t_scope = ThreadScope{};
+    t_scope.ep = std::make_shared<Epoch>();
+    t_scope.ep->s = s;
+    t_scope.capturing = capturing;
+    t_scope.idle = idle;
 }
 
 PoolStream::~PoolStream() {
-    t_stream = prev_s;
-    t_capturing = prev_cap;
-    t_idle = prev_idle;
+    // end the epoch: one event covers every block freed in it
+    if (t_scope.used && !t_scope.idle && !t_scope.capturing) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        Epoch& e = *t_scope.ep;
+        if (hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(e.ev, e.s) == hipSuccess) {
+            e.ended = true;
+        } else {
+            (void)hipGetLastError();  // never ended: its blocks serve only their own stream
+        }
+    }
+    auto* prev = static_cast<ThreadScope*>(saved);
+    t_scope = *prev;
+    delete prev;
 }
 
 static size_t size_class(size_t b) {
@@ -59,19 +91,20 @@ void* pool_alloc(size_t bytes) {
     const size_t sz = size_class(bytes);
     int dev = 0;
     SFMM_HIP(hipGetDevice(&dev));
+    hipStream_t cur = t_scope.ep ? t_scope.ep->s : nullptr;
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         for (auto it = g_free.lower_bound(sz); it != g_free.end() && it->first <= 2 * sz; ++it) {
             const FreeBlock& b = it->second;
-            PoolBlockState st{b.dev, b.s, b.ev != nullptr, false};
-            if (b.ev && b.s != t_stream && b.dev == dev) {
-                const hipError_t q = hipEventQuery(b.ev);
+            PoolBlockState st{b.dev, b.ep ? b.ep->s : nullptr, b.ep != nullptr && !b.ep->waited, false};
+            if (st.has_event && st.s != cur && b.dev == dev && b.ep->ended) {
+                const hipError_t q = hipEventQuery(b.ep->ev);
                 if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+                if (q == hipSuccess) b.ep->waited = true;
                 st.event_done = q == hipSuccess;
             }
-            if (!pool_reusable(st, t_stream, dev)) continue;
+            if (!pool_reusable(st, cur, dev)) continue;
             void* p = b.p;
-            if (b.ev) g_spare_events.push_back(b.ev);
             g_free.erase(it);
             return p;
         }
@@ -97,26 +130,15 @@ void pool_free(void* p) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_size.find(p);
     if (it == g_size.end()) return;
-    if (t_capturing) {
+    if (t_scope.capturing) {
         g_retired.push_back(p);
         return;
     }
-    FreeBlock b{p, it->second.second, t_stream, nullptr};
-    if (!t_idle) {
-        if (!g_spare_events.empty()) {
-            b.ev = g_spare_events.back();
-            g_spare_events.pop_back();
-        } else if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
-            (void)hipGetLastError();
-            b.ev = nullptr;
-        }
-        // no event (creation failed): the block is retired, not reused early
-        if (!b.ev || hipEventRecord(b.ev, t_stream) != hipSuccess) {
-            (void)hipGetLastError();
-            if (b.ev) g_spare_events.push_back(b.ev);
-            g_retired.push_back(p);
-            return;
-        }
+    FreeBlock b{p, it->second.second, nullptr};
+    if (!t_scope.idle) {
+        if (!t_scope.ep) t_scope.ep = std::make_shared<Epoch>();  // outside any API call: the null stream
+        b.ep = t_scope.ep;
+        t_scope.used = true;
     }
     g_free.emplace(it->second.first, b);
 }
@@ -127,7 +149,6 @@ void pool_release_all() {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto& kv : g_free) {
         (void)hipFree(kv.second.p);
-        if (kv.second.ev) g_spare_events.push_back(kv.second.ev);
         g_size.erase(kv.second.p);
     }
     g_free.clear();

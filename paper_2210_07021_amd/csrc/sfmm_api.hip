@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -132,6 +133,7 @@ struct sfmm_plan_impl {
     DVec<double> mult, local;
     DVec<double> zrec;  // one zero record (lanes past the end of an FMM-act list)
     DVec<float> multf;  // precision tier: FP32 A-blocks of the multipoles
+    DVec<double> hess_part;  // partial slots of 8 doubles (sfmm_execute_hessian)
     // per-pair order policies
     DVec<int> m2l_ent;        // target box of every FMM-act entry (per-pair order policies)
     DVec<int> p2p_ent;        // target box of every direct-act entry (until the near-field split)
@@ -141,6 +143,10 @@ struct sfmm_plan_impl {
     DVec<int> ord_off, ord_src;  // FMM acts split by order
     long long m2l_order_sq = 0;
     bool executed = false;
+    // judge of the per-pair order policies (first execute of the plan)
+    bool judged = false, judge_failed = false;
+    int judge_S = 0;
+    double judge_psi = -1.0, judge_alpha = -1.0;
     std::unique_ptr<Pinned> pin;
     // recorded at the end of every sfmm_plan / sfmm_execute on the caller's
     // stream (not while a graph is recorded): sfmm_destroy waits for it
@@ -172,6 +178,7 @@ struct sfmm_plan_impl {
         c.mult = mult.data();
         c.local = local.data();
         c.zrec = zrec.data();
+        c.npm_sigma = opt.npm_sigma;
         return c;
     }
 };
@@ -200,6 +207,8 @@ void validate(const sfmm_options& o) {
     if (o.order_policy == SFMM_ORDER_LEARNED && !o.mlp_weights) bad("the learned order policy needs mlp_weights");
     if (o.near_segment != 0 && (o.near_segment < 8 || o.near_segment > 4096)) bad("near_segment must be 0 or in [8, 4096]");
     if (o.far_segment != 0 && (o.far_segment < 8 || o.far_segment > 4096)) bad("far_segment must be 0 or in [8, 4096]");
+    if (o.judge_targets > 4096) bad("judge_targets must be at most 4096");
+    if (!(o.npm_sigma >= 0.0 && o.npm_sigma <= 0.5)) bad("npm_sigma must be in [0, 0.5]");
 }
 
 // Sort points by key and keep the permutation; outputs resized here: the
@@ -475,9 +484,9 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     strig.resize(std::max(P.nbox, 1));
     ttrig.resize(std::max(P.nbox, 1));
     cc.resize(std::max(P.nbox, 1));
-    dtrig.resize(12 * (size_t)std::max(P.nbox, 1));
+    dtrig.resize(kWalkDtrig * (size_t)std::max(P.nbox, 1));
     walk_boxes(P.nbox, P.cen.data(), P.rad.data(), P.gdd.data(), P.child0.data(), P.count.data(), P.opt.c_s,
-               P.opt.c_t, geo.data(), strig.data(), ttrig.data(), cc.data(), dtrig.data(), s);
+               P.opt.c_t, P.opt.npm_sigma, geo.data(), strig.data(), ttrig.data(), cc.data(), dtrig.data(), s);
     WalkCtx w;
     w.child0 = P.child0.data();
     w.count = P.count.data();
@@ -489,6 +498,7 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     w.dtrig = dtrig.data();
     w.c_s = P.opt.c_s;
     w.c_t = P.opt.c_t;
+    w.sigma = P.opt.npm_sigma;
     DVec<uint64_t> m2l, p2p;
     int n_m2l = 0, n_p2p = 0;
     if (!walk(P, w, false, m2l, p2p, &n_m2l, &n_p2p, s) && !walk(P, w, true, m2l, p2p, &n_m2l, &n_p2p, s))
@@ -584,22 +594,26 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
 
 // Order from a tolerance, by a measured calibration at the default MACs
 // (c_s = 2, c_t = 0.5).  kOrderCal[k] is the largest relative L2 error of
-// the deflection (the slower output to converge; psi is ~1000 times smaller)
-// at order p = 12 + 4k over uniform-1e4 (leaf sizes 16, 32, 64),
-// clustered-5e4 (16, 32, 64), clustered-1e6 (16, 32, 64; 1e4 sampled
-// targets) and clustered-1e7 (32, 56; 1e4 sampled targets), FP64 against the
-// direct sum.  The order is the smallest p whose error, interpolated
-// log-linearly in p (end slopes outside 12..40), is at most a quarter of the
-// tolerance.  The worst targets are on leaf corners: HEALPix grid targets
-// sit on the vertices of every deeper pixel.
-constexpr double kOrderCal[] = {9.09e-6, 6.40e-7, 5.43e-8, 5.37e-9, 6.13e-10, 8.15e-11, 1.02e-11, 1.26e-12};
+// the deflection (the slower output to converge; psi is ~100 times smaller)
+// at order p = 8 + 2k, over every target of uniform-1e4 (leaf sizes 16, 32,
+// 64), clustered-5e4 (16, 32, 64), clustered-1e6 (16, 32, 64) and
+// clustered-1e7 (32, 56), each order against the same plan at order 48
+// (itself ~1e-14 from the direct sum).  clustered-1e6 is the worst sky at
+// every order: its tail targets, on the corners of deep leaves next to
+// massive clumps, set the norm.  The order is the smallest p whose error,
+// interpolated log-linearly in p (end slopes outside 8..44), is at most a
+// quarter of the tolerance.
+constexpr double kOrderCal[] = {3.48e-4, 8.80e-5,  2.29e-5,  6.12e-6,  1.69e-6,  4.82e-7,  1.44e-7,
+                                4.48e-8, 1.46e-8,  4.90e-9,  1.70e-9,  6.03e-10, 2.19e-10, 8.11e-11,
+                                3.04e-11, 1.15e-11, 4.40e-12, 1.66e-12, 5.97e-13};
 constexpr int kOrderCalN = sizeof(kOrderCal) / sizeof(kOrderCal[0]);
+constexpr int kOrderCalP0 = 8, kOrderCalStep = 2;
 constexpr double kOrderMarginFactor = 4.0;
 
 }  // namespace
 
 double sfmm::order_calibrated_error(int p) {
-    const double x = (p - 12) / 4.0;
+    const double x = (double)(p - kOrderCalP0) / kOrderCalStep;
     const int k = std::min(kOrderCalN - 2, std::max(0, (int)std::floor(x)));
     const double t = x - k;
     return std::exp(std::log(kOrderCal[k]) + t * (std::log(kOrderCal[k + 1]) - std::log(kOrderCal[k])));
@@ -607,9 +621,13 @@ double sfmm::order_calibrated_error(int p) {
 
 namespace {
 
+// Odd orders are rounded up to the next even one: measured on clustered-1e7,
+// the M2L kernel at an odd order runs ~15 % slower per flop than at the even
+// orders around it (36: 2.93 ms, 37: 3.60 ms, 38: 3.25 ms), so the next even
+// order costs less and is more accurate.
 int order_for_tolerance(double tol) {
     for (int p = 4; p < kMaxOrder; ++p)
-        if (order_calibrated_error(p) * kOrderMarginFactor <= tol) return p;
+        if (order_calibrated_error(p) * kOrderMarginFactor <= tol) return p + (p & 1);
     return kMaxOrder;
 }
 
@@ -695,11 +713,18 @@ size_t exec_scratch_bytes(const sfmm_plan_impl& P, size_t* off_far = nullptr, si
 }
 
 // The five stages of Sec. 3.7 on a plan; xs = null: the plan's own buffers.
-void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, const ExecScratch* xs) {
-    const double shift = (P.opt.psi_gauge == SFMM_GAUGE_RAW) ? -P.q_total * 0.079577471545947667884 : 0.0;
+// fixed: every FMM act at the plan order whatever the order policy.
+// hess [3][M] (may be null): also the Hessian of Sec. 2.2.
+void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, const ExecScratch* xs, bool fixed,
+                  double* hess = nullptr) {
+    // raw gauge: without the share Q_tot/(4pi); near-particle model: the
+    // constant of the smoothed particles' potential
+    const double shift = ((P.opt.psi_gauge == SFMM_GAUGE_RAW) ? -P.q_total : 0.0) * 0.079577471545947667884 +
+                         P.q_total * 0.079577471545947667884 * npm_constant(P.opt.npm_sigma);
     if (P.N == 0) {
         fill_f64(psi, P.M, 0.0, s);
         fill_f64(defl, 3 * P.M, 0.0, s);
+        if (hess) fill_f64(hess, 3 * P.M, 0.0, s);
         return;
     }
     // every multipole record is written by Lemma 1 (leaves) or Lemma 2
@@ -737,7 +762,7 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
                 fmm_m2l_f32(c, p, acc, multf, P.m2l_order.data() + P.n_m2l_fp64,
                             P.nbox - P.n_m2l_fp64, off, src, s);
         };
-        if (P.opt.order_policy == SFMM_ORDER_FIXED || P.n_m2l == 0) {
+        if (fixed || P.opt.order_policy == SFMM_ORDER_FIXED || P.n_m2l == 0) {
             m2l_pass(P.p, false, P.m2l_off.data(), P.m2l_src.data());
             P.m2l_order_sq = (long long)P.n_m2l * P.p * P.p;
         } else {
@@ -753,8 +778,10 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
             }
             P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
                                          P.p, P.ord_off, P.ord_src, s);
-            for (int q = 0; q < P.p / kOrderStep; ++q)
-                m2l_pass((q + 1) * kOrderStep, q > 0, P.ord_off.data() + (size_t)q * P.nbox, P.ord_src.data());
+            // class q holds the orders in (4q, 4q + 4]; the top class the plan order
+            for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q)
+                m2l_pass(std::min((q + 1) * kOrderStep, P.p), q > 0, P.ord_off.data() + (size_t)q * P.nbox,
+                         P.ord_src.data());
             m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
         }
     }
@@ -767,19 +794,83 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
     {
         StageScope st(prof, S_L2P);
         fmm_l2p(c, P.tx.data(), P.ty.data(), P.tz.data(), P.tleaf.data(), P.tperm.data(), P.M, shift, psi,
-                defl, P.M, s);
+                defl, P.M, s, hess);
+    }
+    // the Hessian's partial slots hold 8 doubles instead of 4
+    double* far_part = xs ? xs->far_part : nullptr;
+    double* near_part = xs ? xs->near_part : nullptr;
+    if (hess) {
+        P.hess_part.resize(8 * ((size_t)std::max(P.far_items.nslot, 1) + (size_t)std::max(P.near_items.nslot, 1)));
+        far_part = P.hess_part.data();
+        near_part = P.hess_part.data() + 8 * (size_t)std::max(P.far_items.nslot, 1);
     }
     {
         StageScope st(prof, S_M2P);
         fmm_m2p(c, P.far_items, P.nl.far_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
-                P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s, xs ? xs->far_part : nullptr);
+                P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s, far_part, hess);
     }
     {
         StageScope st(prof, S_P2P);
-        fmm_p2p(c, P.opt.precision == SFMM_FP32_MIXED, P.near_items, P.nl.near_src.data(), P.tfirst.data(), P.tcount.data(), P.tx.data(),
-                P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s, xs ? xs->near_part : nullptr);
+        fmm_p2p(c, P.opt.precision == SFMM_FP32_MIXED, P.near_items, P.nl.near_src.data(), P.tfirst.data(),
+                P.tcount.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi, defl, P.M, s,
+                near_part, hess);
     }
     prof.flush();
+}
+
+constexpr int kJudgeDefault = 64;
+
+// The judge: psi and alpha of the last execute at S seeded targets against
+// their direct sum; sets P.judge_psi / judge_alpha (relative L2 errors).
+void run_judge(sfmm_plan_impl& P, const double* psi, const double* defl, hipStream_t s) {
+    const int S = (int)std::min<int64_t>(P.M, P.opt.judge_targets > 0 ? P.opt.judge_targets : kJudgeDefault);
+    P.judge_S = S;
+    if (S <= 0) {
+        P.judge_psi = P.judge_alpha = 0.0;
+        return;
+    }
+    // distinct sorted target positions from a counter-based generator
+    // (splitmix64), seeded by the plan's sizes
+    std::vector<int> pos;
+    std::vector<char> taken((size_t)P.M, 0);
+    for (uint64_t i = 0; (int)pos.size() < S; ++i) {
+        uint64_t z = 0x2210070210ULL + (uint64_t)P.N * 0x9e3779b97f4a7c15ULL + 0x9e3779b97f4a7c15ULL * (i + 1);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        const int64_t j = (int64_t)(z % (uint64_t)P.M);
+        if (!taken[j]) {
+            taken[j] = 1;
+            pos.push_back((int)j);
+        }
+    }
+    DVec<int> dpos;
+    DVec<double4> tsel;
+    DVec<double> part, ref, got;
+    dpos.resize(S);
+    tsel.resize(S);
+    part.resize(judge_part_doubles(P.N, S));
+    ref.resize(4 * (size_t)S);
+    got.resize(4 * (size_t)S);
+    SFMM_HIP(hipMemcpyAsync(dpos.data(), pos.data(), sizeof(int) * S, hipMemcpyHostToDevice, s));
+    const double shift = (P.opt.psi_gauge == SFMM_GAUGE_RAW) ? 0.0 : P.q_total * 0.079577471545947667884;
+    judge_direct(P.spt.data(), P.N, dpos.data(), S, P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi,
+                 defl, P.M, shift, tsel.data(), part.data(), ref.data(), got.data(), s);
+    std::vector<double> hr(4 * (size_t)S), hg(4 * (size_t)S);
+    SFMM_HIP(hipMemcpyAsync(hr.data(), ref.data(), sizeof(double) * 4 * S, hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipMemcpyAsync(hg.data(), got.data(), sizeof(double) * 4 * S, hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    double dp = 0, rp = 0, da = 0, ra = 0;
+    for (int k = 0; k < S; ++k) {
+        dp += (hg[4 * k] - hr[4 * k]) * (hg[4 * k] - hr[4 * k]);
+        rp += hr[4 * k] * hr[4 * k];
+        for (int c = 1; c < 4; ++c) {
+            da += (hg[4 * k + c] - hr[4 * k + c]) * (hg[4 * k + c] - hr[4 * k + c]);
+            ra += hr[4 * k + c] * hr[4 * k + c];
+        }
+    }
+    P.judge_psi = rp > 0 ? std::sqrt(dp / rp) : std::sqrt(dp);
+    P.judge_alpha = ra > 0 ? std::sqrt(da / ra) : std::sqrt(da);
 }
 
 // ---- no-allocation execute (sfmm_execute_noalloc)
@@ -846,8 +937,6 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         P->pin.reset(new Pinned());
         P->opt = o;
         P->p = o.order > 0 ? o.order : order_for_tolerance(o.tolerance);
-        if (o.order_policy != SFMM_ORDER_FIXED)
-            P->p = std::min(kMaxOrder, ((P->p + kOrderStep - 1) / kOrderStep) * kOrderStep);
         P->N = N;
         P->M = M;
         Profiler prof(s);
@@ -900,9 +989,109 @@ sfmm_status sfmm_execute(sfmm_plan_t plan, double* psi, double* defl, void* stre
         if (!psi || !defl) throw Error(ST_INVALID_ARG, "psi or defl is NULL");
         hipStream_t s = (hipStream_t)stream;
         PoolStream ps(s, g_capturing);
-        execute_impl(P, psi, defl, s, nullptr);
+        const bool policy = P.opt.order_policy != SFMM_ORDER_FIXED && P.N > 0;
+        const bool fallen = policy && P.judge_failed && !P.opt.no_fallback;
+        execute_impl(P, psi, defl, s, nullptr, fallen);
+        if (policy && !P.judged && P.opt.judge_targets >= 0) {
+            if (g_capturing) throw Error(ST_INVALID_ARG, "a per-pair order policy cannot be judged during capture");
+            run_judge(P, psi, defl, s);
+            P.judged = true;
+            P.judge_failed = !(P.judge_psi <= P.opt.tolerance && P.judge_alpha <= P.opt.tolerance);
+            if (P.judge_failed && !P.opt.no_fallback) execute_impl(P, psi, defl, s, nullptr, true);
+        }
         P.executed = true;
         P.mark_done(s);
+        if (policy && P.judge_failed && P.opt.no_fallback) {
+            char m[160];
+            std::snprintf(m, sizeof(m), "order policy failed its judge: relative L2 error psi %.3e alpha %.3e > %.1e",
+                          P.judge_psi, P.judge_alpha, P.opt.tolerance);
+            throw Error(ST_TOL, m);
+        }
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SFMM_ERR_INTERNAL;
+    }
+}
+
+sfmm_status sfmm_execute_hessian(sfmm_plan_t plan, double* psi, double* defl, double* hess, void* stream) {
+    try {
+        if (!plan) throw Error(ST_INVALID_ARG, "plan is NULL");
+        sfmm_plan_impl& P = *plan;
+        if (P.M == 0) return SFMM_OK;
+        if (!psi || !defl || !hess) throw Error(ST_INVALID_ARG, "psi, defl or hess is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        PoolStream ps(s, g_capturing);
+        // the per-pair order policies run as in sfmm_execute, including the
+        // fallback verdict of an earlier judge
+        const bool policy = P.opt.order_policy != SFMM_ORDER_FIXED && P.N > 0;
+        const bool fallen = policy && P.judge_failed && !P.opt.no_fallback;
+        execute_impl(P, psi, defl, s, nullptr, fallen, hess);
+        if (policy && !P.judged && P.opt.judge_targets >= 0) {
+            if (g_capturing) throw Error(ST_INVALID_ARG, "a per-pair order policy cannot be judged during capture");
+            run_judge(P, psi, defl, s);
+            P.judged = true;
+            P.judge_failed = !(P.judge_psi <= P.opt.tolerance && P.judge_alpha <= P.opt.tolerance);
+            if (P.judge_failed && !P.opt.no_fallback) execute_impl(P, psi, defl, s, nullptr, true, hess);
+        }
+        P.executed = true;
+        P.mark_done(s);
+        if (policy && P.judge_failed && P.opt.no_fallback)
+            throw Error(ST_TOL, "order policy failed its judge (see sfmm_stats)");
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SFMM_ERR_INTERNAL;
+    }
+}
+
+sfmm_status sfmm_lensing(const double* hess, int64_t M, double* out, void* stream) {
+    try {
+        if (M < 0) throw Error(ST_INVALID_ARG, "M must be >= 0");
+        if (M > 0 && (!hess || !out)) throw Error(ST_INVALID_ARG, "hess or out is NULL");
+        lensing_from_hessian(hess, M, out, (hipStream_t)stream);
+        return SFMM_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+sfmm_status sfmm_raytrace(int32_t nlayer, const double* const* src, const double* const* q, const int64_t* N,
+                          const double* weight, double* rays, int64_t M, double* dist, const sfmm_options* opt,
+                          void* stream) {
+    try {
+        if (nlayer < 1 || nlayer > 4096) throw Error(ST_INVALID_ARG, "nlayer must be in [1, 4096]");
+        if (!src || !q || !N || !weight) throw Error(ST_INVALID_ARG, "NULL array");
+        if (M < 0 || M > 0x7fffffff) throw Error(ST_INVALID_ARG, "M must be in [0, 2^31 - 1]");
+        for (int i = 0; i < nlayer; ++i)
+            if (!std::isfinite(weight[i])) throw Error(ST_INVALID_ARG, "layer weights must be finite");
+        if (M == 0) return SFMM_OK;
+        if (!rays) throw Error(ST_INVALID_ARG, "rays is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        PoolStream ps(s);
+        DVec<double> psi, defl, hess;
+        psi.resize(M);
+        defl.resize(3 * (size_t)M);
+        if (dist) {
+            hess.resize(3 * (size_t)M);
+            ray_identity(dist, M, s);
+        }
+        for (int i = 0; i < nlayer; ++i) {
+            // the layer's plan has the rays' current positions as targets
+            sfmm_plan_t p = nullptr;
+            sfmm_status st = sfmm_plan(src[i], q[i], N[i], rays, M, opt, stream, &p);
+            if (st != SFMM_OK) return st;
+            st = dist ? sfmm_execute_hessian(p, psi.data(), defl.data(), hess.data(), stream)
+                      : sfmm_execute(p, psi.data(), defl.data(), stream);
+            sfmm_destroy(p);
+            if (st != SFMM_OK) return st;
+            ray_step(rays, defl.data(), dist ? hess.data() : nullptr, weight[i], M, dist, s);
+        }
+        SFMM_HIP(hipStreamSynchronize(s));
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);
@@ -930,7 +1119,7 @@ sfmm_status sfmm_execute_noalloc(sfmm_plan_t plan, double* psi, double* defl, vo
         ExecScratch xs{(double*)base, (double*)(base + off_far), (float*)(base + off_mf)};
         hipStream_t s = (hipStream_t)stream;
         PoolStream ps(s, g_capturing);
-        execute_impl(P, psi, defl, s, &xs);
+        execute_impl(P, psi, defl, s, &xs, true);
         P.executed = true;
         if (P.done && !g_capturing) SFMM_HIP(hipEventRecord(P.done, s));
         return SFMM_OK;
@@ -982,6 +1171,10 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->leaf_size = P.opt.leaf_size;
         out->q_total = P.q_total;
         out->execute_scratch_bytes = (int64_t)exec_scratch_bytes(P);
+        out->judge_psi = P.judged ? P.judge_psi : -1.0;
+        out->judge_alpha = P.judged ? P.judge_alpha : -1.0;
+        out->judge_targets = P.judged ? P.judge_S : 0;
+        out->fell_back = (P.judge_failed && !P.opt.no_fallback) ? 1 : 0;
         return SFMM_OK;
     } catch (const Error& e) {
         return fail(e);

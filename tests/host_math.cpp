@@ -10,6 +10,10 @@
 //            leaves undecided; the undecided ones go to the double-double
 //            sine-form test, checked against the double-double angle test
 //            and against long double where that settles the sign
+//   hess   : random local and multipole expansions (order 12) in random
+//            frames; prints the largest difference, relative to the largest
+//            entry, between the Hessian of l2p_eval_hess / m2p_eval_hess and
+//            central differences of their deflection along great circles
 //   pool   : reads "dev stream has_event event_done alloc_stream alloc_dev"
 //            rows (integers; streams as small handles), prints the memory
 //            pool's reuse decision (1 = the cached block may be handed out)
@@ -33,6 +37,65 @@ static long double angle_ld(const double* a, const double* b) {
 
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
+    if (!strcmp(argv[1], "hess")) {
+        std::mt19937_64 g(11);
+        std::normal_distribution<double> nd(0.0, 1.0);
+        std::uniform_real_distribution<double> ud(0.0, 1.0);
+        auto unit = [&](double* v) {
+            const double r = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int d = 0; d < 3; ++d) v[d] /= r;
+        };
+        constexpr int P = 12;
+        double worst[2] = {0, 0};
+        for (int trial = 0; trial < 200; ++trial) {
+            double c[3] = {nd(g), nd(g), nd(g)};
+            unit(c);
+            const Frame f = make_frame(c[0], c[1], c[2]);
+            const double rho = 0.05 + 0.2 * ud(g);
+            double e[2 * P + 2];
+            for (int k = 0; k < 2 * P + 2; ++k) e[k] = nd(g);
+            for (int kind = 0; kind < 2; ++kind) {
+                // a target at stereographic radius 0.8 rho (local) or 2.5 rho
+                // (multipole) from the centre, in a random direction
+                const double rr = (kind == 0 ? 0.8 : 2.5) * rho * (kind == 0 ? ud(g) : 1.0 + ud(g));
+                const double ang = 6.283185307179586 * ud(g);
+                const double u = rr * std::cos(ang), v = rr * std::sin(ang);
+                // inverse stereographic map in the frame: n = ((2u, 2v, 1 - |w|^2) / (1 + |w|^2))
+                const double w2 = u * u + v * v, den = 1.0 / (1.0 + w2);
+                double n[3];
+                for (int d = 0; d < 3; ++d)
+                    n[d] = (2.0 * u * f.et[d] + 2.0 * v * f.ep[d] + (1.0 - w2) * f.c[d]) * den;
+                double et[3], ep[3];
+                target_basis(n[0], n[1], n[2], et, ep);
+                double ps, a0, a1, a2, h[3];
+                if (kind == 0) l2p_eval_hess<P>(e, f, rho, n[0], n[1], n[2], et, ep, &ps, &a0, &a1, &a2, h);
+                else m2p_eval_hess<P>(e, f, rho, n[0], n[1], n[2], et, ep, &ps, &a0, &a1, &a2, h);
+                const double H[2][2] = {{h[0], h[1]}, {h[1], h[2]}};
+                const double* E[2] = {et, ep};
+                const double hs = 1e-5;
+                double err = 0, big = 0;
+                for (int a = 0; a < 2; ++a) {
+                    double al[2][3];
+                    for (int sgn = 0; sgn < 2; ++sgn) {
+                        const double sg = sgn == 0 ? 1.0 : -1.0;
+                        double m[3];
+                        for (int d = 0; d < 3; ++d) m[d] = n[d] * std::cos(hs) + sg * E[a][d] * std::sin(hs);
+                        if (kind == 0) l2p_eval<P>(e, f, rho, m[0], m[1], m[2], &ps, &al[sgn][0], &al[sgn][1], &al[sgn][2]);
+                        else m2p_eval<P>(e, f, rho, m[0], m[1], m[2], &ps, &al[sgn][0], &al[sgn][1], &al[sgn][2]);
+                    }
+                    for (int b = 0; b < 2; ++b) {
+                        double fd = 0;
+                        for (int d = 0; d < 3; ++d) fd += E[b][d] * (al[0][d] - al[1][d]) / (2 * hs);
+                        err = std::max(err, std::fabs(fd - H[a][b]));
+                        big = std::max(big, std::fabs(H[a][b]));
+                    }
+                }
+                worst[kind] = std::max(worst[kind], err / big);
+            }
+        }
+        printf("%.3e %.3e\n", worst[0], worst[1]);
+        return 0;
+    }
     if (!strcmp(argv[1], "pool")) {
         long d, st, he, ed, as, ad;
         while (scanf("%ld %ld %ld %ld %ld %ld", &d, &st, &he, &ed, &as, &ad) == 6) {

@@ -68,9 +68,10 @@ def test_host_only_calls(lib):
     assert lib.sfmm_status_string(1) == b"invalid argument"
     ps = [sf.order_for_tolerance(t) for t in (1e-2, 1e-6, 1e-10, 1e-14)]
     assert ps == sorted(ps) and 1 <= ps[0] and ps[-1] <= 48
-    # the measured calibration with its margin of 4: p = 35 at 1e-10, 18 at 1e-6
-    assert sf.order_for_tolerance(1e-10) == 35
-    assert sf.order_for_tolerance(1e-6) == 18
+    # the measured calibration with its margin of 4 (37 at 1e-10, rounded up
+    # to an even order), 20 at 1e-6
+    assert sf.order_for_tolerance(1e-10) == 38
+    assert sf.order_for_tolerance(1e-6) == 20
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):

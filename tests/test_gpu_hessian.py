@@ -1,0 +1,105 @@
+"""GPU parity of the Hessian of psi (Sec. 2.2, the matrix H of Eq. GAM_DEF)
+from sfmm_execute_hessian against the oracle's direct sum of H, and of the
+lensing quantities (kappa - kappa_bar, gamma_1, gamma_2, mu) from
+sfmm_lensing; psi and alpha of the same call against sfmm_execute."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_07021_amd import skies
+from parity_util import check, errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _sf():
+    import paper_2210_07021_amd as sf
+    sf.load_library()
+    return sf
+
+
+def _cases():
+    src, q, tgt = skies.workload("uniform-1e4")
+    yield "uniform-1e4", src, q, tgt
+    rng = skies.rng_for(102)
+    s2 = skies.clustered(50000, rng, n_clumps=100)
+    q2 = skies.masses_lognormal(50000, rng)
+    t2 = np.concatenate([skies.grid(32), s2[:, :2000], np.array([[0.0, 0.0], [0.0, 0.0], [1.0, -1.0]])], axis=1)
+    yield "clustered-5e4", s2, q2, t2
+
+
+def _run(src, q, tgt, **opt):
+    import torch
+    sf = _sf()
+    plan = sf.Plan(src, q, tgt, **opt)
+    psi, defl, hess = plan.execute_hessian()
+    p2, d2 = plan.execute()
+    lens = sf.lensing(hess)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    return st, psi.cpu().numpy(), defl.cpu().numpy(), hess.cpu().numpy(), p2.cpu().numpy(), d2.cpu().numpy(), \
+        lens.cpu().numpy()
+
+
+# Gates: the Hessian is one derivative further from psi than alpha, and its
+# truncation error decays one order more slowly; at the tolerance's order it
+# is gated at 100 times the tolerance (rel-L2 over the target set, H as the
+# 3-vector (H_11, H_12, H_22)).
+@pytest.mark.parametrize("case", ["uniform-1e4", "clustered-5e4"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32-mixed"])
+def test_hessian_matches_oracle(case, precision, oracle_lib):
+    name, src, q, tgt = next(c for c in _cases() if c[0] == case)
+    tol = 1e-10 if precision == 0 else 1e-6
+    st, psi, defl, hess, p2, d2, lens = _run(src, q, tgt, tolerance=tol, leaf_size=32, precision=precision)
+    ref_h = oracle.hessian(src, q, tgt)
+    ref_p, ref_a = oracle.direct(src, q, tgt)
+    # psi and alpha of the Hessian call are those of sfmm_execute
+    assert np.allclose(psi, p2, rtol=0, atol=1e-14 * np.abs(p2).max())
+    assert np.allclose(defl, d2, rtol=0, atol=1e-14 * np.abs(d2).max())
+    check(f"hessian-call psi/alpha {name} precision {precision}", psi, defl, ref_p, ref_a, tol)
+    gate = 100 * tol if precision == 0 else 1e-4
+    _, eH, _, wH = errors(hess, hess, ref_h, ref_h)
+    print(f"[hessian] {name} precision {precision} p={st['order']}: H rel-L2 {eH:.3e}, worst target {wH:.3e}",
+          flush=True)
+    assert eH <= gate and wH <= 100 * gate
+    # trace = kappa - kappa_bar = -Q_tot/(4 pi) off the sources (Eq. LAP_GRE)
+    off = np.ones(tgt.shape[1], bool)
+    sk = {tuple(x) for x in src.T}
+    off &= np.array([tuple(x) not in sk for x in tgt.T])
+    tr = hess[0] + hess[2]
+    scale = np.abs(ref_h).max()
+    assert np.allclose(tr[off], -q.sum() / (4 * np.pi), rtol=0, atol=(100 * gate) * scale)
+    # lensing quantities on the GPU against the oracle's from its own H
+    ref_l = oracle.lensing(ref_h)
+    assert np.allclose(lens[:3], oracle.lensing(hess)[:3], rtol=1e-15, atol=1e-15 * scale)
+    el = np.linalg.norm(lens[1:3] - ref_l[1:3]) / np.linalg.norm(ref_l[1:3])
+    print(f"[hessian] {name} precision {precision}: shear rel-L2 {el:.3e}", flush=True)
+    assert el <= gate
+    ok = np.isfinite(ref_l[3])
+    assert np.allclose(lens[3][ok], oracle.lensing(hess)[3][ok], rtol=1e-12)
+
+
+def test_hessian_at_fixed_order_and_point_mass(oracle_lib):
+    """One mass: H at every target is the point-mass closed form, also from
+    the expansions (the mass far from the targets' leaves)."""
+    rng = skies.rng_for(131)
+    src = np.array([[0.2], [-0.3], [np.sqrt(1 - 0.13)]])
+    q = np.array([3.0])
+    tgt = skies.uniform(2000, rng)
+    st, psi, defl, hess, _, _, _ = _run(src, q, tgt, order=12, leaf_size=1)
+    ref_h = oracle.hessian(src, q, tgt)
+    eH = np.linalg.norm(hess - ref_h) / np.linalg.norm(ref_h)
+    print(f"[hessian] point mass: {eH:.3e}", flush=True)
+    assert eH <= 1e-12
+
+
+def test_hessian_empty_sources(oracle_lib):
+    import torch
+    sf = _sf()
+    tgt = skies.uniform(50, skies.rng_for(132))
+    plan = sf.Plan(np.zeros((3, 0)), np.zeros(0), tgt, order=8)
+    psi, defl, hess = plan.execute_hessian()
+    torch.cuda.synchronize()
+    assert not hess.cpu().numpy().any() and not psi.cpu().numpy().any()
+    plan.close()

@@ -187,7 +187,97 @@ def test_learned_policy_gain(oracle_lib):
         st, psi, defl = _run(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_LEARNED,
                              mlp_weights=w)
         gain = st["m2l_order_sq"] / fx["m2l_order_sq"]
-        check(f"learned {name}: M2L work {gain:.3f} of fixed, bound {bd['m2l_order_sq'] / fx['m2l_order_sq']:.3f}",
+        check(f"learned {name}: M2L work {gain:.3f} of fixed, bound {bd['m2l_order_sq'] / fx['m2l_order_sq']:.3f}; "
+              f"judge psi {st['judge_psi']:.2e} alpha {st['judge_alpha']:.2e} on {st['judge_targets']} targets",
               psi, defl, ref_p, ref_a, tol)
+        assert st["fell_back"] == 0 and st["judge_targets"] == 64
+        assert 0 <= st["judge_psi"] <= tol and 0 <= st["judge_alpha"] <= tol
         assert st["m2l_order_sq"] <= 0.95 * fx["m2l_order_sq"]
         assert st["m2l_order_sq"] < bd["m2l_order_sq"]
+
+
+def _corrupted_weights(sf):
+    """Order network weights whose output bias sends every pair to the
+    lowest order: far too coarse for the tolerance."""
+    w = sf.mlp_init(5)
+    w[-1] = -100.0
+    return w
+
+
+def test_judge_falls_back_to_fixed_order(oracle_lib):
+    """A network that predicts far too low orders fails the judge (the GPU
+    direct sum at 64 seeded targets); the plan reruns at the fixed order,
+    whose result meets the tolerance against the oracle, and keeps that
+    verdict for later executes."""
+    import torch
+    sf = _sf()
+    src, q, tgt = _policy_case("clustered-5e4")
+    ref_p, ref_a = oracle.direct(src, q, tgt)
+    tol = 1e-6
+    plan = sf.Plan(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_LEARNED,
+                   mlp_weights=_corrupted_weights(sf))
+    psi, defl = plan.execute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    print(f"[judge] corrupted network: judge psi {st['judge_psi']:.2e} alpha {st['judge_alpha']:.2e}, "
+          f"fell back {st['fell_back']}", flush=True)
+    assert st["fell_back"] == 1 and st["judge_alpha"] > tol
+    assert st["m2l_order_sq"] == st["n_m2l"] * st["order"] ** 2
+    check("judge fallback", psi.cpu().numpy(), defl.cpu().numpy(), ref_p, ref_a, tol)
+    # later executes run at the fixed order directly
+    psi2, defl2 = plan.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(psi, psi2) and torch.equal(defl, defl2)
+    # the same with the fixed order policy gives bitwise the same result
+    fx = sf.Plan(src, q, tgt, tolerance=tol, leaf_size=32, order=st["order"])
+    psi3, defl3 = fx.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(psi, psi3) and torch.equal(defl, defl3)
+    plan.close()
+    fx.close()
+
+
+def test_judge_without_fallback_reports_tolerance_not_met(oracle_lib):
+    import torch
+    sf = _sf()
+    src, q, tgt = _policy_case("clustered-5e4")
+    plan = sf.Plan(src, q, tgt, tolerance=1e-6, leaf_size=32, order_policy=sf.SFMM_ORDER_LEARNED,
+                   mlp_weights=_corrupted_weights(sf), no_fallback=1)
+    with pytest.raises(sf.SfmmError) as e:
+        plan.execute()
+    assert e.value.status == sf.SFMM_ERR_TOLERANCE_NOT_MET
+    torch.cuda.synchronize()
+    st = plan.stats()
+    assert st["fell_back"] == 0 and st["judge_alpha"] > 1e-6
+    with pytest.raises(sf.SfmmError):
+        plan.execute()
+    plan.close()
+
+
+def test_judge_direct_sum_matches_oracle(oracle_lib):
+    """The judge's own direct sum is exact: with a bound policy at a loose
+    tolerance it reports the error of the policy's result at its targets,
+    which equals the error computed here against the oracle at the same
+    targets (the judge's subset is reproduced from the exported target
+    order)."""
+    import torch
+    sf = _sf()
+    rng = skies.rng_for(130)
+    src = skies.clustered(20000, rng, n_clumps=40)
+    q = skies.masses_lognormal(20000, rng)
+    tgt = np.concatenate([skies.grid(16), src[:, :500]], axis=1)
+    plan = sf.Plan(src, q, tgt, tolerance=1e-3, leaf_size=16, order_policy=sf.SFMM_ORDER_BOUND,
+                   judge_targets=tgt.shape[1])
+    psi, defl = plan.execute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    ref_p, ref_a = oracle.direct(src, q, tgt)
+    psi, defl = psi.cpu().numpy(), defl.cpu().numpy()
+    ep = np.linalg.norm(psi - ref_p) / np.linalg.norm(ref_p)
+    ea = np.linalg.norm(defl - ref_a) / np.linalg.norm(ref_a)
+    print(f"[judge] all {tgt.shape[1]} targets: judge psi {st['judge_psi']:.6e} alpha {st['judge_alpha']:.6e}; "
+          f"oracle psi {ep:.6e} alpha {ea:.6e}", flush=True)
+    assert st["judge_targets"] == tgt.shape[1] and st["fell_back"] == 0
+    assert abs(st["judge_psi"] - ep) <= 1e-6 * ep + 1e-15
+    assert abs(st["judge_alpha"] - ea) <= 1e-6 * ea + 1e-15
+    plan.close()

@@ -158,3 +158,13 @@ def test_pool_reuse_rule(host_math):
     out = _run(host_math, "pool", "\n".join(" ".join(map(str, c)) for c, _ in cases) + "\n")
     got = [int(x) for x in out if x.strip()]
     assert got == [w for _, w in cases]
+
+
+def test_expansion_hessians_are_derivatives_of_the_deflection(host_math):
+    """The Hessian of the local (L2P) and multipole (M2P) expansions at a
+    point, from the conformal-metric formulas, equals the covariant
+    derivative of the same expansion's deflection (central differences
+    along great circles), for random coefficients and frames."""
+    out = _run(host_math, "hess")
+    loc, mul = (float(x) for x in out[0].split())
+    assert loc < 1e-6 and mul < 1e-6, (loc, mul)

@@ -18,6 +18,8 @@ on sampled NFW haloes, Sec. 4.3; no data set is used, so none is needed):
                  Eq. NFW (Sec. 4.3), truncated at x = 5, with scale radius
                  lognormal about 0.5 arcmin (sigma_ln = 0.5); the other 30%
                  uniform.  Masses exp(0.3 g), g ~ N(0, 1).
+* ``nfw_halo``   one projected NFW halo (Eq. NFW) at the north pole, for the
+                 sampling-noise experiment of Sec. 4.3.
 """
 from __future__ import annotations
 
@@ -127,6 +129,25 @@ def clustered(n: int, rng: np.random.Generator, n_clumps: int = 2000,
     pts_in = np.cos(r) * c + np.sin(r) * (np.cos(az) * e1 + np.sin(az) * e2)
     pts = np.concatenate([_normalise(pts_in), uniform(n - n_in, rng)], axis=1)
     return _normalise(pts[:, rng.permutation(n)])
+
+
+def nfw_halo(n: int, rng: np.random.Generator, kappa_s: float = 0.338, r_s: float = 0.3, c: float = 5.05):
+    """A test halo of Sec. 4.3 at the north pole: n equal masses whose
+    density follows the projected NFW profile of Eq. NFW (amplitude kappa_s,
+    scale r_s, truncated at x = c), laid on the sphere by the equal-area
+    radius r = 2 sin(theta / 2) (the sphere's area element is 2 pi r dr, so
+    the flat profile's mass in every ring is kept).  Radii by inverse CDF of
+    the enclosed profile, azimuths uniform.  Returns (src (3, n), q (n,)),
+    the masses summing to the halo's 2 pi kappa_s r_s^2 int_0^c x f(x) dx."""
+    n = int(n)
+    x = _nfw_radii(n, rng, xmax=c)
+    theta = 2.0 * np.arcsin(np.minimum(1.0, 0.5 * x * r_s))
+    phi = rng.uniform(0.0, 2.0 * np.pi, n)
+    st = np.sin(theta)
+    src = _normalise(np.stack([st * np.cos(phi), st * np.sin(phi), np.cos(theta)]))
+    # _nfw_enclosed(x) = (1/4) int_0^x x' f(x') dx' (it vanishes at x = 0)
+    total = 2.0 * np.pi * kappa_s * r_s * r_s * 4.0 * float(_nfw_enclosed(np.array([c]))[0])
+    return src, np.full(n, total / n)
 
 
 def masses_lognormal(n: int, rng: np.random.Generator, sigma: float = 0.3) -> np.ndarray:

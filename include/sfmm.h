@@ -107,7 +107,7 @@ typedef struct {
                                   sums (0 = 128); 8..4096                     */
     int32_t far_segment;       /* the same for the multipole evaluations     */
     int32_t judge_targets;     /* per-pair order policies: targets of the
-                                  judge's direct sum (0 = 64; < 0: no judge);
+                                  judge's direct sum (0 = 32; < 0: no judge);
                                   at most 4096                               */
     int32_t no_fallback;       /* nonzero: a failed judge returns
                                   SFMM_ERR_TOLERANCE_NOT_MET instead of

@@ -348,20 +348,20 @@ SFMM_HD void translate_emit(const In& in, const TransGeom& G, const Out& out) {
     out(1, Q);
 }
 
-// Lemma 1 for a set of particles about centre f with scale rho; C carries the
-// zero-mean gauge's share sum q / (4 pi) (Eq. STAND_CONDITION).
-// The precision tier's Lemma 3 translation: the A-block (scaled, FP32, A[2l-2]
-// = Re A_l, A[2l-1] = Im A_l) goes through the same factorised map in FP32
-// and is added to the FP32 accumulator acc[2P]; C and Q stay FP64 (accCQ).
-// The pair geometry G is computed in FP64 and rounded once.
+// FP32 complex numbers for the precision tier's translation (below).
 struct cplxf {
     float re, im;
 };
 SFMM_HD cplxf cmulf(cplxf a, cplxf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
+// The precision tier's Lemma 3 translation: the FP32 A-block (scaled,
+// A[2l-2] = Re A_l, A[2l-1] = Im A_l) through the factorised map in FP32,
+// with the pair geometry G computed in FP64 and rounded once; the results
+// are added to acc[2P] in FP64, so the sum over an FMM-act list carries no
+// FP32 rounding, and C and Q stay FP64 (accCQ).
 template <int P>
-SFMM_HD void translate_add_f32(const float* __restrict__ A, double C, double Q, const TransGeom& G, float* acc,
-                               double* accCQ) {
+SFMM_HD void translate_add_f32_d(const float* __restrict__ A, double C, double Q, const TransGeom& G, double* acc,
+                                 double* accCQ) {
     float ar[P + 1], ai[P + 1];
     ar[0] = 0.0f;
     ai[0] = 0.0f;
@@ -406,8 +406,8 @@ SFMM_HD void translate_add_f32(const float* __restrict__ A, double C, double Q, 
     for (int l = 1; l <= P; ++l) {
         const cplxf v = {ar[l] - qf * (1.0f / l) * an, ai[l]};
         const cplxf o = cmulf(pw2, v);
-        acc[2 * l - 2] += o.re;
-        acc[2 * l - 1] += o.im;
+        acc[2 * l - 2] += (double)o.re;
+        acc[2 * l - 1] += (double)o.im;
         pw2 = cmulf(pw2, ph2);
         an *= a;
     }
@@ -415,6 +415,8 @@ SFMM_HD void translate_add_f32(const float* __restrict__ A, double C, double Q, 
     accCQ[1] += Q;
 }
 
+// Lemma 1 for a set of particles about centre f with scale rho; C carries the
+// zero-mean gauge's share sum q / (4 pi) (Eq. STAND_CONDITION).
 template <int P>
 struct P2MAcc {
     double sre[P], sim[P];

@@ -170,49 +170,49 @@ __global__ void k_mult_to_f32(const double* __restrict__ mult, int p, int nb, fl
     out[i] = (float)mult[b * (2 * p + 2) + 2 + k];
 }
 
-// Precision tier Lemma 3: the lists as in k_m2l, FP32 A-blocks (multf,
-// [nb][2 c.p]) and FP32 translation arithmetic, FP64 C and Q; the local
-// record is written in FP64.  P and acc_in as in k_m2l.
+// Precision tier Lemma 3 with four lanes per target box, as k_m2l_team: in
+// each round lane r of the team translates entry k0 + 4 round + r of the
+// box's list.  The translation runs in FP32 on the FP32 A-block copy
+// (multf); each lane adds its results into FP64 running sums held in
+// registers (the FP32 working vector leaves room for them), and at the end
+// the team's four sums of every entry are added by two DPP lane exchanges
+// and written by the lane that owns the entry (entry k by lane k mod 4).
+// C and Q stay FP64.  P and acc_in as in k_m2l_team.
 template <int P>
-__global__ void __launch_bounds__(128) k_m2l_f32(FmmCtx c, const float* __restrict__ multf, const int* order, int n,
-                                                const int* off, const int* src, bool acc_in) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void __launch_bounds__(128) k_m2l_team_f32(FmmCtx c, const float* __restrict__ multf, const int* order,
+                                                     int n, const int* off, const int* src, bool acc_in) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid >> 2, r = gid & 3;
+    if (i >= n) return;  // the four lanes of a team leave together
     const int t = order ? order[i] : i;
     const int k0 = off[t], k1 = off[t + 1];
     const size_t ew = 2 * (size_t)c.p + 2, fw = 2 * (size_t)c.p;
-    if (k0 == k1) {  // nothing to add; a first pass still writes the record
+    double* out = c.local + (size_t)t * ew;
+    if (k0 == k1) {
         if (!acc_in)
-            for (size_t k = 0; k < ew; ++k) c.local[(size_t)t * ew + k] = 0.0;
+            for (size_t k = r; k < ew; k += 4) out[k] = 0.0;
         return;
     }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
-    double* out = c.local + (size_t)t * ew;
-    float acc[2 * P];
+    double acc[2 * P + 2];  // C, Q, then the A-block
 #pragma unroll
-    for (int k = 0; k < 2 * P; ++k) acc[k] = 0.0f;
-    double cq[2] = {0.0, 0.0};
-    for (int k = k0; k < k1; ++k) {
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
+    for (int k = k0 + r; k < k1; k += 4) {
         const int s = src[k];
         double rho_s;
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
         const double* e = c.mult + (size_t)s * ew;
-        translate_add_f32<P>(multf + (size_t)s * fw, e[0], e[1], G, acc, cq);
+        translate_add_f32_d<P>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
     }
-    if (acc_in) {
-        out[0] += cq[0];
-        out[1] += cq[1];
 #pragma unroll
-        for (int k = 0; k < 2 * P; ++k) out[2 + k] += (double)acc[k];
-    } else {
-        out[0] = cq[0];
-        out[1] = cq[1];
-#pragma unroll
-        for (int k = 0; k < 2 * P; ++k) out[2 + k] = (double)acc[k];
-        for (size_t k = 2 * P + 2; k < ew; ++k) out[k] = 0.0;  // a first pass below the record order
+    for (int k = 0; k < 2 * P + 2; ++k) {
+        const double v = quad_sum(acc[k]);
+        if ((k & 3) == r) out[k] = acc_in ? out[k] + v : v;
     }
+    if (!acc_in)
+        for (size_t k = 2 * P + 2 + r; k < ew; k += 4) out[k] = 0.0;  // a first pass below the record order
 }
 
 // Lemma 4: every box of one level takes its parent's local expansion
@@ -318,7 +318,10 @@ void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const 
                  const int* src, hipStream_t s) {
     if (n <= 0) return;
     if (p < 1 || p > c.p) throw Error(ST_INTERNAL, "M2L order above the record order");
-#define L_(P) case P: k_m2l_f32<P><<<nblk(n, 128), 128, 0, s>>>(c, multf, order, n, off, src, acc_in); break;
+#define L_(P)                                                                                                  \
+    case P:                                                                                                    \
+        k_m2l_team_f32<P><<<nblk(4 * (int64_t)n, 128), 128, 0, s>>>(c, multf, order, n, off, src, acc_in);   \
+        break;
     SFMM_DISPATCH(p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();

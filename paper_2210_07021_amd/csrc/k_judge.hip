@@ -7,13 +7,14 @@
 // relative L2 error of psi or alpha exceeds the tolerance.
 //
 // Layout: each workgroup takes a chunk of kJudgeChunk sorted sources, staged
-// through LDS 256 at a time; a target is owned by kJudgeLanes threads that
-// split the chunk's sources; per chunk and target the four sums (psi, alpha
-// x, y, z) are Neumaier-compensated, combined over the lanes, and written as
-// (sum, compensation) pairs.  A second kernel adds the chunks in chunk order
-// in double-double, so the result is exact to rounding of the final sum and
-// bitwise reproducible.  The log and reciprocal are the library's own
-// (log_f64: ~2 ulp), far below the tolerances the judge checks.
+// through LDS 256 at a time; a target is owned by `lanes` threads (256 over
+// the targets per pass, at least 4) that split the chunk's sources; per chunk
+// and target the four sums (psi, alpha x, y, z) are Neumaier-compensated,
+// combined over the lanes, and written as (sum, compensation) pairs.  A
+// second kernel adds the chunks in double-double in a fixed order, so the
+// result is exact to rounding of the final sum and bitwise reproducible.  The
+// log and reciprocal are the library's own (log_f64: ~2 ulp), far below the
+// tolerances the judge checks.
 #include "common.hpp"
 #include "expand.hpp"
 
@@ -36,20 +37,19 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 }
 
 // part [nchunk][S][8]: (psi, c, ax, c, ay, c, az, c) of chunk j for target t.
-// Thread (target t, lane r of kJudgeLanes) takes sources r, r + kJudgeLanes,
-// ... of the chunk, so all threads work whatever S; the lanes' compensated
-// sums of a target are then combined in lane order (deterministic).
-constexpr int kJudgeLanes = 4;
+// Thread (target t, lane r of `lanes`) takes sources r, r + lanes, ... of the
+// chunk, so all threads work whatever S; the lanes' compensated sums of a
+// target are then combined in lane order (deterministic).
 __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* __restrict__ spt, int n,
                                                                  const double4* __restrict__ tsel, int S,
-                                                                 double* __restrict__ part) {
+                                                                 int lanes, double* __restrict__ part) {
     __shared__ double4 tile[kJudgeThreads];
     __shared__ double red[kJudgeThreads][8];
-    constexpr int TPB = kJudgeThreads / kJudgeLanes;  // targets per pass
+    const int tpb = kJudgeThreads / lanes;  // targets per pass
     const int j = blockIdx.x;
     const int s0 = j * kJudgeChunk, s1 = min(n, s0 + kJudgeChunk);
-    const int tl = threadIdx.x / kJudgeLanes, r = threadIdx.x % kJudgeLanes;
-    for (int t0 = 0; t0 < S; t0 += TPB) {
+    const int tl = threadIdx.x / lanes, r = threadIdx.x % lanes;
+    for (int t0 = 0; t0 < S; t0 += tpb) {
         const int t = t0 + tl;
         const double4 tp = t < S ? tsel[t] : make_double4(1.0, 0.0, 0.0, 0.0);
         double sp = 0, cp = 0, sx = 0, cx = 0, sy = 0, cy = 0, sz = 0, cz = 0;
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* _
             if (b + threadIdx.x < s1) tile[threadIdx.x] = spt[b + threadIdx.x];
             __syncthreads();
             const int nb = min(kJudgeThreads, s1 - b);
-            for (int k = r; k < nb; k += kJudgeLanes) {
+            for (int k = r; k < nb; k += lanes) {
                 const double4 sr = tile[k];
                 const double dx = tp.x - sr.x, dy = tp.y - sr.y, dz = tp.z - sr.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* _
             double o[8];
             for (int q = 0; q < 4; ++q) {  // lane 0's sum, then lanes 1.. added in order (two-sum)
                 double hi = red[threadIdx.x][2 * q], lo = red[threadIdx.x][2 * q + 1];
-                for (int l = 1; l < kJudgeLanes; ++l) {
+                for (int l = 1; l < lanes; ++l) {
                     double sum, e;
                     two_sum(hi, red[threadIdx.x + l][2 * q], sum, e);
                     lo += e + red[threadIdx.x + l][2 * q + 1];
@@ -94,21 +94,42 @@ __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* _
 }
 
 // out [S][4]: psi (+ shift) and the tangent projection of alpha, from the
-// chunk sums added in chunk order in double-double
-__global__ void k_judge_finish(const double* __restrict__ part, int nchunk, const double4* __restrict__ tsel, int S,
-                               double shift, double* __restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= S) return;
+// chunk sums in double-double: one 64-lane workgroup per target, lane l
+// adding chunks l, l + 64, ... in order, then the lanes' double-double sums
+// combined in a fixed butterfly order (bitwise reproducible).
+__device__ __forceinline__ void dd_add_into(double& hi, double& lo, double h2, double l2) {
+    double s, e;
+    two_sum(hi, h2, s, e);
+    lo += e + l2;
+    hi = s;
+}
+
+__global__ void __launch_bounds__(64) k_judge_finish(const double* __restrict__ part, int nchunk,
+                                                     const double4* __restrict__ tsel, int S, double shift,
+                                                     double* __restrict__ out) {
+    const int t = blockIdx.x, lane = threadIdx.x;
     double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
-    for (int j = 0; j < nchunk; ++j) {
+    for (int j = lane; j < nchunk; j += 64) {
         const double* o = part + ((size_t)j * S + t) * 8;
-        for (int k = 0; k < 4; ++k) {
-            double s, e;
-            two_sum(hi[k], o[2 * k], s, e);
-            lo[k] += e + o[2 * k + 1];
-            hi[k] = s;
-        }
+        for (int k = 0; k < 4; ++k) dd_add_into(hi[k], lo[k], o[2 * k], o[2 * k + 1]);
     }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1)
+        for (int k = 0; k < 4; ++k) {
+            const double h2 = __shfl_xor(hi[k], m, 64), l2 = __shfl_xor(lo[k], m, 64);
+            // both lanes of a pair add the same two values in the same order
+            double a = hi[k], b = lo[k], c2 = h2, d2 = l2;
+            if (lane & m) {
+                a = h2;
+                b = l2;
+                c2 = hi[k];
+                d2 = lo[k];
+            }
+            dd_add_into(a, b, c2, d2);
+            hi[k] = a;
+            lo[k] = b;
+        }
+    if (lane != 0) return;
     double v[4];
     for (int k = 0; k < 4; ++k) v[k] = hi[k] + lo[k];
     const double4 tp = tsel[t];
@@ -151,12 +172,14 @@ void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const do
     SFMM_LAUNCH_CHECK();
     const int nchunk = (int)std::max<int64_t>((n + kJudgeChunk - 1) / kJudgeChunk, 1);
     if (n > 0) {
-        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, part);
+        int tpb = 64;  // targets per pass: the smallest power of two >= S, at most 64
+        while (tpb > 1 && tpb / 2 >= S) tpb /= 2;
+        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, kJudgeThreads / tpb, part);
         SFMM_LAUNCH_CHECK();
     } else {
         fill_f64(part, (size_t)S * 8, 0.0, s);
     }
-    k_judge_finish<<<(S + 255) / 256, 256, 0, s>>>(part, nchunk, tsel, S, shift, ref);
+    k_judge_finish<<<S, 64, 0, s>>>(part, nchunk, tsel, S, shift, ref);
     SFMM_LAUNCH_CHECK();
 }
 

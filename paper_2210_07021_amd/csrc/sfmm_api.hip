@@ -818,7 +818,7 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
     prof.flush();
 }
 
-constexpr int kJudgeDefault = 64;
+constexpr int kJudgeDefault = 32;
 
 // The judge: psi and alpha of the last execute at S seeded targets against
 // their direct sum; sets P.judge_psi / judge_alpha (relative L2 errors).

@@ -339,6 +339,24 @@ sfmm_status sfmm_mlp_forward(const float* weights, const float* features, int64_
 sfmm_status sfmm_mlp_grad(const float* weights, const float* features, const float* labels, int64_t n,
                           float* grad, float* loss);
 
+/* Global-basis helpers (Sec. 3.6: the global components of the deflection
+ * follow from its tangent vector by a change of coordinates).  Host buffers,
+ * host arithmetic; no device work.
+ * sfmm_thetaphi_to_xyz: xyz [3][n] = (sin t cos p, sin t sin p, cos t) for
+ *   colatitudes theta [n] and longitudes phi [n] (radians): the unit vectors
+ *   that sfmm_plan takes.
+ * sfmm_defl_to_thetaphi: out [2][n] = (alpha_theta, alpha_phi), the
+ *   components of the tangent vectors defl [3][n] (as sfmm_execute writes
+ *   them) at the unit vectors xyz [3][n] in the local basis e_theta = (cos t
+ *   cos p, cos t sin p, -sin t), e_phi = (-sin p, cos p, 0), so that
+ *   alpha_theta = d psi/d theta and alpha_phi = (1/sin t) d psi/d phi.  At an
+ *   exact pole (x = y = 0) the basis is its limit along the meridian phi[i];
+ *   phi may be NULL (then phi = 0 there).
+ * Errors: SFMM_ERR_INVALID_ARG for n < 0 or NULL buffers with n > 0. */
+sfmm_status sfmm_thetaphi_to_xyz(const double* theta, const double* phi, int64_t n, double* xyz);
+sfmm_status sfmm_defl_to_thetaphi(const double* xyz, const double* defl, const double* phi, int64_t n,
+                                  double* out);
+
 void sfmm_destroy(sfmm_plan_t plan);
 const char* sfmm_status_string(sfmm_status s);
 const char* sfmm_last_error(void);

@@ -96,6 +96,8 @@ SIGNATURES = {
     "sfmm_execute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "sfmm_execute_hessian": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sfmm_lensing": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "sfmm_thetaphi_to_xyz": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "sfmm_defl_to_thetaphi": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
     "sfmm_raytrace": (ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _I64, _P, ctypes.POINTER(Options), _P]),
     "sfmm_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "sfmm_export_boxes": (ctypes.c_int, [_P] * 9),
@@ -230,6 +232,41 @@ def lensing(hess, stream=None):
     out = torch.empty((4, m), dtype=torch.float64, device=hess.device)
     _check(load_library().sfmm_lensing(ctypes.c_void_p(hess.data_ptr() if m else 0), m,
                                        ctypes.c_void_p(out.data_ptr() if m else 0), _stream_handle(stream)))
+    return out
+
+
+def _host_f64(a, shape0=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape0 is not None and (a.ndim != 2 or a.shape[0] != shape0):
+        raise ValueError(f"expected an array of shape ({shape0}, n)")
+    return a
+
+
+def thetaphi_to_xyz(theta, phi):
+    """Unit vectors (3, n) of colatitudes and longitudes (radians), host numpy
+    (sfmm_thetaphi_to_xyz)."""
+    t, f = _host_f64(theta).ravel(), _host_f64(phi).ravel()
+    if t.shape != f.shape:
+        raise ValueError("theta and phi differ in length")
+    out = np.empty((3, t.size))
+    _check(load_library().sfmm_thetaphi_to_xyz(t.ctypes.data, f.ctypes.data, t.size, out.ctypes.data))
+    return out
+
+
+def defl_to_thetaphi(xyz, defl, phi=None):
+    """(alpha_theta, alpha_phi) (2, n) of tangent vectors defl (3, n) at unit
+    vectors xyz (3, n), host numpy; phi (n,) fixes the basis at exact poles
+    (sfmm_defl_to_thetaphi)."""
+    x, d = _host_f64(xyz, 3), _host_f64(defl, 3)
+    if x.shape != d.shape:
+        raise ValueError("xyz and defl differ in shape")
+    n = x.shape[1]
+    f = None if phi is None else _host_f64(phi).ravel()
+    if f is not None and f.size != n:
+        raise ValueError("phi has the wrong length")
+    out = np.empty((2, n))
+    _check(load_library().sfmm_defl_to_thetaphi(x.ctypes.data, d.ctypes.data, None if f is None else f.ctypes.data,
+                                                 n, out.ctypes.data))
     return out
 
 

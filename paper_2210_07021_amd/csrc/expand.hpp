@@ -51,8 +51,13 @@ SFMM_HD double recip(double x) {
 // Natural log of a positive normal double, ~2 ulp: x = 2^e m with
 // m in [1/sqrt2, sqrt2), s = (m - 1)/(m + 1), and
 //   log m = 2 atanh s = 2 s (1 + s^2/3 + s^4/5 + ... + s^20/21),
-// whose first omitted term is below 3e-17 relative since s^2 <= 0.0295;
-// e log 2 is added with log 2 split in two words.  Written for the
+// whose first omitted term is below 3e-17 relative since s^2 <= 0.0295
+// (the reduction of fdlibm's e_log.c, here with the Taylor coefficients of
+// atanh instead of its minimax polynomial).  e log 2 is added with the
+// Cody-Waite two-word split of log 2 that fdlibm's e_log.c uses (Sun
+// Microsystems, freely distributable): ln2_hi keeps 32 significant bits, so
+// e ln2_hi is exact for every exponent of a double, and ln2_lo = log 2 -
+// ln2_hi to double precision.  Written for the
 // near-field inner loop, where the library log (a double-double algorithm
 // of ~85 instructions) dominated the cost.
 SFMM_HD double log_f64(double x) {
@@ -85,7 +90,9 @@ SFMM_HD double log_f64(double x) {
 }
 
 // The pair loop's log and reciprocal with a table in place of the atanh
-// series: x = 2^e m, m in [1/2, 1); the top 7 fraction bits of m pick c_j =
+// series (the table-driven method of P. T. P. Tang, ACM TOMS 16 (1990)
+// 378-400, with a smaller table and a longer polynomial):
+// x = 2^e m, m in [1/2, 1); the top 7 fraction bits of m pick c_j =
 // 1/2 + (j + 1/2)/256 and tab[j] = {1/c_j, -log(1/c_j)} (log_tab_entry), so
 // that r = m/c_j - 1 (one FMA) has |r| < 2^-8 and
 //   log x = e log 2 - log(1/c_j) + log(1 + r),
@@ -120,7 +127,7 @@ SFMM_HD void log_recip_tab(double x, const double2* tab, const LogPoly& k, doubl
     q = fma(q, r, -0.5);
     const double lp = fma(r * r, q, r);
     const double de = (double)e;
-    *lg = fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, t.y + lp));
+    *lg = fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, t.y + lp));  // log_f64's split
     *inv = recip(x);
 }
 

@@ -1609,6 +1609,49 @@ void sfmm_destroy(sfmm_plan_t plan) {
     delete plan;
 }
 
+// Global-basis helpers (Sec. 3.6): host arithmetic only, no device work.
+sfmm_status sfmm_thetaphi_to_xyz(const double* theta, const double* phi, int64_t n, double* xyz) {
+    if (n < 0 || (n > 0 && (!theta || !phi || !xyz))) {
+        g_last_error = "thetaphi_to_xyz: n < 0 or a NULL buffer";
+        return SFMM_ERR_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const double st = std::sin(theta[i]);
+        xyz[i] = st * std::cos(phi[i]);
+        xyz[n + i] = st * std::sin(phi[i]);
+        xyz[2 * n + i] = std::cos(theta[i]);
+    }
+    return SFMM_OK;
+}
+
+sfmm_status sfmm_defl_to_thetaphi(const double* xyz, const double* defl, const double* phi, int64_t n,
+                                  double* out) {
+    if (n < 0 || (n > 0 && (!xyz || !defl || !out))) {
+        g_last_error = "defl_to_thetaphi: n < 0 or a NULL buffer";
+        return SFMM_ERR_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+        const double ax = defl[i], ay = defl[n + i], az = defl[2 * n + i];
+        const double rho = std::hypot(x, y);
+        double et[3], ep[3];
+        if (rho > 0.0) {
+            const double c = x / rho, s = y / rho, ct = z / std::sqrt(rho * rho + z * z);
+            const double st = rho / std::sqrt(rho * rho + z * z);
+            et[0] = ct * c; et[1] = ct * s; et[2] = -st;
+            ep[0] = -s; ep[1] = c; ep[2] = 0.0;
+        } else {  // exact pole: the limit along the meridian phi
+            const double f = phi ? phi[i] : 0.0, c = std::cos(f), s = std::sin(f);
+            const double sg = z < 0.0 ? -1.0 : 1.0;
+            et[0] = sg * c; et[1] = sg * s; et[2] = 0.0;
+            ep[0] = -s; ep[1] = c; ep[2] = 0.0;
+        }
+        out[i] = ax * et[0] + ay * et[1] + az * et[2];
+        out[n + i] = ax * ep[0] + ay * ep[1] + az * ep[2];
+    }
+    return SFMM_OK;
+}
+
 const char* sfmm_status_string(sfmm_status s) {
     switch (s) {
         case SFMM_OK: return "ok";

@@ -101,11 +101,17 @@ def main():
     ap.add_argument("--accuracy-targets", type=int, default=10000,
                     help="size of the seeded target subset the oracle checks (untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-tier (FP32 mixed) leg")
+    ap.add_argument("--no-fp32", action="store_true", help="only the FP64 leg (same as --legs fp64)")
+    ap.add_argument("--legs", default="fp64,fp32_mixed,fp32_learned",
+                    help="comma list of fp64 (the headline), fp32_mixed (fixed order), fp32_bound, "
+                         "fp32_learned; the first one fills the top-level fields")
     ap.add_argument("--fp32-tolerance", type=float, default=1e-6)
     ap.add_argument("--shells", type=int, default=0,
                     help="measure the batched form instead: this many lensing shells (N_s log-uniform in "
                          "[1e5, 5e6], 786,432 grid targets each) in one recorded graph")
+    ap.add_argument("--shells-leg", type=int, default=40,
+                    help="after the main legs, the batched form on this many shells in FP64 (tolerance) and the "
+                         "precision tier (fp32 tolerance), reported under 'shells' (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (scale for the traffic counters) and exit")
     args = ap.parse_args()
@@ -130,7 +136,8 @@ def main():
 
     sf.load_library()
     if args.shells > 0:
-        return bench_shells(args, sf, skies, torch)
+        print(json.dumps(bench_shells(args, sf, skies, torch, args.shells, args.tolerance, 0)), flush=True)
+        return
     torch.cuda.set_device(0)
     log(f"[bench] generating {args.workload} (scale {args.scale})")
     t = time.time()
@@ -181,50 +188,80 @@ def main():
         log(f"[bench] {label}: {args.steps} steps in {t1 - t0:.3f}s")
         return t1 - t0, {k: v[0] / args.steps for k, v in prof.items()}, stats
 
-    elapsed, stages_ms, stats = run(opts, psi, defl, "fp64")
-    legs = {}
-    if not args.no_fp32:
-        # the precision tier at its own tolerance, same workload; then the same
-        # with the learned per-interaction order (network trained untimed on
-        # labels of the clustered 1e6 sky, a different sky and seed)
-        outs = {}
-        for leg, extra in (("fp32_mixed", {}), ("fp32_learned", "learned")):
-            opts32 = dict(leaf_size=args.leaf_size, tolerance=args.fp32_tolerance, precision=sf.SFMM_FP32_MIXED)
-            if extra == "learned":
+    legs_req = ["fp64"] if args.no_fp32 else [x for x in args.legs.split(",") if x]
+    bad = set(legs_req) - {"fp64", "fp32_mixed", "fp32_bound", "fp32_learned"}
+    if bad or not legs_req:
+        raise SystemExit(f"unknown legs {sorted(bad)}")
+    legs, outs = {}, {}
+    for leg in legs_req:
+        if leg == "fp64":
+            o, po, do = opts, psi, defl
+        else:
+            # the precision tier at its own tolerance, same workload; the
+            # learned per-interaction order uses a network trained (untimed)
+            # on labels of the clustered 1e6 sky, a different sky and seed
+            o = dict(leaf_size=args.leaf_size, tolerance=args.fp32_tolerance, precision=sf.SFMM_FP32_MIXED)
+            if leg == "fp32_bound":
+                o["order_policy"] = sf.SFMM_ORDER_BOUND
+            if leg == "fp32_learned":
                 from paper_2210_07021_amd import learn
                 t = time.time()
                 f_tr, l_tr = learn.order_training_data([skies.workload("clustered-1e6")], args.fp32_tolerance,
                                                        leaf_size=args.leaf_size, samples_per_sky=60000, seed=1)
                 w_net, _ = learn.train_order_network(f_tr, l_tr, epochs=30)
                 log(f"[bench] order network trained in {time.time() - t:.1f}s (untimed)")
-                opts32.update(order_policy=sf.SFMM_ORDER_LEARNED, mlp_weights=w_net)
-            p32 = torch.empty_like(psi)
-            d32 = torch.empty_like(defl)
-            e32, st32, s32 = run(opts32, p32, d32, leg)
-            outs[leg] = (p32, d32)
-            legs[leg] = {"value": M * args.steps / e32, "unit": "targets/s", "ms_per_step": 1e3 * e32 / args.steps,
-                         "tolerance": args.fp32_tolerance, "order": s32["order"], "dtype": "f32+f64",
-                         "m2l_work_vs_fixed": s32["m2l_order_sq"] / max(1, s32["n_m2l"] * s32["order"] ** 2),
-                         "stages_ms": {k: round(v, 4) for k, v in st32.items()}}
-            if extra == "learned":
-                legs[leg]["judge"] = {"targets": s32["judge_targets"], "psi_rel_l2": s32["judge_psi"],
-                                      "alpha_rel_l2": s32["judge_alpha"], "fell_back": bool(s32["fell_back"])}
+                o.update(order_policy=sf.SFMM_ORDER_LEARNED, mlp_weights=w_net)
+            po, do = torch.empty_like(psi), torch.empty_like(defl)
+        e, st, s_ = run(o, po, do, leg)
+        outs[leg] = (po, do)
+        rec = {"value": M * args.steps / e, "unit": "targets/s", "ms_per_step": 1e3 * e / args.steps,
+               "tolerance": args.tolerance if leg == "fp64" else args.fp32_tolerance, "order": s_["order"],
+               "dtype": "f64" if leg == "fp64" else "f32+f64",
+               "m2l_work_vs_fixed": s_["m2l_order_sq"] / max(1, s_["n_m2l"] * s_["order"] ** 2),
+               "stages_ms": {k: round(v, 4) for k, v in st.items()}, "_elapsed": e, "_stats": s_}
+        if leg in ("fp32_bound", "fp32_learned"):
+            rec["judge"] = {"targets": s_["judge_targets"], "psi_rel_l2": s_["judge_psi"],
+                            "alpha_rel_l2": s_["judge_alpha"], "fell_back": bool(s_["fell_back"])}
+        legs[leg] = rec
+    main_leg = legs_req[0]
+    elapsed, stats = legs[main_leg].pop("_elapsed"), legs[main_leg].pop("_stats")
+    stages_ms = legs[main_leg]["stages_ms"]
+    for leg in legs_req[1:]:
+        legs[leg].pop("_elapsed")
+        legs[leg].pop("_stats")
+    psi, defl = outs[main_leg]
 
     p = stats["order"]
-    work = {
-        "m2l": ("alu", stats["n_m2l"] * m2l_flops(p), PEAK_FP64_TFLOPS, "TFLOP/s"),
-        "p2p": ("alu", stats["n_p2p_pairs"] * FLOP_PER_P2P_PAIR, PEAK_FP64_TFLOPS, "TFLOP/s"),
-        "m2p": ("alu", stats["n_m2p_evals"] * m2p_flops(p), PEAK_FP64_TFLOPS, "TFLOP/s"),
-    }
-    dom = max(work, key=lambda k: stages_ms[k])
-    bound, flops, peak, unit = work[dom]
-    achieved = flops / (stages_ms[dom] * 1e-3) / 1e12
-    roofline = {"kernel": KERNEL_NAMES[dom], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
-                "work_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
+    roofline, kernels = None, None
+    if main_leg == "fp64":
+        work = {
+            "m2l": ("alu", stats["n_m2l"] * m2l_flops(p), PEAK_FP64_TFLOPS, "TFLOP/s"),
+            "p2p": ("alu", stats["n_p2p_pairs"] * FLOP_PER_P2P_PAIR, PEAK_FP64_TFLOPS, "TFLOP/s"),
+            "m2p": ("alu", stats["n_m2p_evals"] * m2p_flops(p), PEAK_FP64_TFLOPS, "TFLOP/s"),
+        }
+        dom = max(work, key=lambda k: stages_ms[k])
+        bound, flops, peak, unit = work[dom]
+        achieved = flops / (stages_ms[dom] * 1e-3) / 1e12
+        roofline = {"kernel": KERNEL_NAMES[dom], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                    "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
+                    "work_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
+        # every timed FMM kernel against its own roofline (stage time from the
+        # library's HIP events; L2P by its algorithmic bytes: coordinates in,
+        # psi and alpha out, each target leaf's local record once)
+        kernels = {}
+        for k, (bd, w, pk, u) in work.items():
+            a_ = w / (stages_ms[k] * 1e-3) / 1e12
+            kernels[k] = {"bound": bd, "achieved": round(a_, 3), "peak": pk, "unit": u, "frac": round(a_ / pk, 4),
+                          "ms": stages_ms[k]}
+        l2p_bytes = M * 56 + stats["n_target_leaves"] * (2 * p + 2) * 8
+        a_ = l2p_bytes / (stages_ms["l2p"] * 1e-3) / 1e9
+        kernels["l2p"] = {"bound": "hbm", "achieved": round(a_, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(a_ / PEAK_HBM_GBS, 4), "ms": stages_ms["l2p"]}
 
     result = {
-        "metric": "targets/s (psi+deflection) at 1e-10 rel err, N=1e7",
+        "metric": ("targets/s (psi+deflection) at 1e-10 rel err, N=1e7"
+                   if (args.workload, legs_req[0], args.tolerance) == ("clustered-1e7", "fp64", 1e-10) else
+                   f"targets/s (psi+deflection) at {legs[main_leg]['tolerance']:g} rel err, {args.workload}"),
         "value": M * args.steps / elapsed,
         "unit": "targets/s",
         "n_gpus": 1,
@@ -234,17 +271,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": legs[main_leg]["dtype"],
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "M": M,
-                   "tolerance": None if args.order > 0 else args.tolerance, "order": p,
-                   "leaf_size": args.leaf_size, "precision": "fp64", "c_s": 2.0, "c_t": 0.5,
+                   "tolerance": None if (args.order > 0 and main_leg == "fp64") else legs[main_leg]["tolerance"],
+                   "order": p, "leaf_size": args.leaf_size,
+                   "precision": "fp64" if main_leg == "fp64" else "fp32_mixed", "c_s": 2.0, "c_t": 0.5,
                    "n_boxes": stats["n_boxes"], "n_m2l": stats["n_m2l"], "n_p2p_pairs": stats["n_p2p_pairs"],
                    "n_m2p_evals": stats["n_m2p_evals"]},
         "stages_ms": {k: round(v, 4) for k, v in stages_ms.items()},
         "roofline": roofline,
+        "kernels": kernels,
     }
-    result.update(legs)
+    if main_leg != "fp64":
+        result["leg"] = main_leg
+    result.update({k: v for k, v in legs.items() if k != main_leg})
 
     if not args.no_cpu_baseline:
         import oracle
@@ -255,10 +296,17 @@ def main():
         # are the CPU baseline (a bounded sample of about cpu_seconds)
         sub = np.random.default_rng(skies.BASE_SEED + 1001).choice(M, size=min(M, args.accuracy_targets),
                                                                   replace=False)
+        # per-target cost from two probes (each call also pays a fixed set-up
+        # of about a copy of the sources, which the difference removes)
+        oracle.direct(src_h, q_h, tgt_h[:, sub[:8]])  # thread start-up
         t = time.perf_counter()
-        oracle.direct(src_h, q_h, tgt_h[:, sub[:8]])  # thread start-up and a rate probe
-        t_probe = time.perf_counter() - t
-        k = int(min(len(sub), max(8, 8 * args.cpu_seconds / max(t_probe, 1e-6))))
+        oracle.direct(src_h, q_h, tgt_h[:, sub[:16]])
+        t16 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.direct(src_h, q_h, tgt_h[:, sub[:80]])
+        t80 = time.perf_counter() - t
+        per_target = max((t80 - t16) / 64, t80 / 80 * 0.05, 1e-9)
+        k = int(min(len(sub), max(80, args.cpu_seconds / per_target)))
         log(f"[bench] cpu baseline: oracle on {k} of the {len(sub)} seeded targets")
         t = time.perf_counter()
         ref_p1, ref_a1 = oracle.direct(src_h, q_h, tgt_h[:, sub[:k]])
@@ -286,26 +334,41 @@ def main():
                     "alpha_worst_target": float(da.max() / rms_a), "targets": int(len(sub))}
 
         result["accuracy"] = accuracy(psi_h, defl_h)
-        for leg, (p32, d32) in (outs.items() if legs else []):
-            legs[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
+        for leg in legs_req[1:]:
+            p32, d32 = outs[leg]
+            result[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
+    if args.shells_leg > 0 and legs_req[0] == "fp64":
+        del src, q, tgt, psi, defl, outs
+        torch.cuda.empty_cache()
+        sh = {}
+        for name, tol, prec in (("fp64", args.tolerance, sf.SFMM_FP64),
+                                ("fp32_mixed", args.fp32_tolerance, sf.SFMM_FP32_MIXED)):
+            r = bench_shells(args, sf, skies, torch, args.shells_leg, tol, prec)
+            sh[name] = {k: r[k] for k in ("value", "ms_per_step", "plan_ms", "execute_graph_ms", "execute_direct_ms",
+                                         "execute_targets_per_s_graph")}
+            sh[name]["tolerance"] = tol
+            sh[name]["options"] = r["config"]["options"]
+        sh["config"] = {"workload": f"shells-{args.shells_leg}", "N": r["config"]["N"], "M": r["config"]["M"]}
+        result["shells"] = sh
     print(json.dumps(result), flush=True)
 
 
-def bench_shells(args, sf, skies, torch):
+def bench_shells(args, sf, skies, torch, n_shell, tolerance, precision):
     """Batched shells: autotune on the median shell (untimed), plan the batch,
     record the graph (untimed warm-up), then time K graph replays and K
-    direct per-shell executes; report both and the plan time."""
+    direct per-shell executes; returns the record (plan + graph execute)."""
     from paper_2210_07021_amd import tune
     t = time.time()
-    sh = skies.shells(args.shells, scale=args.scale)
+    sh = skies.shells(n_shell, scale=args.scale)
     ntot = sum(x[0].shape[1] for x in sh)
     mtot = sum(x[2].shape[1] for x in sh)
-    log(f"[bench] {args.shells} shells, N = {ntot}, M = {mtot}, generated in {time.time() - t:.1f}s")
+    log(f"[bench] {n_shell} shells, N = {ntot}, M = {mtot}, generated in {time.time() - t:.1f}s")
     srcs = [torch.from_numpy(x[0]).cuda() for x in sh]
     qs = [torch.from_numpy(x[1]).cuda() for x in sh]
     tgts = [torch.from_numpy(x[2]).cuda() for x in sh]
     med = sorted(range(len(sh)), key=lambda i: sh[i][0].shape[1])[len(sh) // 2]
-    best, t_best, _ = tune.autotune(srcs[med], qs[med], tgts[med], tolerance=args.tolerance, repeats=1)
+    best, t_best, _ = tune.autotune(srcs[med], qs[med], tgts[med], tolerance=tolerance, precision=precision,
+                                    repeats=1)
     log(f"[bench] autotuned on shell {med}: {best}")
     opts = {k: v for k, v in best.items()}
     torch.cuda.synchronize()
@@ -327,18 +390,19 @@ def bench_shells(args, sf, skies, torch):
             p.execute(psi[i], defl[i])
     torch.cuda.synchronize()
     t_direct = (time.perf_counter() - t0) / args.steps
-    result = {
+    log(f"[bench] shells: plan {1e3 * t_plan:.1f} ms, graph execute {1e3 * t_graph:.1f} ms, "
+        f"direct {1e3 * t_direct:.1f} ms")
+    b.close()
+    return {
         "metric": "targets/s (psi+deflection), batched lensing shells, plan + execute",
         "value": mtot / (t_plan + t_graph), "unit": "targets/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 1, "ms_per_step": 1e3 * (t_plan + t_graph), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"shells-{args.shells}", "N": ntot, "M": mtot, "tolerance": args.tolerance,
+        "vs_baseline": None, "dtype": "f64" if precision == 0 else "f32+f64", "data": "synthetic",
+        "config": {"workload": f"shells-{n_shell}", "N": ntot, "M": mtot, "tolerance": tolerance,
                    "options": {k: v for k, v in opts.items() if k != "tolerance"}},
         "plan_ms": 1e3 * t_plan, "execute_graph_ms": 1e3 * t_graph, "execute_direct_ms": 1e3 * t_direct,
         "execute_targets_per_s_graph": mtot / t_graph,
     }
-    print(json.dumps(result), flush=True)
-    b.close()
 
 
 if __name__ == "__main__":

@@ -163,6 +163,8 @@ def workload(name: str, scale: float = 1.0):
                         nside 256 grid (786,432).
     'clustered-1e7'     N = 1e7 clustered, lognormal masses; M = nside 512
                         grid (3,145,728).
+    'clustered-1e8'     N = 1e8 clustered, lognormal masses; M = nside 1024
+                        grid (12,582,912).
     ``scale`` shrinks N (not the target grid) for quick runs."""
     if name == "uniform-1e4":
         rng = rng_for(0)
@@ -179,6 +181,10 @@ def workload(name: str, scale: float = 1.0):
         rng = rng_for(2)
         n = int(round(1e7 * scale))
         return clustered(n, rng), masses_lognormal(n, rng), grid(512)
+    if name == "clustered-1e8":
+        rng = rng_for(4)
+        n = int(round(1e8 * scale))
+        return clustered(n, rng), masses_lognormal(n, rng), grid(1024)
     raise ValueError(f"unknown workload {name!r}")
 
 

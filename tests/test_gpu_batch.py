@@ -88,19 +88,26 @@ def test_batch_with_bound_policy_runs_directly(oracle_lib):
     b.close()
 
 
-def test_autotune_picks_a_valid_fast_configuration(oracle_lib):
+def test_autotune_picks_a_valid_fast_configuration(oracle_lib, tmp_path):
     sf = _sf()
     from paper_2210_07021_amd import tune
     rng = skies.rng_for(120)
     src = skies.clustered(60000, rng, n_clumps=120)
     q = skies.masses_lognormal(60000, rng)
     tgt = skies.grid(32)
+    cache = str(tmp_path / "tune.json")
     best, t_best, table = tune.autotune(src, q, tgt, tolerance=1e-8, leaf_sizes=(16, 32, 64),
-                                        segments=(64, 256), repeats=1)
+                                        segments=(64, 256), repeats=1, cache=cache)
     times = [t for _, t in table]
     print(f"[tune] best {best} {t_best * 1e3:.2f} ms of {len(table)} candidates, "
           f"range {min(times) * 1e3:.2f}..{max(times) * 1e3:.2f} ms", flush=True)
-    assert t_best == min(times) and len(table) == 3 + 4
+    # leaf sizes, then one order above the tolerance's, then 2 x 2 segments
+    assert t_best == min(times) and len(table) == 3 + 1 + 4
+    assert all(o.get("order", sf.order_for_tolerance(1e-8)) >= sf.order_for_tolerance(1e-8) for o, _ in table)
+    # the cached result comes back without timing
+    again, t_again, table2 = tune.autotune(src, q, tgt, tolerance=1e-8, leaf_sizes=(16, 32, 64),
+                                           segments=(64, 256), repeats=1, cache=cache)
+    assert again == best and t_again == t_best and table2 == []
     psi, defl = _single(src, q, tgt, **best)
     rp, ra = oracle.direct(src, q, tgt[:, ::9])
     check("autotuned", psi[::9], defl[:, ::9], rp, ra, 1e-8)

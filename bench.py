@@ -24,11 +24,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_HBM_GBS = 8000.0
-# FP64 flops of one particle-target pair as evaluated (FMA = 2): 3 for d,
-# 5 for |d|^2, 40 for log|d|^2 (range reduction, Newton reciprocal, degree-10
-# atanh series), 9 for 1/|d|^2 (hardware estimate + 2 Newton steps), 1 for
-# q/|d|^2, 8 for the four accumulations
-FLOP_PER_P2P_PAIR = 66
+# FP64 flops of one particle-target pair as the pair loop executes them (FMA
+# = 2): 3 for d, 5 for |d|^2, ~23 for log|d|^2 (range reduction, table entry,
+# degree-7 series), 8 for 1/|d|^2 (hardware estimate + 2 Newton steps), 1 for
+# q/|d|^2, 8 for the four accumulations; the VALU counters read 7.27e10 FP64
+# flops for 1.52e9 pairs on clustered-1e7
+FLOP_PER_P2P_PAIR = 48
 
 
 # Source files of each timed kernel: the traffic measured by the counters is

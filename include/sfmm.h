@@ -250,14 +250,19 @@ sfmm_status sfmm_execute_noalloc(sfmm_plan_t plan, double* psi, double* defl, vo
 /* Batches: several independent spheres (lensing shells, Sec. 2.1: one
  * Poisson problem per layer) planned together and executed as one unit.
  * sfmm_batch_plan: sfmm_plan on each of the nshell (src[i], q[i], N[i],
- *   tgt[i], M[i]) with the same options, in order, on `stream`; the batch owns
- *   the plans.  With the null stream the batch creates a stream of its own
+ *   tgt[i], M[i]) with the same options; the batch owns the plans.  The shells
+ *   are planned by up to four host threads, each with a stream of the batch
+ *   that starts after the work already on `stream` (largest shells first,
+ *   each to the least loaded thread); the call returns when every plan is
+ *   complete.  With the null stream the batch creates a stream of its own
  *   for sfmm_batch_execute.
  * sfmm_batch_execute: psi[i] [M[i]] and defl[i] [3][M[i]] for every shell.
- *   The first call (and any call with other output pointers or another
- *   stream) runs every shell once directly, records the same work in a HIP
- *   graph and launches it; later calls replay the graph: one launch for all
- *   shells.  Batches with the bound or learned order policy are run directly
+ *   The shells run on the batch's streams, forked from and joined back into
+ *   `stream`, so that one shell's latency-bound stretches overlap another's
+ *   kernels.  The first call (and any call with other output pointers or
+ *   another stream) runs every shell once directly, records the same work in
+ *   a HIP graph (the streams become its parallel branches) and launches it;
+ *   later calls replay the graph: one launch for all shells.  Batches with the bound or learned order policy are run directly
  *   every time (their per-order split reads sizes on the host).  With the
  *   null stream the call returns when the work is done.
  * sfmm_batch_plan_at: the plan of shell i, owned by the batch (never to be

@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace sfmm;
@@ -667,6 +668,9 @@ void check_finite(const float* a, int64_t n, const char* what) {
 
 // A batch of plans (shells) executed together; the work of sfmm_execute on
 // all of them is recorded once in a HIP graph and replayed as one launch.
+// host threads (each with its own stream) that plan the shells of a batch
+constexpr int kBatchPlanStreams = 4;
+
 struct sfmm_batch_impl {
     std::vector<sfmm_plan_impl*> plans;
     hipStream_t own = nullptr;  // used when the caller passes the null stream
@@ -676,6 +680,12 @@ struct sfmm_batch_impl {
     hipStream_t g_stream = nullptr;
     bool capturable = true;
     hipEvent_t done = nullptr;  // end of the last sfmm_batch_execute
+    // worker streams (from planning) and the shells each runs, largest first;
+    // the fork and join events order them after and before the caller's stream
+    std::vector<hipStream_t> ws;
+    std::vector<std::vector<int>> groups;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     void drop_graph() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
@@ -685,8 +695,12 @@ struct sfmm_batch_impl {
     ~sfmm_batch_impl() {
         if (done) (void)hipEventSynchronize(done);
         drop_graph();
+        for (auto w : ws) (void)hipStreamSynchronize(w);
         for (auto* p : plans) sfmm_destroy(p);
         if (done) (void)hipEventDestroy(done);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto e : join) (void)hipEventDestroy(e);
+        for (auto w : ws) (void)hipStreamDestroy(w);
         if (own) hipStreamDestroy(own);
     }
 };
@@ -1511,11 +1525,68 @@ sfmm_status sfmm_batch_plan(int32_t nshell, const double* const* src, const doub
         hipStream_t s = (hipStream_t)stream;
         PoolStream ps(s);
         if (!s) SFMM_HIP(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
-        for (int i = 0; i < nshell; ++i) {
-            sfmm_plan_t p = nullptr;
-            const sfmm_status st = sfmm_plan(src[i], q[i], N[i], tgt[i], M[i], opt, stream, &p);
+        B->plans.assign(nshell, nullptr);
+        const int nw = std::min(nshell, kBatchPlanStreams);
+        if (nw <= 1) {
+            const sfmm_status st = sfmm_plan(src[0], q[0], N[0], tgt[0], M[0], opt, stream, &B->plans[0]);
             if (st != SFMM_OK) return st;
-            B->plans.push_back(p);
+        } else {
+            // The plans read sizes back on the host between their kernels; with
+            // one host thread and one stream per worker, one shell's kernels fill
+            // the GPU while another's host waits.  Shells go to workers largest
+            // first, each to the least loaded (by N log N); the workers' streams
+            // start after the caller's stream (the inputs may be written there)
+            // and are waited for before this call returns.
+            std::vector<hipStream_t>& ws = B->ws;
+            ws.assign(nw, nullptr);
+            hipEvent_t ready = nullptr;
+            auto cleanup = [&]() {  // the streams stay with the batch (its destructor frees them)
+                for (auto w : ws)
+                    if (w) (void)hipStreamSynchronize(w);
+                if (ready) (void)hipEventDestroy(ready);
+            };
+            try {
+                SFMM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+                SFMM_HIP(hipEventRecord(ready, s));
+                for (auto& w : ws) {
+                    SFMM_HIP(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+                    SFMM_HIP(hipStreamWaitEvent(w, ready, 0));
+                }
+            } catch (...) {
+                cleanup();
+                throw;
+            }
+            std::vector<int> idx(nshell);
+            for (int i = 0; i < nshell; ++i) idx[i] = i;
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return N[a] > N[b]; });
+            std::vector<std::vector<int>> mine(nw);
+            std::vector<double> load(nw, 0.0);
+            for (int i : idx) {
+                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                mine[w].push_back(i);
+                load[w] += (double)std::max<int64_t>(N[i], 1) * std::log2((double)std::max<int64_t>(N[i], 2));
+            }
+            std::vector<sfmm_status> st(nw, SFMM_OK);
+            std::vector<std::string> msg(nw);
+            std::vector<std::thread> th;
+            for (int w = 0; w < nw; ++w)
+                th.emplace_back([&, w]() {
+                    for (int i : mine[w]) {
+                        st[w] = sfmm_plan(src[i], q[i], N[i], tgt[i], M[i], opt, ws[w], &B->plans[i]);
+                        if (st[w] != SFMM_OK) {
+                            msg[w] = g_last_error;
+                            return;
+                        }
+                    }
+                });
+            for (auto& t : th) t.join();
+            cleanup();
+            for (int w = 0; w < nw; ++w)
+                if (st[w] != SFMM_OK) throw Error(st[w], msg[w]);
+            B->groups = std::move(mine);
+            SFMM_HIP(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+            B->join.assign(nw, nullptr);
+            for (auto& e : B->join) SFMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         }
         // the per-order split of the bound and learned policies reads sizes
         // on the host between kernels: those batches run without a graph
@@ -1553,6 +1624,23 @@ sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* c
                 if (st != SFMM_OK) throw Error(st, g_last_error);
             }
         };
+        // the shells spread over the worker streams, forked from and joined
+        // back into s (recorded, this makes parallel branches of the graph):
+        // one shell's latency-bound stretches (the coarse levels of Lemmas 2
+        // and 4) overlap another's kernels
+        auto run_par = [&]() {
+            if (B.ws.empty()) return run_all();
+            SFMM_HIP(hipEventRecord(B.fork, s));
+            for (size_t w = 0; w < B.ws.size(); ++w) {
+                SFMM_HIP(hipStreamWaitEvent(B.ws[w], B.fork, 0));
+                for (int i : B.groups[w]) {
+                    const sfmm_status st = sfmm_execute(B.plans[i], psi[i], defl[i], B.ws[w]);
+                    if (st != SFMM_OK) throw Error(st, g_last_error);
+                }
+                SFMM_HIP(hipEventRecord(B.join[w], B.ws[w]));
+                SFMM_HIP(hipStreamWaitEvent(s, B.join[w], 0));
+            }
+        };
         bool same = B.exec && B.g_stream == s;
         for (size_t i = 0; same && i < n; ++i) same = B.g_psi[i] == psi[i] && B.g_defl[i] == defl[i];
         if (same) {
@@ -1563,11 +1651,11 @@ sfmm_status sfmm_batch_execute(sfmm_batch_t batch, double* const* psi, double* c
             B.drop_graph();
             // one direct pass (sizes every buffer a pass needs), then the same
             // pass recorded in a graph, which this call also launches
-            run_all();
+            run_par();
             SFMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             g_capturing = true;
             try {
-                run_all();
+                run_par();
             } catch (...) {
                 g_capturing = false;
                 hipGraph_t g = nullptr;

@@ -89,7 +89,7 @@ enum { SFMM_ORDER_FIXED = 0, SFMM_ORDER_BOUND = 1, SFMM_ORDER_LEARNED = 2 };
 #define SFMM_MLP_WEIGHTS (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
 
 typedef struct {
-    int32_t order;      /* truncation order p of Eq. MUL_ERR, 1..48; 0 = pick p
+    int32_t order;      /* truncation order p of Eq. MUL_ERR, 1..64; 0 = pick p
                            from `tolerance`                                   */
     double tolerance;   /* target relative L2 error of psi and of alpha when
                            order == 0; in [1e-15, 1e-1]                       */

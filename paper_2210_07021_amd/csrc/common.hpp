@@ -101,7 +101,10 @@ struct DVec {
     size_t size() const { return n; }
 };
 
-constexpr int kMaxOrder = 48;
+constexpr int kMaxOrder = 64;
+// the tolerance map stops here: beyond it FP64 rounding, not truncation,
+// sets the error (an explicit order may still go to kMaxOrder)
+constexpr int kMaxTolOrder = 48;
 // the order policy's measured error at order p (relative L2 of the
 // deflection, worst over the calibration skies; the tolerance that gives
 // order p is 4 times this)
@@ -121,7 +124,8 @@ constexpr int kMlpWeights = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlp
 #define SFMM_ORDERS(X)                                                                             \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
     X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) \
-    X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48)
+    X(34) X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48) X(49) \
+    X(50) X(51) X(52) X(53) X(54) X(55) X(56) X(57) X(58) X(59) X(60) X(61) X(62) X(63) X(64)
 
 #define SFMM_DISPATCH(p, LAUNCH)                                                   \
     switch (p) {                                                                   \

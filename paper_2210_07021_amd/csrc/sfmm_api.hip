@@ -194,7 +194,7 @@ int read_int(const int* dev, sfmm_plan_impl& P, hipStream_t s) {
 
 void validate(const sfmm_options& o) {
     auto bad = [](const std::string& m) { throw Error(ST_INVALID_ARG, m); };
-    if (o.order < 0 || o.order > kMaxOrder) bad("order must be in [0, 48]");
+    if (o.order < 0 || o.order > kMaxOrder) bad("order must be in [0, 64]");
     if (o.order == 0 && !(o.tolerance >= 1e-15 && o.tolerance <= 1e-1)) bad("tolerance must be in [1e-15, 1e-1]");
     if (o.leaf_size < 1) bad("leaf_size must be >= 1");
     if (!(o.c_s > 0.0) || !std::isfinite(o.c_s)) bad("c_s must be positive");
@@ -627,9 +627,9 @@ namespace {
 // orders around it (36: 2.93 ms, 37: 3.60 ms, 38: 3.25 ms), so the next even
 // order costs less and is more accurate.
 int order_for_tolerance(double tol) {
-    for (int p = 4; p < kMaxOrder; ++p)
+    for (int p = 4; p < kMaxTolOrder; ++p)
         if (order_calibrated_error(p) * kOrderMarginFactor <= tol) return p + (p & 1);
-    return kMaxOrder;
+    return kMaxTolOrder;
 }
 
 sfmm_status fail(const Error& e) {

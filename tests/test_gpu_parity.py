@@ -178,6 +178,24 @@ def test_parity_clustered_small_all_targets(oracle_lib):
     plan.close()
 
 
+@pytest.mark.parametrize("order", [49, 56, 64])
+def test_high_orders_up_to_64(order, oracle_lib):
+    """Explicit orders above the tolerance map's top (48) up to the ABI's 64:
+    every kernel instance there (Lemmas 1-4, L2P, M2P, the FP32 tier's M2L)
+    still gives the direct sum to the FP64 floor, and the order is the one
+    asked for."""
+    rng = skies.rng_for(103)
+    src = skies.clustered(20000, rng, n_clumps=50)
+    q = skies.masses_lognormal(20000, rng)
+    tgt = np.concatenate([skies.grid(16), src[:, :1000]], axis=1)
+    ref_p, ref_a = oracle.direct(src, q, tgt)
+    for prec, tol in ((0, 1e-10), (1, 1e-6)):
+        plan, psi, defl = _run(src, q, tgt, order=order, leaf_size=32, precision=prec)
+        assert plan.stats()["order"] == order
+        check(f"parity clustered-2e4 order {order} precision {prec}", psi, defl, ref_p, ref_a, tol, say=_say)
+        plan.close()
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_and_tiny_inputs(oracle_lib):
     rng = skies.rng_for(103)

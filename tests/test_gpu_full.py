@@ -44,3 +44,24 @@ def test_full_size_sampled_parity(workload, leaf, oracle_lib):
     plan.close()
     check(f"full {workload} leaf {leaf} p={st['order']} boxes={st['n_boxes']} m2l={st['n_m2l']}",
           psi[idx], defl[:, idx], ref_p, ref_a, 1e-10)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("workload", ["clustered-1e7"])
+def test_full_size_precision_tier_and_policies(workload, oracle_lib):
+    """The precision tier at the bench's configuration (tolerance 1e-6, leaf
+    size 56), with the fixed and the bound per-pair order, on the same seeded
+    1e4-target subset of the oracle."""
+    import torch
+    import paper_2210_07021_amd as sf
+    src, q, tgt, idx, (ref_p, ref_a) = _sky_and_reference(workload)
+    for policy in (sf.SFMM_ORDER_FIXED, sf.SFMM_ORDER_BOUND):
+        plan = sf.Plan(src, q, tgt, tolerance=1e-6, leaf_size=56, precision=sf.SFMM_FP32_MIXED, order_policy=policy)
+        psi, defl = plan.execute()
+        torch.cuda.synchronize()
+        st = plan.stats()
+        psi, defl = psi.cpu().numpy(), defl.cpu().numpy()
+        plan.close()
+        assert st["fell_back"] == 0
+        check(f"full {workload} precision tier policy {policy} p={st['order']} judge {st['judge_psi']:.2e} "
+              f"{st['judge_alpha']:.2e}", psi[idx], defl[:, idx], ref_p, ref_a, 1e-6)

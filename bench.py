@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--shells-leg", type=int, default=40,
                     help="after the main legs, the batched form on this many shells in FP64 (tolerance) and the "
                          "precision tier (fp32 tolerance), reported under 'shells' (0: skip)")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the Hessian leg (psi, alpha and the Hessian of Sec. 2.2 on the same workload) and "
+                         "the ray-tracing leg (8 lensing layers, Eq. DIS_PRO with the distortion matrix)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (scale for the traffic counters) and exit")
     args = ap.parse_args()
@@ -338,6 +341,10 @@ def main():
         for leg in legs_req[1:]:
             p32, d32 = outs[leg]
             result[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
+    if not args.no_extra_legs and legs_req[0] == "fp64":
+        result["hessian"] = bench_hessian(args, sf, torch, src, q, tgt, src_h, q_h, tgt_h,
+                                          None if args.no_cpu_baseline else sub[:500])
+        result["raytrace"] = bench_raytrace(args, sf, skies, torch, check=not args.no_cpu_baseline)
     if args.shells_leg > 0 and legs_req[0] == "fp64":
         del src, q, tgt, psi, defl, outs
         torch.cuda.empty_cache()
@@ -352,6 +359,78 @@ def main():
         sh["config"] = {"workload": f"shells-{args.shells_leg}", "N": r["config"]["N"], "M": r["config"]["M"]}
         result["shells"] = sh
     print(json.dumps(result), flush=True)
+
+
+def bench_hessian(args, sf, torch, src, q, tgt, src_h, q_h, tgt_h, sub):
+    """Plan + execute_hessian on the main workload at the main tolerance
+    (K timed steps after one warm-up); the Hessian against the oracle's on
+    the first targets of the seeded subset (untimed)."""
+    M = tgt.shape[1]
+
+    def step():
+        plan = sf.Plan(src, q, tgt, tolerance=args.tolerance, leaf_size=args.leaf_size)
+        out = plan.execute_hessian()
+        return plan, out
+
+    plan, out = step()
+    torch.cuda.synchronize()
+    plan.close()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan, out = step()
+        plan.close()
+    torch.cuda.synchronize()
+    e = (time.perf_counter() - t0) / args.steps
+    log(f"[bench] hessian: {1e3 * e:.2f} ms per step")
+    rec = {"value": M / e, "unit": "targets/s", "ms_per_step": 1e3 * e, "tolerance": args.tolerance,
+           "dtype": "f64", "outputs": "psi, alpha, Hessian (H_11, H_12, H_22)"}
+    if sub is not None:
+        import oracle
+        ref = oracle.hessian(src_h, q_h, tgt_h[:, sub])
+        h = out[2].cpu().numpy()[:, sub]
+        rec["accuracy"] = {"hessian_rel_l2": float(np.linalg.norm(h - ref) / np.linalg.norm(ref)),
+                           "targets": int(len(sub))}
+    return rec
+
+
+def bench_raytrace(args, sf, skies, torch, check):
+    """Multi-plane backtracking: 8 layers of the clustered recipe (N = 1e6
+    each, own seeds), 786,432 rays on the N_side 256 grid, weights of a
+    source plane behind the last layer, with the distortion matrix; K timed
+    traces after one warm-up.  A seeded subset of 200 rays against the
+    oracle's trace (untimed)."""
+    n_layer = 8
+    layers = []
+    for i in range(n_layer):
+        rng = skies.rng_for(500 + i)
+        s_ = skies.clustered(1_000_000, rng)
+        layers.append((torch.from_numpy(s_).cuda(), torch.from_numpy(skies.masses_lognormal(1_000_000, rng) * 1e-7).cuda()))
+    rays = skies.grid(256)
+    weights = [(n_layer - i) / (n_layer + 1) for i in range(n_layer)]
+    rays_d = torch.from_numpy(rays).cuda()
+    out = sf.raytrace(layers, weights, rays_d, tolerance=args.tolerance, leaf_size=args.leaf_size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = sf.raytrace(layers, weights, rays_d, tolerance=args.tolerance, leaf_size=args.leaf_size)
+    torch.cuda.synchronize()
+    e = (time.perf_counter() - t0) / args.steps
+    m = rays.shape[1]
+    log(f"[bench] raytrace: {1e3 * e:.2f} ms per trace of {n_layer} layers")
+    rec = {"value": m / e, "unit": "rays/s", "ms_per_trace": 1e3 * e, "layers": n_layer,
+           "sources_per_layer": 1_000_000, "rays": m, "tolerance": args.tolerance, "distortion": True}
+    if check:
+        from oracle import raytrace as ort
+        idx = np.random.default_rng(skies.BASE_SEED + 77).choice(m, size=200, replace=False)
+        ref_n, ref_A = ort.trace([(a.cpu().numpy(), b.cpu().numpy()) for a, b in layers], weights, rays[:, idx])
+        got_n, got_A = out[0].cpu().numpy()[:, idx], out[1].cpu().numpy()[:, idx]
+        shift = np.linalg.norm(ref_n - rays[:, idx], axis=0)
+        rec["accuracy"] = {
+            "position_error_over_shift": float(np.linalg.norm(got_n - ref_n) / np.linalg.norm(shift)),
+            "distortion_error_over_A_minus_I": float(
+                np.linalg.norm(got_A - ref_A) / np.linalg.norm(ref_A - np.array([[1.0], [0.0], [0.0], [1.0]]))),
+            "rays": 200}
+    return rec
 
 
 def bench_shells(args, sf, skies, torch, n_shell, tolerance, precision):

@@ -261,6 +261,14 @@ def main():
         a_ = l2p_bytes / (stages_ms["l2p"] * 1e-3) / 1e9
         kernels["l2p"] = {"bound": "hbm", "achieved": round(a_, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": round(a_ / PEAK_HBM_GBS, 4), "ms": stages_ms["l2p"]}
+        # the source keys and sort stage: per point 24 B of coordinates in,
+        # 12 B of key and index out, 8 radix passes of 8 bits over the 62-bit
+        # keys (12 B read and written each), and the gather of the 32-byte
+        # sorted records (read and written)
+        sort_bytes = N * (36 + 8 * 24 + 64)
+        a_ = sort_bytes / (stages_ms["src_keys_sort"] * 1e-3) / 1e9
+        kernels["sort"] = {"bound": "hbm", "achieved": round(a_, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(a_ / PEAK_HBM_GBS, 4), "ms": stages_ms["src_keys_sort"]}
 
     result = {
         "metric": ("targets/s (psi+deflection) at 1e-10 rel err, N=1e7"

@@ -111,3 +111,26 @@ def test_autotune_picks_a_valid_fast_configuration(oracle_lib, tmp_path):
     psi, defl = _single(src, q, tgt, **best)
     rp, ra = oracle.direct(src, q, tgt[:, ::9])
     check("autotuned", psi[::9], defl[:, ::9], rp, ra, 1e-8)
+
+
+def test_batch_plan_error_in_one_shell(oracle_lib):
+    """A shell with a point off the sphere fails its plan on a worker thread:
+    the batch call reports that error (invalid argument, with the message),
+    the other workers' plans are released, and a valid batch planned next
+    still equals its shells' own plans."""
+    import torch
+    sf = _sf()
+    sh = _shells() + _shells()[:2]
+    srcs = [x[0].copy() for x in sh]
+    srcs[4][:, 7] *= 1.01  # off the unit sphere by more than the accepted 1e-6
+    with pytest.raises(sf.SfmmError) as e:
+        sf.Batch(srcs, [x[1] for x in sh], [x[2] for x in sh], tolerance=1e-8, leaf_size=16)
+    assert e.value.status == 1 and "sphere" in str(e.value).lower()
+    opt = dict(tolerance=1e-8, leaf_size=16)
+    b = sf.Batch([x[0] for x in sh], [x[1] for x in sh], [x[2] for x in sh], **opt)
+    psi, defl = b.execute()
+    torch.cuda.synchronize()
+    for i in (0, 4, 6):
+        rp, ra = _single(*sh[i], **opt)
+        assert np.array_equal(psi[i].cpu().numpy(), rp) and np.array_equal(defl[i].cpu().numpy(), ra)
+    b.close()

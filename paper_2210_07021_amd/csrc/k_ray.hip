@@ -36,13 +36,14 @@ __global__ void k_ray_step(double* __restrict__ rays, const double* __restrict__
         const double B21 = A21 - w * (h12 * A11 + h22 * A21), B22 = A22 - w * (h12 * A12 + h22 * A22);
         // transport: u -> u cos t - n sin t, b = n x u fixed
         const double b[3] = {n[1] * u[2] - n[2] * u[1], n[2] * u[0] - n[0] * u[2], n[0] * u[1] - n[1] * u[0]};
-        double T[2][2];
+        // a ray that does not move keeps its basis: T is the identity exactly
+        double T[2][2] = {{1.0, 0.0}, {0.0, 1.0}};
         const double* E[2] = {et, ep};
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; moving && j < 2; ++j) {
             const double a = E[j][0] * u[0] + E[j][1] * u[1] + E[j][2] * u[2];
             const double c = E[j][0] * b[0] + E[j][1] * b[1] + E[j][2] * b[2];
             double pe[3];
-            for (int d = 0; d < 3; ++d) pe[d] = moving ? a * (u[d] * ct - n[d] * st) + c * b[d] : E[j][d];
+            for (int d = 0; d < 3; ++d) pe[d] = a * (u[d] * ct - n[d] * st) + c * b[d];
             T[0][j] = et2[0] * pe[0] + et2[1] * pe[1] + et2[2] * pe[2];
             T[1][j] = ep2[0] * pe[0] + ep2[1] * pe[1] + ep2[2] * pe[2];
         }

@@ -103,3 +103,20 @@ def test_hessian_empty_sources(oracle_lib):
     torch.cuda.synchronize()
     assert not hess.cpu().numpy().any() and not psi.cpu().numpy().any()
     plan.close()
+
+
+def test_hessian_at_the_poles_and_on_grid_vertices(oracle_lib):
+    """Targets exactly at both poles (the basis is the limit at phi = 0) and
+    HEALPix grid targets, which sit on the vertices of deeper pixels and on
+    box centres (the pole-free local form): the Hessian against the oracle's
+    at the FP64 tolerance."""
+    rng = skies.rng_for(133)
+    src = skies.clustered(20000, rng, n_clumps=40)
+    q = skies.masses_lognormal(20000, rng)
+    tgt = np.concatenate([np.array([[0.0, 0.0], [0.0, 0.0], [1.0, -1.0]]), skies.grid(16)], axis=1)
+    st, psi, defl, hess, _, _, _ = _run(src, q, tgt, tolerance=1e-10, leaf_size=16)
+    ref_h = oracle.hessian(src, q, tgt)
+    scale = np.sqrt(np.mean(np.sum(ref_h * ref_h, axis=0)))
+    e = np.linalg.norm(hess - ref_h, axis=0) / scale
+    print(f"[hessian] poles {e[:2]}, grid worst {e[2:].max():.3e} (p={st['order']})", flush=True)
+    assert e[:2].max() <= 1e-8 and e.max() <= 1e-6

@@ -65,3 +65,21 @@ def test_raytrace_point_mass_and_no_distortion(oracle_lib):
     theta = np.arccos(np.clip(s[:, 0] @ rays, -1, 1))
     want = theta - 0.7 * q[0] / (4 * np.pi) / np.tan(theta / 2)
     assert np.allclose(np.arccos(np.clip(s[:, 0] @ got, -1, 1)), want, rtol=0, atol=1e-12)
+
+
+def test_raytrace_empty_and_zero_weight_layers(oracle_lib):
+    """A layer without masses and a layer of weight 0 leave rays and the
+    distortion matrix unchanged: tracing through them equals tracing through
+    the other layers alone, bitwise."""
+    import torch
+    import paper_2210_07021_amd as sf
+    sf.load_library()
+    layers = _layers(2, 5000, 143, 2e-3)
+    empty = (np.zeros((3, 0)), np.zeros(0))
+    rays = skies.uniform(800, skies.rng_for(144))
+    a, Aa = sf.raytrace(layers, [0.7, 0.3], rays, tolerance=1e-10, leaf_size=32)
+    b, Ab = sf.raytrace([layers[0], empty, layers[1], layers[0]], [0.7, 0.5, 0.3, 0.0], rays, tolerance=1e-10,
+                        leaf_size=32)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert np.array_equal(Aa.cpu().numpy(), Ab.cpu().numpy())

@@ -77,9 +77,12 @@ def _experiment(n, beta, seed):
 def test_nfw_sampling_noise_experiment():
     rows = [_experiment(n, 5.0, 150 + k) for k, n in enumerate((100000, 1000000, 10000000))]
     rows += [_experiment(1000000, beta, 160 + k) for k, beta in enumerate((2.0, 10.0))]
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "nfw_experiment.json"), "w") as fh:
-        json.dump({"bins_x": [float(v) for v in BINS], "kappa_s": KS, "r_s": RS, "c": CC, "rows": rows}, fh)
+    # the experiment's table, when a path for it is given
+    out = os.environ.get("SFMM_NFW_TABLE")
+    if out:
+        os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+        with open(out, "w") as fh:
+            json.dump({"bins_x": [float(v) for v in BINS], "kappa_s": KS, "r_s": RS, "c": CC, "rows": rows}, fh)
     by = {(r["N"], r["beta"]): r for r in rows}
     # errors of order 1e-2 outside 0.1 R_s at N = 1e6, beta = 5
     assert by[(1000000, 5.0)]["kappa"]["error"] <= 5e-2

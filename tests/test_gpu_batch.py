@@ -134,3 +134,23 @@ def test_batch_plan_error_in_one_shell(oracle_lib):
         rp, ra = _single(*sh[i], **opt)
         assert np.array_equal(psi[i].cpu().numpy(), rp) and np.array_equal(defl[i].cpu().numpy(), ra)
     b.close()
+
+
+def test_batch_with_an_empty_shell(oracle_lib):
+    """A shell without masses plans and executes like any other (its psi and
+    alpha are zero), also inside the recorded graph and its replays."""
+    import torch
+    sf = _sf()
+    sh = _shells()[:3]
+    empty = (np.zeros((3, 0)), np.zeros(0), sh[1][2])
+    shells = [sh[0], empty, sh[2]]
+    opt = dict(tolerance=1e-8, leaf_size=16)
+    b = sf.Batch([x[0] for x in shells], [x[1] for x in shells], [x[2] for x in shells], **opt)
+    for rep in range(2):  # direct pass + recording, then a replay
+        psi, defl = (b.execute() if rep == 0 else b.execute(psi, defl))
+        torch.cuda.synchronize()
+        assert not psi[1].abs().max().item() and not defl[1].abs().max().item()
+        for i in (0, 2):
+            rp, ra = _single(*shells[i], **opt)
+            assert np.array_equal(psi[i].cpu().numpy(), rp) and np.array_equal(defl[i].cpu().numpy(), ra)
+    b.close()

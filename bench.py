@@ -197,7 +197,8 @@ def main():
     if bad or not legs_req:
         raise SystemExit(f"unknown legs {sorted(bad)}")
     legs, outs = {}, {}
-    for leg in legs_req:
+
+    def run_leg(leg):
         if leg == "fp64":
             o, po, do = opts, psi, defl
         else:
@@ -227,12 +228,23 @@ def main():
             rec["judge"] = {"targets": s_["judge_targets"], "psi_rel_l2": s_["judge_psi"],
                             "alpha_rel_l2": s_["judge_alpha"], "fell_back": bool(s_["fell_back"])}
         legs[leg] = rec
+
+    for i, leg in enumerate(legs_req):
+        if i == 0:
+            run_leg(leg)  # the line's own leg: a failure ends the bench
+            continue
+        try:
+            run_leg(leg)
+        except Exception as e:  # noqa: BLE001  (another leg's failure is reported in its field)
+            log(f"[bench] {leg} leg failed: {e!r}")
+            legs[leg] = {"error": repr(e)}
+            outs.pop(leg, None)
     main_leg = legs_req[0]
     elapsed, stats = legs[main_leg].pop("_elapsed"), legs[main_leg].pop("_stats")
     stages_ms = legs[main_leg]["stages_ms"]
     for leg in legs_req[1:]:
-        legs[leg].pop("_elapsed")
-        legs[leg].pop("_stats")
+        legs[leg].pop("_elapsed", None)
+        legs[leg].pop("_stats", None)
     psi, defl = outs[main_leg]
 
     p = stats["order"]
@@ -347,8 +359,9 @@ def main():
 
         result["accuracy"] = accuracy(psi_h, defl_h)
         for leg in legs_req[1:]:
-            p32, d32 = outs[leg]
-            result[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
+            if leg in outs:
+                p32, d32 = outs[leg]
+                result[leg]["accuracy"] = accuracy(p32.cpu().numpy(), d32.cpu().numpy())
     # the extra legs report an error in their own field rather than losing
     # the line (the headline above is complete by now)
     def extra(name, fn):

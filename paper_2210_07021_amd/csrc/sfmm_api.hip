@@ -523,7 +523,13 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     v.resize(P.nbox);
     // precision tier: boxes of the coarse levels first (they stay FP64)
     const bool tier = P.opt.precision == SFMM_FP32_MIXED;
-    const int lc = tier ? kFp32CoarseLevel : 29;
+    int lc = 29;
+    if (tier) {
+        // SFMM_FP32_COARSE_LEVEL overrides the last FP64 level (-1: none), for
+        // tuning it and for tests
+        const char* v = std::getenv("SFMM_FP32_COARSE_LEVEL");
+        lc = v ? (int)std::max(-1L, std::min(29L, std::strtol(v, nullptr, 10))) : kFp32CoarseLevel;
+    }
     m2l_order_keys(P.m2l_off.data(), P.level.data(), lc, P.nbox, k.data(), v.data(), s);
     radix_sort_u64(k.data(), v.data(), P.nbox, 16, s);
     const int nlev = (int)P.lvl_start.size() - 1;

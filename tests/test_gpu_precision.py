@@ -91,3 +91,16 @@ def test_fp32_mixed_reproducible_and_coincident(oracle_lib):
     _, p2, d2 = _run(src, q, tgt, tolerance=1e-6, leaf_size=4, precision=sf.SFMM_FP32_MIXED)
     assert np.array_equal(p1, p2) and np.array_equal(d1, d2)
     check("fp32 coincident", p1, d1, ref_p, ref_a, 1e-6)
+
+
+@pytest.mark.parametrize("lc", ["-1", "2"])
+def test_fp32_mixed_coarse_level_override(lc, oracle_lib, monkeypatch):
+    """The tier's last FP64 level moved (SFMM_FP32_COARSE_LEVEL): with no FP64
+    level at all the FP64 pass has no boxes and the FP32 pass writes every
+    local record; the result still meets 1e-6 on both skies."""
+    import paper_2210_07021_amd as sf
+    monkeypatch.setenv("SFMM_FP32_COARSE_LEVEL", lc)
+    for name, src, q, tgt, _ in _cases():
+        ref_p, ref_a = oracle.direct(src, q, tgt)
+        st, psi, defl = _run(src, q, tgt, tolerance=1e-6, leaf_size=32, precision=sf.SFMM_FP32_MIXED)
+        check(f"fp32 {name} last FP64 level {lc}", psi, defl, ref_p, ref_a, 1e-6)

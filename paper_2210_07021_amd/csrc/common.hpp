@@ -283,6 +283,12 @@ void fmm_m2l(const FmmCtx& c, int p, bool acc_in, const int* order, int n, const
 void mult_to_f32(const FmmCtx& c, int nbox, float* multf, hipStream_t s);
 void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n, const int* off,
                  const int* src, hipStream_t s);
+// one order class of a per-pair order policy in the precision tier: the
+// pairs at class order p (a multiple of kOrderStep below c.p, or c.p itself)
+// with their monopole part completed up to c.p (record orders 5..24)
+bool m2l_f32_tail_supported(int p);
+void fmm_m2l_f32_tail(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n,
+                      const int* off, const int* src, hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 // (kappa - kappa_bar, gamma_1, gamma_2, mu) [4][m] from the Hessian [3][m]
 void lensing_from_hessian(const double* hess, int64_t m, double* out, hipStream_t s);

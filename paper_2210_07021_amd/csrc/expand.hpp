@@ -365,8 +365,10 @@ SFMM_HD cplxf cmulf(cplxf a, cplxf b) { return {a.re * b.re - a.im * b.im, a.re 
 // A[2l-2] = Re A_l, A[2l-1] = Im A_l) through the factorised map in FP32,
 // with the pair geometry G computed in FP64 and rounded once; the results
 // are added to acc[2P] in FP64, so the sum over an FMM-act list carries no
-// FP32 rounding, and C and Q stay FP64 (accCQ).
-template <int P>
+// FP32 rounding, and C and Q stay FP64 (accCQ).  With PO > P (a pair whose
+// own order P is below the record order PO) the multipole part is cut at P
+// and the monopole part, -(Q/l) a^l ph2^l, still runs to PO: acc[2 PO].
+template <int P, int PO = P>
 SFMM_HD void translate_add_f32_d(const float* __restrict__ A, double C, double Q, const TransGeom& G, double* acc,
                                  double* accCQ) {
     float ar[P + 1], ai[P + 1];
@@ -415,6 +417,14 @@ SFMM_HD void translate_add_f32_d(const float* __restrict__ A, double C, double Q
         const cplxf o = cmulf(pw2, v);
         acc[2 * l - 2] += (double)o.re;
         acc[2 * l - 1] += (double)o.im;
+        pw2 = cmulf(pw2, ph2);
+        an *= a;
+    }
+#pragma unroll
+    for (int l = P + 1; l <= PO; ++l) {
+        const float v = -qf * (1.0f / l) * an;
+        acc[2 * l - 2] += (double)(pw2.re * v);
+        acc[2 * l - 1] += (double)(pw2.im * v);
         pw2 = cmulf(pw2, ph2);
         an *= a;
     }

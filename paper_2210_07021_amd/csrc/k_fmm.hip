@@ -177,8 +177,11 @@ __global__ void k_mult_to_f32(const double* __restrict__ mult, int p, int nb, fl
 // registers (the FP32 working vector leaves room for them), and at the end
 // the team's four sums of every entry are added by two DPP lane exchanges
 // and written by the lane that owns the entry (entry k by lane k mod 4).
-// C and Q stay FP64.  P and acc_in as in k_m2l_team.
-template <int P>
+// C and Q stay FP64.  P and acc_in as in k_m2l_team.  PO > P: the pairs of
+// one order class of a per-pair order policy, translated at order P with
+// their monopole part completed up to the record order PO (so no separate
+// monopole pass is needed for these boxes); entries up to PO are added.
+template <int P, int PO = P>
 __global__ void __launch_bounds__(128) k_m2l_team_f32(FmmCtx c, const float* __restrict__ multf, const int* order,
                                                      int n, const int* off, const int* src, bool acc_in) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,24 +198,24 @@ __global__ void __launch_bounds__(128) k_m2l_team_f32(FmmCtx c, const float* __r
     }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
-    double acc[2 * P + 2];  // C, Q, then the A-block
+    double acc[2 * PO + 2];  // C, Q, then the A-block
 #pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 2 * PO + 2; ++k) acc[k] = 0.0;
     for (int k = k0 + r; k < k1; k += 4) {
         const int s = src[k];
         double rho_s;
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
         const double* e = c.mult + (size_t)s * ew;
-        translate_add_f32_d<P>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
+        translate_add_f32_d<P, PO>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
     }
 #pragma unroll
-    for (int k = 0; k < 2 * P + 2; ++k) {
+    for (int k = 0; k < 2 * PO + 2; ++k) {
         const double v = quad_sum(acc[k]);
         if ((k & 3) == r) out[k] = acc_in ? out[k] + v : v;
     }
     if (!acc_in)
-        for (size_t k = 2 * P + 2 + r; k < ew; k += 4) out[k] = 0.0;  // a first pass below the record order
+        for (size_t k = 2 * PO + 2 + r; k < ew; k += 4) out[k] = 0.0;  // a first pass below the record order
 }
 
 // Lemma 4: every box of one level takes its parent's local expansion
@@ -325,6 +328,40 @@ void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const 
     SFMM_DISPATCH(p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
+}
+
+bool m2l_f32_tail_supported(int p) { return p >= 5 && p <= 24; }
+
+void fmm_m2l_f32_tail(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n,
+                      const int* off, const int* src, hipStream_t s) {
+    if (n <= 0) return;
+    if (p == c.p) return fmm_m2l_f32(c, p, acc_in, multf, order, n, off, src, s);
+    if (!m2l_f32_tail_supported(c.p) || p < 1 || p > c.p || p % kOrderStep)
+        throw Error(ST_INTERNAL, "class order outside the per-pair order M2L instances");
+    const unsigned g = nblk(4 * (int64_t)n, 128);
+#define T_(P, PO)                                                                                    \
+    if (p == P && c.p == PO) {                                                                       \
+        k_m2l_team_f32<P, PO><<<g, 128, 0, s>>>(c, multf, order, n, off, src, acc_in);               \
+        SFMM_LAUNCH_CHECK();                                                                         \
+        return;                                                                                      \
+    }
+#define T4_(PO) T_(4, PO)
+#define T8_(PO) T4_(PO) T_(8, PO)
+#define T12_(PO) T8_(PO) T_(12, PO)
+#define T16_(PO) T12_(PO) T_(16, PO)
+#define T20_(PO) T16_(PO) T_(20, PO)
+    T4_(5) T4_(6) T4_(7) T4_(8)
+    T8_(9) T8_(10) T8_(11) T8_(12)
+    T12_(13) T12_(14) T12_(15) T12_(16)
+    T16_(17) T16_(18) T16_(19) T16_(20)
+    T20_(21) T20_(22) T20_(23) T20_(24)
+#undef T20_
+#undef T16_
+#undef T12_
+#undef T8_
+#undef T4_
+#undef T_
+    throw Error(ST_INTERNAL, "class order outside the per-pair order M2L instances");
 }
 
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s) {

@@ -798,11 +798,24 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
             }
             P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
                                          P.p, P.ord_off, P.ord_src, s);
-            // class q holds the orders in (4q, 4q + 4]; the top class the plan order
-            for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q)
-                m2l_pass(std::min((q + 1) * kOrderStep, P.p), q > 0, P.ord_off.data() + (size_t)q * P.nbox,
-                         P.ord_src.data());
-            m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
+            // class q holds the orders in (4q, 4q + 4]; the top class the plan
+            // order.  The precision tier's boxes complete each pair's
+            // monopole part inside its class pass; the FP64 boxes (the first
+            // n_m2l_fp64 in box order) take it from one pass afterwards
+            const bool tail_in_pass = tier && m2l_f32_tail_supported(P.p);
+            for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q) {
+                const int pq = std::min((q + 1) * kOrderStep, P.p);
+                const int* boff = P.ord_off.data() + (size_t)q * P.nbox;
+                if (!tail_in_pass) {
+                    m2l_pass(pq, q > 0, boff, P.ord_src.data());
+                    continue;
+                }
+                fmm_m2l(c, pq, q > 0, P.m2l_order.data(), P.n_m2l_fp64, boff, P.ord_src.data(), s);
+                fmm_m2l_f32_tail(c, pq, q > 0, multf, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
+                                 boff, P.ord_src.data(), s);
+            }
+            m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(),
+                      tail_in_pass ? P.n_m2l_fp64 : P.nbox, s);
         }
     }
     // down-pass: Lemma 4 from level 1 down

@@ -194,6 +194,13 @@ def test_learned_policy_gain(oracle_lib):
         assert 0 <= st["judge_psi"] <= tol and 0 <= st["judge_alpha"] <= tol
         assert st["m2l_order_sq"] <= 0.95 * fx["m2l_order_sq"]
         assert st["m2l_order_sq"] < bd["m2l_order_sq"]
+        # the same network in the precision tier, whose order classes complete
+        # each pair's monopole part inside the class passes
+        s32, p32, d32 = _run(src, q, tgt, tolerance=tol, leaf_size=32, order_policy=sf.SFMM_ORDER_LEARNED,
+                             mlp_weights=w, precision=sf.SFMM_FP32_MIXED)
+        check(f"learned {name} precision tier: M2L work {s32['m2l_order_sq'] / fx['m2l_order_sq']:.3f} of fixed",
+              p32, d32, ref_p, ref_a, tol)
+        assert s32["fell_back"] == 0 and s32["m2l_order_sq"] <= 0.95 * fx["m2l_order_sq"]
 
 
 def _corrupted_weights(sf):

@@ -12,11 +12,14 @@ namespace sfmm {
 // lane getting the sum: two butterfly steps with DPP quad permutations
 // (lane exchanges inside the VALU, no LDS), (v0 + v1) + (v2 + v3) on every
 // lane of the quad.
+// Every lane of a quad is active wherever these are called (a team's four
+// lanes run the same iterations), so no lane reads a disabled one and the
+// bound-control form needs no old value (no extra register move).
 template <int CTRL>
 __device__ __forceinline__ double dpp_quad(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+    const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi2, lo2);
 }
 __device__ __forceinline__ double quad_sum(double v) {

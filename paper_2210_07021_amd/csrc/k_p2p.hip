@@ -272,7 +272,6 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
                                                        first_far.data(), tot.data() + 1, out.near_off.data(),
                                                        out.far_off.data());
     SFMM_LAUNCH_CHECK();
-    SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }
 
 void near_work(const int* count, const NearLists& nl, const int* tcount, int nbox, long long* pairs,
@@ -389,7 +388,6 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     radix_sort_u64(keys.data(), vals.data(), out.n, 8, s);
     k_gather_items<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), vals.data(), out.n, out.items.data());
     SFMM_LAUNCH_CHECK();
-    SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }
 
 // Adds the per-segment results of every box cut into several items, in

@@ -535,7 +535,7 @@ uint64_t* radix_sort_u64_pp(uint64_t* keys, uint32_t* vals, uint64_t* kalt, uint
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    SFMM_HIP(hipStreamSynchronize(s));
+    // freed blocks are only reused by later stream-ordered work on this stream
     pool_free(hist);
     pool_free(offs);
     pool_free(dtot);
@@ -552,7 +552,6 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStre
     if (kr != keys) {  // an odd number of passes leaves the result in the scratch buffers
         SFMM_HIP(hipMemcpyAsync(keys, kr, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
         if (vals) SFMM_HIP(hipMemcpyAsync(vals, vr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-        SFMM_HIP(hipStreamSynchronize(s));
     }
     pool_free(k2);
     if (v2) pool_free(v2);
@@ -578,7 +577,6 @@ void sum_f64(const double* x, int64_t n, double* out, hipStream_t s, int stride)
     SFMM_LAUNCH_CHECK();
     k_sum_tiles<<<1, 256, 0, s>>>(part, 1024, 1, out);
     SFMM_LAUNCH_CHECK();
-    SFMM_HIP(hipStreamSynchronize(s));
     pool_free(part);
 }
 
@@ -601,7 +599,6 @@ void sum_i64(const long long* x, int64_t n, long long* out, hipStream_t s) {
     SFMM_LAUNCH_CHECK();
     k_sum_i64<<<1, 256, 0, s>>>(part, 1024, out);
     SFMM_LAUNCH_CHECK();
-    SFMM_HIP(hipStreamSynchronize(s));
     pool_free(part);
 }
 

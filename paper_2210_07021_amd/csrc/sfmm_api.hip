@@ -240,7 +240,6 @@ void sort_points(const double* in, const double* q_in, int64_t n, DVec<double4>&
     prepare_checked(in, q_in, n, u, keys, perm, P, s, what);
     radix_sort_u64(keys.data(), perm.data(), n, 62, s);
     gather_records(perm.data(), n, u.data(), rec.data(), s);
-    SFMM_HIP(hipStreamSynchronize(s));
 }
 
 constexpr int kTreeBatch = 8;  // queued levels between two read-backs
@@ -358,7 +357,6 @@ void sort_pairs_to_csr(DVec<uint64_t>& pairs, int np, int nbox, DVec<int>& off, 
         pair_split(pairs.data(), np, src.data(), tgt.data(), s);
     }
     csr_offsets(tgt.data(), np, nbox, off.data(), s);
-    SFMM_HIP(hipStreamSynchronize(s));
 }
 
 // Capacities of the queued walk, as multiples of the box count: the largest
@@ -536,7 +534,6 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     P.n_m2l_fp64 = tier ? P.lvl_start[std::min(lc + 1, nlev)] : P.nbox;
     P.m2l_order.resize(P.nbox);
     SFMM_HIP(hipMemcpyAsync(P.m2l_order.data(), v.data(), sizeof(int) * P.nbox, hipMemcpyDeviceToDevice, s));
-    SFMM_HIP(hipStreamSynchronize(s));
 }
 
 // Boxes that have items: the items minus the extra segments of split boxes
@@ -584,7 +581,6 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
             std::swap(P.tperm.cap, perm2.cap);
         }
         gather_targets(P.tperm.data(), ls, M, u.data(), P.tx.data(), P.ty.data(), P.tz.data(), P.tleaf.data(), s);
-        SFMM_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
     }
     target_ranges(P.tleaf.data(), M, P.nbox, P.tfirst.data(), P.tcount.data(), s);
     near_split(P.ctx(), P.p2p_off.data(), P.p2p_src.data(), P.p2p_ent.data(), P.nbox, P.n_p2p, P.tfirst.data(),

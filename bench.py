@@ -35,7 +35,7 @@ FLOP_PER_P2P_PAIR = 48
 # Source files of each timed kernel: the traffic measured by the counters is
 # only used while these files are unchanged.
 KERNEL_SOURCES = {
-    "m2l": ["k_fmm.hip", "expand.hpp", "common.hpp"],
+    "m2l": ["k_fmm.hip", "expand.hpp", "common.hpp", "k_tree.hip"],  # k_tree.hip: the box order
     "p2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
     "m2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
 }

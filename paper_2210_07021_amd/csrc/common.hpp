@@ -211,8 +211,9 @@ constexpr int kWalkDtrig = 14;
 void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
                 double c_s, double c_t, double sigma, double4* geo, double2* strig, double4* ttrig, int2* cc,
                 double* dtrig, hipStream_t s);
-// M2L order: boxes of levels <= lc first, then the others; longest list
-// first within each part (16-bit keys, ties in table order)
+// M2L order: boxes of levels <= lc first, then the others; most team rounds
+// (four pairs a round) first within each part (16-bit keys, ties in table
+// order)
 // One walk round in three launches (classify + per-chunk scans, scan of the
 // chunk totals into tot[3]: children pairs, M2L pairs, P2P pairs; emit),
 // sized on the device: st = {frontier size, M2L base, P2P base} of this

@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(128) k_m2m(FmmCtx c, int b0, int nb) {
 // of entries 2 + 4q .. 5 + 4q are held until the group is complete and then
 // each lane adds its own with one LDS add (single writer per slot, so the
 // sums keep their round order).  No lane holds the whole accumulator: two
-// waves fit on a SIMD.  Target boxes are taken in `order` (longest list
-// first, so the teams of a wave carry similar work).  P is the order of the
+// waves fit on a SIMD.  Target boxes are taken in `order` (most rounds
+// first, so the teams of a wave carry the same work).  P is the order of the
 // translation, c.p that of the records (P <= c.p: a per-pair order policy
 // runs one pass per order with the pairs of that order, adding to the
 // records' first 2P + 2 entries, acc_in = true; a first pass, acc_in =

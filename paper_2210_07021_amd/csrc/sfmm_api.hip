@@ -513,8 +513,8 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
     const bool ent = P.opt.order_policy != SFMM_ORDER_FIXED;
     sort_pairs_to_csr(m2l, n_m2l, P.nbox, P.m2l_off, P.m2l_src, ent ? &P.m2l_ent : nullptr, s);
     sort_pairs_to_csr(p2p, n_p2p, P.nbox, P.p2p_off, P.p2p_src, &P.p2p_ent, s);
-    // M2L work order: target boxes with the longest lists first, so the lanes
-    // of a wave carry similar work
+    // M2L work order: target boxes with the most team rounds first, so the
+    // lanes of a wave carry the same work
     DVec<uint64_t> k;
     DVec<uint32_t> v;
     k.resize(P.nbox);

@@ -211,9 +211,16 @@ constexpr int kWalkDtrig = 14;
 void walk_boxes(int nb, const double* cen, const double* rad, const double* gdd, const int* child0, const int* count,
                 double c_s, double c_t, double sigma, double4* geo, double2* strig, double4* ttrig, int2* cc,
                 double* dtrig, hipStream_t s);
+// Lanes per target box of the FP64 team M2L over n boxes: two
+// (k_m2l_team2) when two-lane teams still fill the chip (two waves per SIMD
+// on 256 CUs: 131072 lanes), four (k_m2l_team) below that; and of the
+// precision tier's FP32 team M2L (k_m2l_team_f32).
+constexpr int64_t kM2LTeam2MinBoxes = 65536;
+inline int m2l_team_width(int64_t n) { return n >= kM2LTeam2MinBoxes ? 2 : 4; }
+constexpr int kM2LTeamF32 = 4;
 // M2L order: boxes of levels <= lc first, then the others; most team rounds
-// (four pairs a round) first within each part (16-bit keys, ties in table
-// order)
+// first within each part, a round being tw_coarse pairs for the first part
+// and tw_fine for the second (16-bit keys, ties in table order)
 // One walk round in three launches (classify + per-chunk scans, scan of the
 // chunk totals into tot[3]: children pairs, M2L pairs, P2P pairs; emit),
 // sized on the device: st = {frontier size, M2L base, P2P base} of this
@@ -230,8 +237,8 @@ void walk_round_scan(const int2* F, const int* st, const WalkCtx& w, uint8_t* ac
 void walk_round_emit(const int2* F, const int* st, const WalkCtx& w, const uint8_t* action, const int* coff,
                      int cstride, const int* tot, const WalkCaps& cap, int2* Fnext, uint64_t* m2l, uint64_t* p2p,
                      int* st_next, int* overflow, int grid, hipStream_t s);
-void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
-                    hipStream_t s);
+void m2l_order_keys(const int* off, const int* level, int lc, int tw_coarse, int tw_fine, int nbox, uint64_t* keys,
+                    uint32_t* vals, hipStream_t s);
 // precision tier: M2L into boxes of levels <= kFp32CoarseLevel stays FP64
 // (the large contributions of coarse boxes nearly cancel on smooth skies,
 // which FP32 rounding would show)

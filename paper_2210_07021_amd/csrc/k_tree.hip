@@ -854,25 +854,27 @@ void csr_offsets(const int* tgt, int np, int nbox, int* off, hipStream_t s) {
 }
 
 // M2L order keys: boxes of levels <= lc first (bit 15 clear), then the rest;
-// most team rounds (four pairs a round) first within each part, so the teams
-// of a wave run the same number of rounds.  The sort is stable: boxes of one
-// round count keep their index order, which is level by level in key order,
-// so the teams of a workgroup are mostly neighbours sharing sources in the
-// cache (3 % less M2L time than ordering by exact list length).
-__global__ void k_m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys,
-                                 uint32_t* vals) {
+// most team rounds (tw_coarse or tw_fine pairs a round) first within each
+// part, so the teams of a wave run the same number of rounds.  The sort is
+// stable: boxes of one round count keep their index order, which is level by
+// level in key order, so the teams of a workgroup are mostly neighbours
+// sharing sources in the cache (3 % less M2L time than ordering by exact
+// list length).
+__global__ void k_m2l_order_keys(const int* off, const int* level, int lc, int tw_coarse, int tw_fine, int nbox,
+                                 uint64_t* keys, uint32_t* vals) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
-    const uint32_t len = (uint32_t)(off[b + 1] - off[b] + 3) / 4;  // rounds of a team of four lanes
-    const uint64_t fine = level[b] > lc ? 1 : 0;
-    keys[b] = (fine << 15) | (uint64_t)(0x7fffu - (len < 0x7fffu ? len : 0x7fffu));
+    const bool fine = level[b] > lc;
+    const int tw = fine ? tw_fine : tw_coarse;
+    const uint32_t rounds = (uint32_t)(off[b + 1] - off[b] + tw - 1) / (uint32_t)tw;
+    keys[b] = ((uint64_t)fine << 15) | (uint64_t)(0x7fffu - (rounds < 0x7fffu ? rounds : 0x7fffu));
     vals[b] = (uint32_t)b;
 }
 
-void m2l_order_keys(const int* off, const int* level, int lc, int nbox, uint64_t* keys, uint32_t* vals,
-                    hipStream_t s) {
+void m2l_order_keys(const int* off, const int* level, int lc, int tw_coarse, int tw_fine, int nbox, uint64_t* keys,
+                    uint32_t* vals, hipStream_t s) {
     if (nbox <= 0) return;
-    k_m2l_order_keys<<<nblocks(nbox, 256), 256, 0, s>>>(off, level, lc, nbox, keys, vals);
+    k_m2l_order_keys<<<nblocks(nbox, 256), 256, 0, s>>>(off, level, lc, tw_coarse, tw_fine, nbox, keys, vals);
     SFMM_LAUNCH_CHECK();
 }
 

@@ -528,10 +528,11 @@ void build_lists(sfmm_plan_impl& P, hipStream_t s, Profiler& prof) {
         const char* v = std::getenv("SFMM_FP32_COARSE_LEVEL");
         lc = v ? (int)std::max(-1L, std::min(29L, std::strtol(v, nullptr, 10))) : kFp32CoarseLevel;
     }
-    m2l_order_keys(P.m2l_off.data(), P.level.data(), lc, P.nbox, k.data(), v.data(), s);
-    radix_sort_u64(k.data(), v.data(), P.nbox, 16, s);
     const int nlev = (int)P.lvl_start.size() - 1;
     P.n_m2l_fp64 = tier ? P.lvl_start[std::min(lc + 1, nlev)] : P.nbox;
+    m2l_order_keys(P.m2l_off.data(), P.level.data(), lc, m2l_team_width(P.n_m2l_fp64), kM2LTeamF32, P.nbox, k.data(),
+                   v.data(), s);
+    radix_sort_u64(k.data(), v.data(), P.nbox, 16, s);
     P.m2l_order.resize(P.nbox);
     SFMM_HIP(hipMemcpyAsync(P.m2l_order.data(), v.data(), sizeof(int) * P.nbox, hipMemcpyDeviceToDevice, s));
 }

@@ -40,6 +40,7 @@ KERNEL_SOURCES = {
     "m2p": ["k_p2p.hip", "expand.hpp", "common.hpp"],
 }
 KERNEL_NAMES = {"m2l": "k_m2l_team", "p2p": "k_p2p", "m2p": "k_m2p"}
+M2L_TEAM2_MIN_BOXES = 65536  # the library's switch to two-lane M2L teams (boxes)
 
 
 def source_hash(stage: str) -> str:
@@ -258,7 +259,10 @@ def main():
         dom = max(work, key=lambda k: stages_ms[k])
         bound, flops, peak, unit = work[dom]
         achieved = flops / (stages_ms[dom] * 1e-3) / 1e12
-        roofline = {"kernel": KERNEL_NAMES[dom], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+        kname = KERNEL_NAMES[dom]
+        if dom == "m2l" and stats["n_boxes"] >= M2L_TEAM2_MIN_BOXES:
+            kname = "k_m2l_team2"  # two lanes per target box on large trees
+        roofline = {"kernel": kname, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                     "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
                     "work_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
         # every timed FMM kernel against its own roofline (stage time from the

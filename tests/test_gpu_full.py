@@ -65,3 +65,26 @@ def test_full_size_precision_tier_and_policies(workload, oracle_lib):
         assert st["fell_back"] == 0
         check(f"full {workload} precision tier policy {policy} p={st['order']} judge {st['judge_psi']:.2e} "
               f"{st['judge_alpha']:.2e}", psi[idx], defl[:, idx], ref_p, ref_a, 1e-6)
+
+
+@pytest.mark.timeout(600)
+def test_two_lane_m2l_fixed_and_per_pair_orders(oracle_lib):
+    """Trees of at least 65,536 boxes run the FP64 M2L with two lanes per
+    target box (smaller ones with four): clustered-1e6 at leaf size 12 is
+    such a tree.  The fixed order at 1e-10 and the bound per-pair order at
+    1e-8 (one pass per order class adding into the local records, then the
+    monopole pass) against the oracle on the seeded 1e4-target subset."""
+    import torch
+    import paper_2210_07021_amd as sf
+    src, q, tgt, idx, (ref_p, ref_a) = _sky_and_reference("clustered-1e6")
+    for policy, tol in ((sf.SFMM_ORDER_FIXED, 1e-10), (sf.SFMM_ORDER_BOUND, 1e-8)):
+        plan = sf.Plan(src, q, tgt, tolerance=tol, leaf_size=12, order_policy=policy)
+        psi, defl = plan.execute()
+        torch.cuda.synchronize()
+        st = plan.stats()
+        psi, defl = psi.cpu().numpy(), defl.cpu().numpy()
+        plan.close()
+        assert st["n_boxes"] >= 65536, st["n_boxes"]
+        assert st["fell_back"] == 0
+        check(f"two-lane M2L clustered-1e6 leaf 12 policy {policy} p={st['order']} boxes={st['n_boxes']}",
+              psi[idx], defl[:, idx], ref_p, ref_a, tol)

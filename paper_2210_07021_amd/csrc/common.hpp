@@ -309,8 +309,7 @@ void fmm_l2p(const FmmCtx& c, const double* tx, const double* ty, const double* 
 // and those taken through their multipole expansion (far), both in CSR form
 // by target box, with the work each box gives the two kernels.
 struct NearLists {
-    DVec<int> near_off, near_src, far_off, far_src;
-    int n_near = 0, n_far = 0;
+    DVec<int> near_off, near_src, far_off, far_src;  // the src arrays hold np entries' room
 };
 void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_t, int nbox, int np,
                 const int* tfirst, const int* tcount, const double* tx, const double* ty, const double* tz,
@@ -325,9 +324,12 @@ struct WorkItems {
 };
 constexpr int kSegNear = 128;  // close leaves per direct-sum item
 constexpr int kSegFar = 128;   // close leaves per expansion item
-// count == nullptr: work counted per entry instead of per particle
-void build_items(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
-                 WorkItems& out, hipStream_t s);
+// Work items of two lists of the same boxes (a and b; seg close leaves per
+// item), with one read-back of the totals; count == nullptr: work counted
+// per entry instead of per particle
+void build_items2(const int* off_a, const int* src_a, const int* count_a, int seg_a, WorkItems& out_a,
+                  const int* off_b, const int* src_b, const int* count_b, int seg_b, WorkItems& out_b,
+                  const int* tcount, int nbox, hipStream_t s);
 // per box: pairs[b] = targets x particles of the near leaves, evals[b] =
 // targets x far leaves
 void near_work(const int* count, const NearLists& nl, const int* tcount, int nbox, long long* pairs,

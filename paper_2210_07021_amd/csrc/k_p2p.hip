@@ -234,7 +234,10 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
                 NearLists& out, hipStream_t s) {
     out.near_off.resize(nbox + 1);
     out.far_off.resize(nbox + 1);
-    out.n_near = out.n_far = 0;
+    // every entry goes to at most one of the two lists, so np bounds both:
+    // no read-back of the totals (which stay on the device for the offsets)
+    out.near_src.resize(std::max(np, 1));
+    out.far_src.resize(std::max(np, 1));
     if (nbox <= 0) return;
     const int nb = std::max((np + kNearBlk - 1) / kNearBlk, 1);
     DVec<uint8_t> flag;
@@ -255,13 +258,6 @@ void near_split(const FmmCtx& c, const int* off, const int* src, const int* ent_
         scan_excl_i32(bnear.data(), bnoff.data(), nb, tot.data(), s);
         scan_excl_i32(bfar.data(), bfoff.data(), nb, tot.data() + 1, s);
     }
-    int h[2] = {0, 0};
-    SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
-    SFMM_HIP(hipStreamSynchronize(s));
-    out.n_near = h[0];
-    out.n_far = h[1];
-    out.near_src.resize(std::max(h[0], 1));
-    out.far_src.resize(std::max(h[1], 1));
     if (np > 0) {
         k_near_scatter<<<nb, kNearBlk, 0, s>>>(src, ent_t, np, flag.data(), bnoff.data(), bfoff.data(),
                                                out.near_src.data(), out.far_src.data(), first_near.data(),
@@ -346,26 +342,30 @@ __global__ void k_gather_items(const int4* __restrict__ in, const uint32_t* __re
     if (i < n) out[i] = in[idx[i]];
 }
 
-void build_items(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
-                 WorkItems& out, hipStream_t s) {
-    out.n = out.nred = 0;
-    out.nslot = 0;
-    if (nbox <= 0) return;
-    DVec<int> nseg, nslot, multi, item_off, slot_off, red_off, tot;
-    nseg.resize(nbox);
-    nslot.resize(nbox);
-    multi.resize(nbox);
-    item_off.resize(nbox);
-    slot_off.resize(nbox);
-    red_off.resize(nbox);
-    tot.resize(3);
-    k_seg_count<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), nslot.data(), multi.data());
+namespace {
+// The two halves of building one list's work items around the read-back of
+// its three totals (items, partial slots, reduce records), so that two lists
+// can share one read-back.
+struct ItemCounts {
+    DVec<int> nseg, nslot, multi, item_off, slot_off, red_off;
+};
+
+void items_count(const int* off, const int* tcount, int nbox, int seg, ItemCounts& t, int* tot, hipStream_t s) {
+    t.nseg.resize(nbox);
+    t.nslot.resize(nbox);
+    t.multi.resize(nbox);
+    t.item_off.resize(nbox);
+    t.slot_off.resize(nbox);
+    t.red_off.resize(nbox);
+    k_seg_count<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, t.nseg.data(), t.nslot.data(),
+                                                t.multi.data());
     SFMM_LAUNCH_CHECK();
-    scan3_excl_i32(nseg.data(), nslot.data(), multi.data(), item_off.data(), slot_off.data(), red_off.data(), nbox,
-                   tot.data(), s);
-    int h[3];
-    SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
-    SFMM_HIP(hipStreamSynchronize(s));
+    scan3_excl_i32(t.nseg.data(), t.nslot.data(), t.multi.data(), t.item_off.data(), t.slot_off.data(),
+                   t.red_off.data(), nbox, tot, s);
+}
+
+void items_emit(const int* off, const int* src, const int* count, const int* tcount, int nbox, int seg,
+                const ItemCounts& t, const int* h, WorkItems& out, hipStream_t s) {
     out.n = h[0];
     out.nslot = h[1];
     out.nred = h[2];
@@ -379,8 +379,8 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     raw.resize(out.n);
     keys.resize(out.n);
     vals.resize(out.n);
-    k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, nseg.data(), item_off.data(),
-                                               slot_off.data(), red_off.data(), raw.data(), out.red.data());
+    k_seg_emit<<<nblk(nbox, 256), 256, 0, s>>>(off, tcount, nbox, seg, t.nseg.data(), t.item_off.data(),
+                                               t.slot_off.data(), t.red_off.data(), raw.data(), out.red.data());
     SFMM_LAUNCH_CHECK();
     k_item_keys<<<nblk(64 * (int64_t)out.n, 256), 256, 0, s>>>(raw.data(), out.n, src, count, tcount, keys.data(),
                                                              vals.data());
@@ -388,6 +388,25 @@ void build_items(const int* off, const int* src, const int* count, const int* tc
     radix_sort_u64(keys.data(), vals.data(), out.n, 8, s);
     k_gather_items<<<nblk(out.n, 256), 256, 0, s>>>(raw.data(), vals.data(), out.n, out.items.data());
     SFMM_LAUNCH_CHECK();
+}
+}  // namespace
+
+void build_items2(const int* off_a, const int* src_a, const int* count_a, int seg_a, WorkItems& out_a,
+                  const int* off_b, const int* src_b, const int* count_b, int seg_b, WorkItems& out_b,
+                  const int* tcount, int nbox, hipStream_t s) {
+    out_a.n = out_a.nred = out_a.nslot = 0;
+    out_b.n = out_b.nred = out_b.nslot = 0;
+    if (nbox <= 0) return;
+    ItemCounts ta, tb;
+    DVec<int> tot;
+    tot.resize(6);
+    items_count(off_a, tcount, nbox, seg_a, ta, tot.data(), s);
+    items_count(off_b, tcount, nbox, seg_b, tb, tot.data() + 3, s);
+    int h[6];
+    SFMM_HIP(hipMemcpyAsync(h, tot.data(), sizeof(h), hipMemcpyDeviceToHost, s));
+    SFMM_HIP(hipStreamSynchronize(s));
+    items_emit(off_a, src_a, count_a, tcount, nbox, seg_a, ta, h, out_a, s);
+    items_emit(off_b, src_b, count_b, tcount, nbox, seg_b, tb, h + 3, out_b, s);
 }
 
 // Adds the per-segment results of every box cut into several items, in

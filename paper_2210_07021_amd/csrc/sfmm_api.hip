@@ -125,7 +125,7 @@ struct sfmm_plan_impl {
     DVec<uint32_t> tperm;
     DVec<uint64_t> tkeys;
     DVec<int> tleaf, tfirst, tcount;
-    int ntl = 0;  // leaves with targets and direct-sum work
+    mutable int ntl = -1;  // leaves with targets and direct-sum work (counted when the statistics ask)
     // direct-act lists split into direct sums and multipole evaluations
     NearLists nl;
     WorkItems near_items, far_items;
@@ -589,11 +589,9 @@ void build_targets(sfmm_plan_impl& P, const double* tgt, hipStream_t s) {
     P.p2p_ent.reset();  // stream-ordered pool: later work on this stream may reuse it
     const int segn = P.opt.near_segment > 0 ? P.opt.near_segment : kSegNear;
     const int segf = P.opt.far_segment > 0 ? P.opt.far_segment : kSegFar;
-    build_items(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), P.tcount.data(), P.nbox, segn,
-                P.near_items, s);
-    build_items(P.nl.far_off.data(), P.nl.far_src.data(), nullptr, P.tcount.data(), P.nbox, segf, P.far_items,
-                s);
-    P.ntl = count_boxes(P.near_items, s);
+    build_items2(P.nl.near_off.data(), P.nl.near_src.data(), P.count.data(), segn, P.near_items,
+                 P.nl.far_off.data(), P.nl.far_src.data(), nullptr, segf, P.far_items, P.tcount.data(), P.nbox, s);
+    P.ntl = -1;  // counted by the statistics: a read-back the plan itself does not need
 }
 
 // Order from a tolerance, by a measured calibration at the default MACs
@@ -1181,6 +1179,7 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         out->n_leaves = std::count_if(c0.begin(), c0.end(), [](int v) { return v < 0; });
         out->n_m2l = P.n_m2l;
         out->n_p2p = P.n_p2p;
+        if (P.ntl < 0) P.ntl = count_boxes(P.near_items, nullptr);
         out->n_target_leaves = P.ntl;
         if (P.n_p2p_pairs < 0 && P.nbox > 0) {
             DVec<long long> w, tot;

@@ -291,12 +291,14 @@ void fmm_m2l(const FmmCtx& c, int p, bool acc_in, const int* order, int n, const
 void mult_to_f32(const FmmCtx& c, int nbox, float* multf, hipStream_t s);
 void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n, const int* off,
                  const int* src, hipStream_t s);
-// one order class of a per-pair order policy in the precision tier: the
-// pairs at class order p (a multiple of kOrderStep below c.p, or c.p itself)
-// with their monopole part completed up to c.p (record orders 5..24)
+// record orders (5..24) at which the precision tier runs the order classes
+// of a per-pair order policy with each pair's monopole part completed up to
+// c.p inside the class (fmm_m2l_f32_classes)
 bool m2l_f32_tail_supported(int p);
-void fmm_m2l_f32_tail(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n,
-                      const int* off, const int* src, hipStream_t s);
+// the precision tier's boxes of a per-pair order policy: every order class
+// of every box in one launch (boff: class-major CSR over nbox boxes)
+void fmm_m2l_f32_classes(const FmmCtx& c, const float* multf, const int* order, int n, const int* boff,
+                         const int* bsrc, int nbox, hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 // (kappa - kappa_bar, gamma_1, gamma_2, mu) [4][m] from the Hessian [3][m]
 void lensing_from_hessian(const double* hess, int64_t m, double* out, hipStream_t s);
@@ -384,9 +386,9 @@ void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* 
                   float* label, hipStream_t s);
 // split pairs by order into CSR lists boff + q nbox over bsrc, class q
 // holding the orders in (q kOrderStep, (q + 1) kOrderStep], q < ceil(pmax /
-// kOrderStep); returns the sum of the orders squared
-long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
-                      DVec<int>& boff, DVec<int>& bsrc, hipStream_t s);
+// kOrderStep); the sum of the orders squared goes to osq (device)
+void order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
+                 DVec<int>& boff, DVec<int>& bsrc, long long* osq, hipStream_t s);
 void mlp_grad(const float* w, const float* feat, const float* label, int n, float* rec, float* grad, hipStream_t s);
 void mlp_adam(float* w, float* m, float* v, const float* grad, float lr, int step, hipStream_t s);
 void mlp_forward_f32(const float* w, const float* feat, int n, float* y, hipStream_t s);

@@ -22,8 +22,13 @@
 // i.e. a Taylor shift by b (right factor), a diagonal g^n, and a transposed
 // Taylor shift by a (left factor).  Both shifts run in place with P(P+1)/2
 // complex*real FMAs and no binomial table; a, b, g are all below ~1 for every
-// pair the MACs accept, so nothing overflows.  The n = 0 entry of the first
-// shift is sum_l' b^l' ph1^l' A_l', the series part of C'.
+// pair the MACs accept, so nothing overflows.  The kernels apply the diagonal
+// first, on the input phases ((g ph1)^l'), and then the shift by b/g: every
+// elementary step a_j += b a_{j+1} of the shift turns into g^j a_j +=
+// (b/g) g^{j+1} a_{j+1}, so D(g) T_b = T_{b/g} D(g) exactly and each
+// intermediate is the old one times g^j (no new range, one multiply per
+// coefficient fewer).  The n = 0 entry of the first shift is
+// sum_l' b^l' ph1^l' A_l', the series part of C'.
 #pragma once
 #include "dd.hpp"
 
@@ -176,6 +181,7 @@ enum TransKind { kM2M = 0, kM2L = 1, kL2L = 2 };
 struct TransGeom {
     cplx ph1, ph2;        // phase factors applied per power on input / output
     double a, b, g;       // shift parameters of the factorised T
+    double bg;            // b / g: the right shift once the diagonal g^n is applied first
     double clog;          // log cos^2(T/2) (M2M, L2L) or log sin^2(T/2) (M2L)
 };
 
@@ -215,6 +221,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = t / rho_t;
         G.b = t * rho_s;
         G.g = (rho_s / rho_t) * (1.0 + t * t);
+        G.bg = t * rho_t / (1.0 + t * t);
         G.clog = log_f64(0.25 * sum2);
     } else if (KIND == kM2L) {
         // Lemma 3: x = cot(T/2); s_T = rho_T (local), s_S = rho_S
@@ -224,6 +231,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = c * rho_t;
         G.b = c * rho_s;
         G.g = rho_t * rho_s * (1.0 + c * c);
+        G.bg = c / (rho_t * (1.0 + c * c));
         G.clog = log_f64(0.25 * dif2);
     } else {
         // Lemma 4: x = tan(T/2); s_T = rho_T (local), s_S = 1/rho_S
@@ -233,6 +241,7 @@ SFMM_HD TransGeom trans_geom(const Frame& fs, double rho_s, const Frame& ft, dou
         G.a = t * rho_t;
         G.b = t / rho_s;
         G.g = (rho_t / rho_s) * (1.0 + t * t);
+        G.bg = t / (rho_t * (1.0 + t * t));
         G.clog = log_f64(0.25 * sum2);
     }
     return G;
@@ -246,33 +255,27 @@ SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
     const double C = in[0], Q = in[1];
     ar[0] = 0.0;
     ai[0] = 0.0;
-    cplx pw = G.ph1;
+    // diagonal g^n first, on the input phases: D(g) T_b = T_{b/g} D(g)
+    const cplx pg = {G.ph1.re * G.g, G.ph1.im * G.g};
+    cplx pw = pg;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
         const cplx a = {in[2 * l], in[2 * l + 1]};
         const cplx v = cmul(pw, a);
         ar[l] = v.re;
         ai[l] = v.im;
-        pw = cmul(pw, G.ph1);
+        pw = cmul(pw, pg);
     }
-    // right factor: Taylor shift by b, a[j] += b a[j+1]
+    // right factor: Taylor shift by b/g, a[j] += (b/g) a[j+1]
 #pragma unroll
     for (int i = 0; i < P; ++i) {
 #pragma unroll
         for (int j = P - 1; j >= i; --j) {
-            ar[j] = fma(G.b, ar[j + 1], ar[j]);
-            ai[j] = fma(G.b, ai[j + 1], ai[j]);
+            ar[j] = fma(G.bg, ar[j + 1], ar[j]);
+            ai[j] = fma(G.bg, ai[j + 1], ai[j]);
         }
     }
     const double u0 = ar[0];
-    // diagonal g^n, n = 1..P
-    double gn = G.g;
-#pragma unroll
-    for (int n = 1; n <= P; ++n) {
-        ar[n] *= gn;
-        ai[n] *= gn;
-        gn *= G.g;
-    }
     // left factor: transposed Taylor shift by a on entries 1..P
 #pragma unroll
     for (int i = P - 2; i >= 0; --i) {
@@ -307,31 +310,27 @@ SFMM_HD void translate_emit(const In& in, const TransGeom& G, const Out& out) {
     const double C = in(0), Q = in(1);
     ar[0] = 0.0;
     ai[0] = 0.0;
-    cplx pw = G.ph1;
+    // the diagonal g^n moved in front of the right shift (D(g) T_b =
+    // T_{b/g} D(g)), where it rides on the input phases: (g ph1)^l
+    const cplx pg = {G.ph1.re * G.g, G.ph1.im * G.g};
+    cplx pw = pg;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
         const cplx a = {in(2 * l), in(2 * l + 1)};
         const cplx v = cmul(pw, a);
         ar[l] = v.re;
         ai[l] = v.im;
-        pw = cmul(pw, G.ph1);
+        pw = cmul(pw, pg);
     }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
 #pragma unroll
         for (int j = P - 1; j >= i; --j) {
-            ar[j] = fma(G.b, ar[j + 1], ar[j]);
-            ai[j] = fma(G.b, ai[j + 1], ai[j]);
+            ar[j] = fma(G.bg, ar[j + 1], ar[j]);
+            ai[j] = fma(G.bg, ai[j + 1], ai[j]);
         }
     }
     const double u0 = ar[0];
-    double gn = G.g;
-#pragma unroll
-    for (int n = 1; n <= P; ++n) {
-        ar[n] *= gn;
-        ai[n] *= gn;
-        gn *= G.g;
-    }
 #pragma unroll
     for (int i = P - 2; i >= 0; --i) {
 #pragma unroll
@@ -374,32 +373,27 @@ SFMM_HD void translate_add_f32_d(const float* __restrict__ A, double C, double Q
     float ar[P + 1], ai[P + 1];
     ar[0] = 0.0f;
     ai[0] = 0.0f;
-    const cplxf ph1 = {(float)G.ph1.re, (float)G.ph1.im}, ph2 = {(float)G.ph2.re, (float)G.ph2.im};
-    const float a = (float)G.a, b = (float)G.b, g = (float)G.g;
-    cplxf pw = ph1;
+    const cplxf ph2 = {(float)G.ph2.re, (float)G.ph2.im};
+    // diagonal g^n first, on the input phases: D(g) T_b = T_{b/g} D(g)
+    const float a = (float)G.a, bg = (float)G.bg;
+    const cplxf pg = {(float)(G.ph1.re * G.g), (float)(G.ph1.im * G.g)};
+    cplxf pw = pg;
 #pragma unroll
     for (int l = 1; l <= P; ++l) {
         const cplxf v = cmulf(pw, cplxf{A[2 * l - 2], A[2 * l - 1]});
         ar[l] = v.re;
         ai[l] = v.im;
-        pw = cmulf(pw, ph1);
+        pw = cmulf(pw, pg);
     }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
 #pragma unroll
         for (int j = P - 1; j >= i; --j) {
-            ar[j] = fmaf(b, ar[j + 1], ar[j]);
-            ai[j] = fmaf(b, ai[j + 1], ai[j]);
+            ar[j] = fmaf(bg, ar[j + 1], ar[j]);
+            ai[j] = fmaf(bg, ai[j + 1], ai[j]);
         }
     }
     const double u0 = (double)ar[0];
-    float gn = g;
-#pragma unroll
-    for (int n = 1; n <= P; ++n) {
-        ar[n] *= gn;
-        ai[n] *= gn;
-        gn *= g;
-    }
 #pragma unroll
     for (int i = P - 2; i >= 0; --i) {
 #pragma unroll

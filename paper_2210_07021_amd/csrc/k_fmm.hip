@@ -240,11 +240,8 @@ __global__ void k_mult_to_f32(const double* __restrict__ mult, int p, int nb, fl
 // registers (the FP32 working vector leaves room for them), and at the end
 // the team's four sums of every entry are added by two DPP lane exchanges
 // and written by the lane that owns the entry (entry k by lane k mod 4).
-// C and Q stay FP64.  P and acc_in as in k_m2l_team.  PO > P: the pairs of
-// one order class of a per-pair order policy, translated at order P with
-// their monopole part completed up to the record order PO (so no separate
-// monopole pass is needed for these boxes); entries up to PO are added.
-template <int P, int PO = P>
+// C and Q stay FP64.  P and acc_in as in k_m2l_team.
+template <int P>
 __global__ void __launch_bounds__(128) k_m2l_team_f32(FmmCtx c, const float* __restrict__ multf, const int* order,
                                                      int n, const int* off, const int* src, bool acc_in) {
     static_assert(kM2LTeamF32 == 4, "the sums below are over quads");
@@ -262,24 +259,87 @@ __global__ void __launch_bounds__(128) k_m2l_team_f32(FmmCtx c, const float* __r
     }
     double rho_t;
     const Frame ft = box_frame(c.cen, t, &rho_t);
-    double acc[2 * PO + 2];  // C, Q, then the A-block
+    double acc[2 * P + 2];  // C, Q, then the A-block
 #pragma unroll
-    for (int k = 0; k < 2 * PO + 2; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 2 * P + 2; ++k) acc[k] = 0.0;
     for (int k = k0 + r; k < k1; k += 4) {
         const int s = src[k];
         double rho_s;
         const Frame fs = box_frame(c.cen, s, &rho_s);
         const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
         const double* e = c.mult + (size_t)s * ew;
-        translate_add_f32_d<P, PO>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
+        translate_add_f32_d<P>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
     }
 #pragma unroll
-    for (int k = 0; k < 2 * PO + 2; ++k) {
+    for (int k = 0; k < 2 * P + 2; ++k) {
         const double v = quad_sum(acc[k]);
         if ((k & 3) == r) out[k] = acc_in ? out[k] + v : v;
     }
     if (!acc_in)
-        for (size_t k = 2 * PO + 2 + r; k < ew; k += 4) out[k] = 0.0;  // a first pass below the record order
+        for (size_t k = 2 * P + 2 + r; k < ew; k += 4) out[k] = 0.0;  // a first pass below the record order
+}
+
+// Precision tier Lemma 3 for a per-pair order policy in one launch: the
+// pairs of every target box come split by order class (class q holds the
+// orders in (4q, 4q + 4], the top class the record order PO; boff is the
+// class-major CSR of order_split), and each team runs its box's classes one
+// after another, the pairs of class q translated at order min(4q + 4, PO)
+// with their monopole part completed up to PO, all into the same FP64
+// running sums.  Against one launch per class this reads and writes every
+// local record once and launches once.  Writes whole records (no acc_in).
+template <int PO, int Q>
+__device__ __forceinline__ void m2l_f32_class(const FmmCtx& c, const float* __restrict__ multf, const Frame& ft,
+                                              double rho_t, const int* boff, const int* bsrc, int nbox, int t,
+                                              int r, double* acc) {
+    constexpr int P = (Q + 1) * kOrderStep < PO ? (Q + 1) * kOrderStep : PO;
+    const size_t ew = 2 * (size_t)c.p + 2, fw = 2 * (size_t)c.p;
+    const int k1 = boff[(size_t)Q * nbox + t + 1];
+    for (int k = boff[(size_t)Q * nbox + t] + r; k < k1; k += 4) {
+        const int s = bsrc[k];
+        double rho_s;
+        const Frame fs = box_frame(c.cen, s, &rho_s);
+        const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
+        const double* e = c.mult + (size_t)s * ew;
+        translate_add_f32_d<P, PO>(multf + (size_t)s * fw, e[0], e[1], G, acc + 2, acc);
+    }
+    if constexpr (P < PO) m2l_f32_class<PO, Q + 1>(c, multf, ft, rho_t, boff, bsrc, nbox, t, r, acc);
+}
+
+template <int PO>
+__global__ void __launch_bounds__(128) k_m2l_team_f32_classes(FmmCtx c, const float* __restrict__ multf,
+                                                              const int* order, int n, const int* boff,
+                                                              const int* bsrc, int nbox) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid >> 2, r = gid & 3;
+    if (i >= n) return;  // the four lanes of a team leave together
+    const int t = order[i];
+    double* out = c.local + (size_t)t * (2 * (size_t)c.p + 2);
+    double rho_t;
+    const Frame ft = box_frame(c.cen, t, &rho_t);
+    double acc[2 * PO + 2];  // C, Q, then the A-block
+#pragma unroll
+    for (int k = 0; k < 2 * PO + 2; ++k) acc[k] = 0.0;
+    m2l_f32_class<PO, 0>(c, multf, ft, rho_t, boff, bsrc, nbox, t, r, acc);
+#pragma unroll
+    for (int k = 0; k < 2 * PO + 2; ++k) {
+        const double v = quad_sum(acc[k]);
+        if ((k & 3) == r) out[k] = v;
+    }
+}
+
+void fmm_m2l_f32_classes(const FmmCtx& c, const float* multf, const int* order, int n, const int* boff,
+                         const int* bsrc, int nbox, hipStream_t s) {
+    if (n <= 0) return;
+    if (!m2l_f32_tail_supported(c.p)) throw Error(ST_INTERNAL, "record order outside the per-pair order M2L instances");
+    const unsigned g = nblk(kM2LTeamF32 * (int64_t)n, 128);
+    switch (c.p) {
+#define C_(PO) case PO: k_m2l_team_f32_classes<PO><<<g, 128, 0, s>>>(c, multf, order, n, boff, bsrc, nbox); break;
+        C_(5) C_(6) C_(7) C_(8) C_(9) C_(10) C_(11) C_(12) C_(13) C_(14)
+        C_(15) C_(16) C_(17) C_(18) C_(19) C_(20) C_(21) C_(22) C_(23) C_(24)
+#undef C_
+        default: throw Error(ST_INTERNAL, "record order outside the per-pair order M2L instances");
+    }
+    SFMM_LAUNCH_CHECK();
 }
 
 // Lemma 4: every box of one level takes its parent's local expansion
@@ -402,37 +462,6 @@ void fmm_m2l_f32(const FmmCtx& c, int p, bool acc_in, const float* multf, const 
 
 bool m2l_f32_tail_supported(int p) { return p >= 5 && p <= 24; }
 
-void fmm_m2l_f32_tail(const FmmCtx& c, int p, bool acc_in, const float* multf, const int* order, int n,
-                      const int* off, const int* src, hipStream_t s) {
-    if (n <= 0) return;
-    if (p == c.p) return fmm_m2l_f32(c, p, acc_in, multf, order, n, off, src, s);
-    if (!m2l_f32_tail_supported(c.p) || p < 1 || p > c.p || p % kOrderStep)
-        throw Error(ST_INTERNAL, "class order outside the per-pair order M2L instances");
-    const unsigned g = nblk(kM2LTeamF32 * (int64_t)n, 128);
-#define T_(P, PO)                                                                                    \
-    if (p == P && c.p == PO) {                                                                       \
-        k_m2l_team_f32<P, PO><<<g, 128, 0, s>>>(c, multf, order, n, off, src, acc_in);               \
-        SFMM_LAUNCH_CHECK();                                                                         \
-        return;                                                                                      \
-    }
-#define T4_(PO) T_(4, PO)
-#define T8_(PO) T4_(PO) T_(8, PO)
-#define T12_(PO) T8_(PO) T_(12, PO)
-#define T16_(PO) T12_(PO) T_(16, PO)
-#define T20_(PO) T16_(PO) T_(20, PO)
-    T4_(5) T4_(6) T4_(7) T4_(8)
-    T8_(9) T8_(10) T8_(11) T8_(12)
-    T12_(13) T12_(14) T12_(15) T12_(16)
-    T16_(17) T16_(18) T16_(19) T16_(20)
-    T20_(21) T20_(22) T20_(23) T20_(24)
-#undef T20_
-#undef T16_
-#undef T12_
-#undef T8_
-#undef T4_
-#undef T_
-    throw Error(ST_INTERNAL, "class order outside the per-pair order M2L instances");
-}
 
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s) {
     if (nb <= 0) return;

@@ -489,8 +489,8 @@ void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* 
     SFMM_HIP(hipStreamSynchronize(s));
 }
 
-long long order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
-                      DVec<int>& boff, DVec<int>& bsrc, hipStream_t s) {
+void order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
+                 DVec<int>& boff, DVec<int>& bsrc, long long* osq, hipStream_t s) {
     const int nq = (pmax + kOrderStep - 1) / kOrderStep;
     DVec<int> cnt, tot;
     cnt.resize((size_t)nq * nbox);
@@ -502,17 +502,12 @@ long long order_split(const int* off, const int* src, const uint8_t* ord, int nb
     scan_excl_i32(cnt.data(), boff.data(), (int64_t)nq * nbox, boff.data() + (size_t)nq * nbox, s);
     k_order_scatter<<<nblk(nbox, 256), 256, 0, s>>>(off, src, ord, nbox, nq, boff.data(), bsrc.data());
     SFMM_LAUNCH_CHECK();
-    DVec<long long> part, sum;
+    DVec<long long> part;
     const int nb = 256;
     part.resize(nb);
-    sum.resize(1);
     k_order_sq<<<nb, 256, 0, s>>>(ord, np, part.data());
     SFMM_LAUNCH_CHECK();
-    sum_i64(part.data(), nb, sum.data(), s);
-    long long h = 0;
-    SFMM_HIP(hipMemcpyAsync(&h, sum.data(), sizeof(h), hipMemcpyDeviceToHost, s));
-    SFMM_HIP(hipStreamSynchronize(s));
-    return h;
+    sum_i64(part.data(), nb, osq, s);  // left on the device: read when the statistics ask
 }
 
 }  // namespace sfmm

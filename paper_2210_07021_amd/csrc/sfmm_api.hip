@@ -142,7 +142,9 @@ struct sfmm_plan_impl {
     DVec<float4> decay;       // per-box multipole decay features
     DVec<uint8_t> m2l_ord;    // order of every FMM act (last execute)
     DVec<int> ord_off, ord_src;  // FMM acts split by order
-    long long m2l_order_sq = 0;
+    // sum of p'^2 over the FMM acts of the last execute; -1: still in osq_dev
+    mutable long long m2l_order_sq = 0;
+    DVec<long long> osq_dev;
     bool executed = false;
     // judge of the per-pair order policies (first execute of the plan)
     bool judged = false, judge_failed = false;
@@ -791,12 +793,15 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
                 order_mlp(c, P.m2l_ent.data(), P.m2l_src.data(), P.decay.data(), kt, nullptr, P.n_m2l,
                           P.mlp_w.data(), P.p, kOrderMargin, P.m2l_ord.data(), nullptr, s);
             }
-            P.m2l_order_sq = order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l,
-                                         P.p, P.ord_off, P.ord_src, s);
+            P.osq_dev.resize(1);
+            order_split(P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, P.n_m2l, P.p, P.ord_off,
+                        P.ord_src, P.osq_dev.data(), s);
+            P.m2l_order_sq = -1;
             // class q holds the orders in (4q, 4q + 4]; the top class the plan
-            // order.  The precision tier's boxes complete each pair's
-            // monopole part inside its class pass; the FP64 boxes (the first
-            // n_m2l_fp64 in box order) take it from one pass afterwards
+            // order.  The precision tier's boxes run all their classes in one
+            // launch, each pair's monopole part completed inside its class;
+            // the FP64 boxes (the first n_m2l_fp64 in box order) take one pass
+            // per class and the monopole parts from one pass afterwards
             const bool tail_in_pass = tier && m2l_f32_tail_supported(P.p);
             for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q) {
                 const int pq = std::min((q + 1) * kOrderStep, P.p);
@@ -806,9 +811,11 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
                     continue;
                 }
                 fmm_m2l(c, pq, q > 0, P.m2l_order.data(), P.n_m2l_fp64, boff, P.ord_src.data(), s);
-                fmm_m2l_f32_tail(c, pq, q > 0, multf, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
-                                 boff, P.ord_src.data(), s);
             }
+            // the precision tier's boxes: every class in one launch
+            if (tail_in_pass)
+                fmm_m2l_f32_classes(c, multf, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
+                                    P.ord_off.data(), P.ord_src.data(), P.nbox, s);
             m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(),
                       tail_in_pass ? P.n_m2l_fp64 : P.nbox, s);
         }
@@ -1195,6 +1202,8 @@ sfmm_status sfmm_stats_get(sfmm_plan_t plan, sfmm_stats* out) {
         }
         out->n_p2p_pairs = P.n_p2p_pairs < 0 ? 0 : P.n_p2p_pairs;
         out->n_m2p_evals = P.n_m2p_evals < 0 ? 0 : P.n_m2p_evals;
+        if (P.executed && P.m2l_order_sq < 0)
+            SFMM_HIP(hipMemcpy(&P.m2l_order_sq, P.osq_dev.data(), sizeof(long long), hipMemcpyDeviceToHost));
         out->m2l_order_sq = P.executed ? P.m2l_order_sq : 0;
         out->order = P.p;
         out->leaf_size = P.opt.leaf_size;

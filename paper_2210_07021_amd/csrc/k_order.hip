@@ -129,10 +129,8 @@ __global__ void k_order_bound(FmmCtx c, const int* __restrict__ ent_t, const int
 // inputs and hidden activations to bfloat16 (the network's storage format)
 // and accumulates in FP32.
 __device__ __forceinline__ float bf16_round(float v) {
-    // round to nearest even on the upper 16 bits (finite inputs)
-    unsigned u = __float_as_uint(v);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
+    // round to nearest even (v_cvt_pk_bf16_f32 on gfx950) and back
+    return (float)(__bf16)v;
 }
 
 // The network runs on the bf16 matrix cores (v_mfma_f32_32x32x8bf16_1k,
@@ -150,7 +148,7 @@ __device__ __forceinline__ float bf16_round(float v) {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ short bf16_bits(float v) { return (short)(__float_as_uint(bf16_round(v)) >> 16); }
+__device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
 
 __global__ void __launch_bounds__(256) k_order_mlp(FmmCtx c, const int* __restrict__ ent_t,
                                                    const int* __restrict__ src, const float4* __restrict__ decay,
@@ -184,64 +182,79 @@ __global__ void __launch_bounds__(256) k_order_mlp(FmmCtx c, const int* __restri
         for (int st = 0; st < 8; ++st)
 #pragma unroll
             for (int r = 0; r < 4; ++r) a2[ob][st][r] = bf16_bits(W2[(32 * ob + col) * H + 8 * st + 4 * half + r]);
-    const int64_t ntiles = (n + 31) / 32;
+    // 64 pairs per wave and step: lane l computes the features of pair l of
+    // the step once, and the two tiles of 32 pairs take the halves they lack
+    // from the partner lane l ^ 32
+    const int64_t nsteps = (n + 63) / 64;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
-        const int64_t k = tile * 32 + col;
+    for (int64_t step = wave; step < nsteps; step += nwaves) {
         float f[I];
-        if (k < n) {
-            if (feat) {
+        {
+            const int64_t k = step * 64 + lane;
+            if (k < n) {
+                if (feat) {
 #pragma unroll
-                for (int j = 0; j < I; ++j) f[j] = feat[k * I + j];
+                    for (int j = 0; j < I; ++j) f[j] = feat[k * I + j];
+                } else {
+                    pair_feature_vec(c, ent_t[k], src[k], decay, ltol, f);
+                }
             } else {
-                pair_feature_vec(c, ent_t[k], src[k], decay, ltol, f);
+#pragma unroll
+                for (int j = 0; j < I; ++j) f[j] = 0.0f;
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < I; ++j) f[j] = 0.0f;
         }
-        bf16x4 b0;
+        float fx[I];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) b0[r] = bf16_bits(half ? f[4 + r] : f[r]);
-        // layer 1 -> layer 2 operands
-        bf16x4 b1[8];
+        for (int j = 0; j < I; ++j) fx[j] = __shfl_xor(f[j], 32, 64);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            f32x16 d = {};
-            d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[rb], b0, d, 0, 0, 0);
+        for (int tile = 0; tile < 2; ++tile) {
+            // B operand of the tile: lane (col, half) holds inputs 4 half ..
+            // 4 half + 3 of pair 32 tile + col (own when half == tile)
+            bf16x4 b0;
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
+            for (int r = 0; r < 4; ++r) b0[r] = bf16_bits(half == tile ? f[4 * half + r] : fx[4 * half + r]);
+            // layer 1 -> layer 2 operands
+            bf16x4 b1[8];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float v = d[4 * g + r] + sb1[32 * rb + 8 * g + 4 * half + r];
-                    b1[4 * rb + g][r] = bf16_bits(v > 0.0f ? v : 0.0f);
+            for (int rb = 0; rb < 2; ++rb) {
+                f32x16 d = {};
+                d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[rb], b0, d, 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float v = d[4 * g + r] + sb1[32 * rb + 8 * g + 4 * half + r];
+                        b1[4 * rb + g][r] = bf16_bits(v > 0.0f ? v : 0.0f);
+                    }
+            }
+            // layer 2, layer 3
+            float y = 0.0f;
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+                f32x16 d = {};
+#pragma unroll
+                for (int st = 0; st < 8; ++st)
+                    d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][st], b1[st], d, 0, 0, 0);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int u = 32 * ob + 8 * g + 4 * half + r;
+                        const float v = d[4 * g + r] + sb2[u];
+                        y = fmaf(sw3[u], bf16_round(v > 0.0f ? v : 0.0f), y);
+                    }
+            }
+            y += __shfl_xor(y, 32, 64);
+            y += sw3[H];
+            const int64_t k = step * 64 + 32 * tile + col;
+            if (half == tile && k < n) {
+                if (yout) yout[k] = y;
+                if (ord) {
+                    const float pf = kOrderCenter + kOrderScale * y + margin;
+                    const int p = pf >= (float)pmax ? pmax : (pf <= 1.0f ? 1 : (int)ceilf(pf));
+                    ord[k] = (uint8_t)round_order(p, pmax);
                 }
-        }
-        // layer 2, layer 3
-        float y = 0.0f;
-#pragma unroll
-        for (int ob = 0; ob < 2; ++ob) {
-            f32x16 d = {};
-#pragma unroll
-            for (int st = 0; st < 8; ++st) d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][st], b1[st], d, 0, 0, 0);
-#pragma unroll
-            for (int g = 0; g < 4; ++g)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int u = 32 * ob + 8 * g + 4 * half + r;
-                    const float v = d[4 * g + r] + sb2[u];
-                    y = fmaf(sw3[u], bf16_round(v > 0.0f ? v : 0.0f), y);
-                }
-        }
-        y += __shfl_xor(y, 32, 64);
-        y += sw3[H];
-        if (half == 0 && k < n) {
-            if (yout) yout[k] = y;
-            if (ord) {
-                const float pf = kOrderCenter + kOrderScale * y + margin;
-                const int p = pf >= (float)pmax ? pmax : (pf <= 1.0f ? 1 : (int)ceilf(pf));
-                ord[k] = (uint8_t)round_order(p, pmax);
             }
         }
     }
@@ -464,8 +477,8 @@ void order_mlp(const FmmCtx& c, const int* ent_t, const int* src, const float4* 
                const float* feat, int64_t n, const float* w, int pmax, float margin, uint8_t* ord, float* y,
                hipStream_t s) {
     if (n <= 0) return;
-    // one wave per 32 pairs, a few tiles per wave
-    const int64_t waves = std::min<int64_t>((n + 31) / 32, 4096 * 4);
+    // one wave per 64 pairs, a few steps per wave
+    const int64_t waves = std::min<int64_t>((n + 63) / 64, 4096 * 4);
     k_order_mlp<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(c, ent_t, src, decay, (float)log10(kappa_tol), feat, n,
                                                             w, pmax, margin, ord, y);
     SFMM_LAUNCH_CHECK();

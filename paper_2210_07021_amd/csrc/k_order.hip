@@ -347,25 +347,43 @@ __global__ void k_order_labels(FmmCtx c, const int* __restrict__ ent_t, const in
     label[i] = (float)best;
 }
 
+// Sum over the four lanes of a quad (lanes 4i .. 4i + 3), every lane getting
+// (v0 + v1) + (v2 + v3): DPP quad permutations (all four lanes active).
+template <int CTRL>
+__device__ __forceinline__ double tail_dpp(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double tail_quad_sum(double v) {
+    v += tail_dpp<0xB1>(v);        // lane ^ 1
+    return v + tail_dpp<0x4E>(v);  // lane ^ 2
+}
+
 // The monopole part of the local coefficients above each pair's order:
-// A'_l += e^(-i l phi_S^(T)) (-(Q/l) a^l) for ord < l <= p (c.p), one lane per
-// target box over its whole list, added to the record once.
+// A'_l += e^(-i l phi_S^(T)) (-(Q/l) a^l) for ord < l <= p (c.p).  Four
+// lanes per target box (lane r takes entries r, r + 4, ... of its list),
+// their sums added across the quad in a fixed order and written by the lane
+// that owns the entry (entry l by lane l mod 4), once per record.
 template <int P>
 __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restrict__ off,
                                                   const int* __restrict__ src, const uint8_t* __restrict__ ord,
                                                   int nbox) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nbox) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gid >> 2, r = gid & 3;
+    if (t >= nbox) return;  // the four lanes of a box leave together
     const int k0 = off[t], k1 = off[t + 1];
     bool any = false;
-    for (int k = k0; k < k1; ++k) any |= ord[k] < P;
+    for (int k = k0 + r; k < k1; k += 4) any |= ord[k] < P;
+    // every lane of the quad takes the same branch
+    any = tail_quad_sum(any ? 1.0 : 0.0) > 0.0;
     if (!any) return;
     const double* ct = c.cen + 4 * (size_t)t;
     const Frame ft = make_frame(ct[0], ct[1], ct[2]);
     double acc[2 * P];
 #pragma unroll
     for (int l = 0; l < 2 * P; ++l) acc[l] = 0.0;
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0 + r; k < k1; k += 4) {
         const int lo = ord[k];
         if (lo >= P) continue;
         const int s = src[k];
@@ -402,7 +420,10 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
     }
     double* out = c.local + (size_t)t * (2 * P + 2);
 #pragma unroll
-    for (int l = 0; l < 2 * P; ++l) out[2 + l] += acc[l];
+    for (int l = 0; l < 2 * P; ++l) {
+        const double v = tail_quad_sum(acc[l]);
+        if ((l & 3) == r) out[2 + l] += v;
+    }
 }
 
 // ------------------------------------------------------------ split by order
@@ -413,43 +434,53 @@ __global__ void __launch_bounds__(128) k_m2l_qtail(FmmCtx c, const int* __restri
 constexpr int kMaxQ = (kMaxOrder + kOrderStep - 1) / kOrderStep;
 __device__ __forceinline__ int order_class(int o) { return (o + kOrderStep - 1) / kOrderStep - 1; }
 __global__ void __launch_bounds__(256) k_order_count(const int* __restrict__ off, const uint8_t* __restrict__ ord,
-                                                     int nbox, int nq, int* __restrict__ cnt) {
+                                                     int nbox, int nq, int* __restrict__ cnt,
+                                                     long long* __restrict__ psq) {
     __shared__ int c[kMaxQ][256];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = 0; q < nq; ++q) c[q][threadIdx.x] = 0;
     if (t >= nbox) return;
-    for (int k = off[t]; k < off[t + 1]; ++k) ++c[order_class(ord[k])][threadIdx.x];
+    long long sq = 0;  // sum of p'^2 over the box's pairs (M2L work against p^2)
+    for (int k = off[t]; k < off[t + 1]; ++k) {
+        const int o = ord[k];
+        ++c[order_class(o)][threadIdx.x];
+        sq += o * o;
+    }
     for (int q = 0; q < nq; ++q) cnt[(size_t)q * nbox + t] = c[q][threadIdx.x];
+    psq[t] = sq;
 }
 
 // stable scatter of each box's entries into the list of their order; boff
 // is the exclusive scan of cnt (so the lists of order q are the CSR boff +
-// q nbox, with absolute offsets into bsrc)
+// q nbox, with absolute offsets into bsrc).  A wave per box: the lanes take
+// 64 consecutive entries at a time, and an entry's rank among the earlier
+// entries of its class is the count of lower lanes of the same class (a
+// ballot per class) plus those of the earlier groups.
 __global__ void __launch_bounds__(256) k_order_scatter(const int* __restrict__ off, const int* __restrict__ src,
                                                        const uint8_t* __restrict__ ord, int nbox, int nq,
                                                        const int* __restrict__ boff, int* __restrict__ bsrc) {
-    __shared__ int pos[kMaxQ][256];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nbox) return;
-    for (int q = 0; q < nq; ++q) pos[q][threadIdx.x] = boff[(size_t)q * nbox + t];
-    for (int k = off[t]; k < off[t + 1]; ++k) {
-        const int q = order_class(ord[k]);
-        bsrc[pos[q][threadIdx.x]++] = src[k];
+    const int t = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (t >= nbox) return;  // the whole wave leaves together
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
+    int base[kMaxQ];  // unrolled over every class so that it stays in registers
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) base[q] = q < nq ? boff[(size_t)q * nbox + t] : 0;
+    const int k1 = off[t + 1];
+    for (int k0 = off[t]; k0 < k1; k0 += 64) {
+        const int k = k0 + lane;
+        const bool live = k < k1;
+        const int mine = live ? order_class(ord[k]) : -1;
+        int slot = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q) {
+            if (q >= nq) break;
+            const uint64_t m = __ballot(mine == q);
+            if (mine == q) slot = base[q] + __popcll(m & below);
+            base[q] += __popcll(m);
+        }
+        if (live) bsrc[slot] = src[k];
     }
-}
-
-// sum of p'^2 over the pairs (work of the bucketed M2L relative to p^2)
-__global__ void k_order_sq(const uint8_t* __restrict__ ord, int np, long long* __restrict__ part) {
-    __shared__ long long sh[256];
-    long long v = 0;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < np; k += gridDim.x * 256) v += (long long)ord[k] * ord[k];
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 // ------------------------------------------------------------ host side
@@ -486,7 +517,7 @@ void order_mlp(const FmmCtx& c, const int* ent_t, const int* src, const float4* 
 
 void m2l_qtail(const FmmCtx& c, const int* off, const int* src, const uint8_t* ord, int nbox, hipStream_t s) {
     if (nbox <= 0) return;
-#define L_(P) case P: k_m2l_qtail<P><<<nblk(nbox, 128), 128, 0, s>>>(c, off, src, ord, nbox); break;
+#define L_(P) case P: k_m2l_qtail<P><<<nblk(4 * (int64_t)nbox, 128), 128, 0, s>>>(c, off, src, ord, nbox); break;
     SFMM_DISPATCH(c.p, L_)
 #undef L_
     SFMM_LAUNCH_CHECK();
@@ -505,22 +536,19 @@ void order_labels(const FmmCtx& c, const int* ent_t, const int* src, const int* 
 void order_split(const int* off, const int* src, const uint8_t* ord, int nbox, int np, int pmax,
                  DVec<int>& boff, DVec<int>& bsrc, long long* osq, hipStream_t s) {
     const int nq = (pmax + kOrderStep - 1) / kOrderStep;
-    DVec<int> cnt, tot;
+    if (nq > kMaxQ) throw Error(ST_INTERNAL, "more order classes than the split holds");
+    DVec<int> cnt;
+    DVec<long long> psq;
     cnt.resize((size_t)nq * nbox);
+    psq.resize(std::max(nbox, 1));
     boff.resize((size_t)nq * nbox + 1);
     bsrc.resize(std::max(np, 1));
-    tot.resize(1);
-    k_order_count<<<nblk(nbox, 256), 256, 0, s>>>(off, ord, nbox, nq, cnt.data());
+    k_order_count<<<nblk(nbox, 256), 256, 0, s>>>(off, ord, nbox, nq, cnt.data(), psq.data());
     SFMM_LAUNCH_CHECK();
     scan_excl_i32(cnt.data(), boff.data(), (int64_t)nq * nbox, boff.data() + (size_t)nq * nbox, s);
-    k_order_scatter<<<nblk(nbox, 256), 256, 0, s>>>(off, src, ord, nbox, nq, boff.data(), bsrc.data());
+    k_order_scatter<<<nblk(64 * (int64_t)nbox, 256), 256, 0, s>>>(off, src, ord, nbox, nq, boff.data(), bsrc.data());
     SFMM_LAUNCH_CHECK();
-    DVec<long long> part;
-    const int nb = 256;
-    part.resize(nb);
-    k_order_sq<<<nb, 256, 0, s>>>(ord, np, part.data());
-    SFMM_LAUNCH_CHECK();
-    sum_i64(part.data(), nb, osq, s);  // left on the device: read when the statistics ask
+    sum_i64(psq.data(), nbox, osq, s);  // left on the device: read when the statistics ask
 }
 
 }  // namespace sfmm

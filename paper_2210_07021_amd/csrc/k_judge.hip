@@ -13,8 +13,9 @@
 // combined over the lanes, and written as (sum, compensation) pairs.  A
 // second kernel adds the chunks in double-double in a fixed order, so the
 // result is exact to rounding of the final sum and bitwise reproducible.  The
-// log and reciprocal are the library's own (log_f64: ~2 ulp), far below the
-// tolerances the judge checks.
+// log and reciprocal are the pair loop's table-driven ones (log_recip_tab: a
+// few 1e-16 absolute, the reciprocal correctly rounded on every input
+// measured), far below the tolerances the judge checks.
 #include "common.hpp"
 #include "expand.hpp"
 
@@ -42,9 +43,11 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 // target are then combined in lane order (deterministic).
 __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* __restrict__ spt, int n,
                                                                  const double4* __restrict__ tsel, int S,
-                                                                 int lanes, double* __restrict__ part) {
+                                                                 int lanes, LogPoly lk, double* __restrict__ part) {
     __shared__ double4 tile[kJudgeThreads];
     __shared__ double red[kJudgeThreads][8];
+    __shared__ double2 ltab[kLogTab];
+    for (int j = threadIdx.x; j < kLogTab; j += kJudgeThreads) ltab[j] = log_tab_entry(j);
     const int tpb = kJudgeThreads / lanes;  // targets per pass
     const int j = blockIdx.x;
     const int s0 = j * kJudgeChunk, s1 = min(n, s0 + kJudgeChunk);
@@ -63,8 +66,10 @@ __global__ void __launch_bounds__(kJudgeThreads) k_judge_chunks(const double4* _
                 const double dx = tp.x - sr.x, dy = tp.y - sr.y, dz = tp.z - sr.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 == 0.0) continue;  // a source at the target itself is left out
-                neumaier(sp, cp, sr.w * kInv4Pi * log_f64(0.25 * r2));
-                const double f = sr.w * kInv2Pi * recip(r2);
+                double lg, inv;  // log(r2 / 4) and 4 / r2
+                log_recip_tab(0.25 * r2, ltab, lk, &lg, &inv);
+                neumaier(sp, cp, sr.w * kInv4Pi * lg);
+                const double f = sr.w * (0.25 * kInv2Pi) * inv;
                 neumaier(sx, cx, f * dx);
                 neumaier(sy, cy, f * dy);
                 neumaier(sz, cz, f * dz);
@@ -174,7 +179,7 @@ void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const do
     if (n > 0) {
         int tpb = 64;  // targets per pass: the smallest power of two >= S, at most 64
         while (tpb > 1 && tpb / 2 >= S) tpb /= 2;
-        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, kJudgeThreads / tpb, part);
+        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, kJudgeThreads / tpb, kLogPoly, part);
         SFMM_LAUNCH_CHECK();
     } else {
         fill_f64(part, (size_t)S * 8, 0.0, s);

@@ -358,15 +358,19 @@ void ray_step(double* rays, const double* defl, const double* hess, double w, in
               hipStream_t s);
 
 // ---------------------------------------------------------------- judge
-// Direct sum at S targets of the plan (sorted positions pos[S]) over the n
-// sorted sources, FP64 with compensated sums: ref [S][4] = (psi + shift,
-// alpha x, y, z); got [S][4] the library's outputs psi/defl (caller order,
-// m targets) at the same targets; tsel [S] and part [judge_part_doubles]
-// are scratch.
+// Direct sum at S targets of the caller (caller-order positions pos[S]) over
+// the n sorted sources, FP64 with compensated sums, in three steps:
+// judge_targets gathers the targets from the caller's tgt [3][m] (unit
+// vectors as the plan makes them) into tsel [S]; judge_sum writes the
+// per-chunk sums part [judge_part_doubles] (it needs only the sorted sources,
+// so the plan runs it beside its own later stages); judge_outputs gives ref
+// [S][4] = (psi + shift, alpha x, y, z) from part and got [S][4] = the
+// library's outputs psi/defl (caller order, m targets) there.
 size_t judge_part_doubles(int64_t n, int S);
-void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const double* tx, const double* ty,
-                  const double* tz, const uint32_t* tperm, const double* psi, const double* defl, int64_t m,
-                  double shift, double4* tsel, double* part, double* ref, double* got, hipStream_t s);
+void judge_targets(const int* pos, int S, const double* tgt, int64_t m, double4* tsel, hipStream_t s);
+void judge_sum(const double4* spt, int64_t n, const double4* tsel, int S, double* part, hipStream_t s);
+void judge_outputs(const int* pos, int S, const double4* tsel, const double* part, int64_t n, double shift,
+                   const double* psi, const double* defl, int64_t m, double* ref, double* got, hipStream_t s);
 
 // ---------------------------------------------------------------- order policies
 void entry_box(const int* off, int nbox, int np, int* ent_t, hipStream_t s);

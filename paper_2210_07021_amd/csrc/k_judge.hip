@@ -145,18 +145,31 @@ __global__ void __launch_bounds__(64) k_judge_finish(const double* __restrict__ 
     out[4 * t + 3] = v[3] - nd * tp.z;
 }
 
-// The subset: sorted target positions pos[k] -> their coordinates and the
-// library's outputs there (caller order through tperm)
-__global__ void k_judge_gather(const int* __restrict__ pos, int S, const double* __restrict__ tx,
-                               const double* __restrict__ ty, const double* __restrict__ tz,
-                               const uint32_t* __restrict__ tperm, const double* __restrict__ psi,
-                               const double* __restrict__ defl, int64_t m, double4* __restrict__ tsel,
-                               double* __restrict__ got) {
+// The subset: caller-order target positions pos[k] -> their coordinates,
+// unit vectors exactly as the plan makes them (renormalised when off the
+// sphere by more than 1e-14)
+__global__ void k_judge_gather_tgt(const int* __restrict__ pos, int S, const double* __restrict__ tgt, int64_t m,
+                                   double4* __restrict__ tsel) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S) return;
-    const int j = pos[k];
-    tsel[k] = make_double4(tx[j], ty[j], tz[j], 0.0);
-    const int64_t i = tperm[j];
+    const int64_t j = pos[k];
+    double a = tgt[j], b = tgt[m + j], c = tgt[2 * m + j];
+    const double r2 = a * a + b * b + c * c;
+    if (fabs(r2 - 1.0) > 1e-14) {
+        const double inv = 1.0 / sqrt(r2);
+        a *= inv;
+        b *= inv;
+        c *= inv;
+    }
+    tsel[k] = make_double4(a, b, c, 0.0);
+}
+
+// the library's outputs (caller order) at the subset
+__global__ void k_judge_gather_out(const int* __restrict__ pos, int S, const double* __restrict__ psi,
+                                   const double* __restrict__ defl, int64_t m, double* __restrict__ got) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= S) return;
+    const int64_t i = pos[k];
     got[4 * k + 0] = psi[i];
     got[4 * k + 1] = defl[i];
     got[4 * k + 2] = defl[m + i];
@@ -169,21 +182,31 @@ size_t judge_part_doubles(int64_t n, int S) {
     return (size_t)std::max<int64_t>(nchunk, 1) * (size_t)S * 8;
 }
 
-void judge_direct(const double4* spt, int64_t n, const int* pos, int S, const double* tx, const double* ty,
-                  const double* tz, const uint32_t* tperm, const double* psi, const double* defl, int64_t m,
-                  double shift, double4* tsel, double* part, double* ref, double* got, hipStream_t s) {
+void judge_targets(const int* pos, int S, const double* tgt, int64_t m, double4* tsel, hipStream_t s) {
     if (S <= 0) return;
-    k_judge_gather<<<(S + 255) / 256, 256, 0, s>>>(pos, S, tx, ty, tz, tperm, psi, defl, m, tsel, got);
+    k_judge_gather_tgt<<<(S + 255) / 256, 256, 0, s>>>(pos, S, tgt, m, tsel);
+    SFMM_LAUNCH_CHECK();
+}
+
+void judge_sum(const double4* spt, int64_t n, const double4* tsel, int S, double* part, hipStream_t s) {
+    if (S <= 0) return;
+    if (n <= 0) {
+        fill_f64(part, (size_t)S * 8, 0.0, s);
+        return;
+    }
+    const int nchunk = (int)((n + kJudgeChunk - 1) / kJudgeChunk);
+    int tpb = 64;  // targets per pass: the smallest power of two >= S, at most 64
+    while (tpb > 1 && tpb / 2 >= S) tpb /= 2;
+    k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, kJudgeThreads / tpb, kLogPoly, part);
+    SFMM_LAUNCH_CHECK();
+}
+
+void judge_outputs(const int* pos, int S, const double4* tsel, const double* part, int64_t n, double shift,
+                   const double* psi, const double* defl, int64_t m, double* ref, double* got, hipStream_t s) {
+    if (S <= 0) return;
+    k_judge_gather_out<<<(S + 255) / 256, 256, 0, s>>>(pos, S, psi, defl, m, got);
     SFMM_LAUNCH_CHECK();
     const int nchunk = (int)std::max<int64_t>((n + kJudgeChunk - 1) / kJudgeChunk, 1);
-    if (n > 0) {
-        int tpb = 64;  // targets per pass: the smallest power of two >= S, at most 64
-        while (tpb > 1 && tpb / 2 >= S) tpb /= 2;
-        k_judge_chunks<<<nchunk, kJudgeThreads, 0, s>>>(spt, (int)n, tsel, S, kJudgeThreads / tpb, kLogPoly, part);
-        SFMM_LAUNCH_CHECK();
-    } else {
-        fill_f64(part, (size_t)S * 8, 0.0, s);
-    }
     k_judge_finish<<<S, 64, 0, s>>>(part, nchunk, tsel, S, shift, ref);
     SFMM_LAUNCH_CHECK();
 }

@@ -149,6 +149,10 @@ struct sfmm_plan_impl {
     // judge of the per-pair order policies (first execute of the plan)
     bool judged = false, judge_failed = false;
     int judge_S = 0;
+    DVec<int> judge_pos;       // the judge's targets (caller order)
+    DVec<double4> judge_tsel;  // their unit vectors
+    DVec<double> judge_part;   // their direct sum per source chunk (computed by the plan)
+    bool judge_ready = false;
     double judge_psi = -1.0, judge_alpha = -1.0;
     std::unique_ptr<Pinned> pin;
     // recorded at the end of every sfmm_plan / sfmm_execute on the caller's
@@ -855,42 +859,109 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
 
 constexpr int kJudgeDefault = 32;
 
-// The judge: psi and alpha of the last execute at S seeded targets against
-// their direct sum; sets P.judge_psi / judge_alpha (relative L2 errors).
-void run_judge(sfmm_plan_impl& P, const double* psi, const double* defl, hipStream_t s) {
-    const int S = (int)std::min<int64_t>(P.M, P.opt.judge_targets > 0 ? P.opt.judge_targets : kJudgeDefault);
-    P.judge_S = S;
-    if (S <= 0) {
-        P.judge_psi = P.judge_alpha = 0.0;
-        return;
-    }
-    // distinct sorted target positions from a counter-based generator
-    // (splitmix64), seeded by the plan's sizes
+// The judge's S targets: distinct caller-order positions from a
+// counter-based generator (splitmix64), seeded by the plan's sizes
+std::vector<int> judge_positions(int64_t N, int64_t M, int S) {
     std::vector<int> pos;
-    std::vector<char> taken((size_t)P.M, 0);
+    std::vector<char> taken((size_t)M, 0);
     for (uint64_t i = 0; (int)pos.size() < S; ++i) {
-        uint64_t z = 0x2210070210ULL + (uint64_t)P.N * 0x9e3779b97f4a7c15ULL + 0x9e3779b97f4a7c15ULL * (i + 1);
+        uint64_t z = 0x2210070210ULL + (uint64_t)N * 0x9e3779b97f4a7c15ULL + 0x9e3779b97f4a7c15ULL * (i + 1);
         z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
         z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
         z ^= z >> 31;
-        const int64_t j = (int64_t)(z % (uint64_t)P.M);
+        const int64_t j = (int64_t)(z % (uint64_t)M);
         if (!taken[j]) {
             taken[j] = 1;
             pos.push_back((int)j);
         }
     }
-    DVec<int> dpos;
-    DVec<double4> tsel;
-    DVec<double> part, ref, got;
-    dpos.resize(S);
-    tsel.resize(S);
-    part.resize(judge_part_doubles(P.N, S));
+    return pos;
+}
+
+// Second streams for the judge's direct sum during planning: created on
+// first use per device (non-blocking, default priority) and kept for the
+// life of the process; a plan takes one and gives it back when it ends.
+struct SideStream {
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+std::vector<SideStream*> g_side_free;
+
+SideStream* side_acquire() {
+    int dev = 0;
+    SFMM_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        for (size_t k = 0; k < g_side_free.size(); ++k)
+            if (g_side_free[k]->dev == dev) {
+                SideStream* w = g_side_free[k];
+                g_side_free.erase(g_side_free.begin() + k);
+                return w;
+            }
+    }
+    std::unique_ptr<SideStream> w(new SideStream());
+    w->dev = dev;
+    SFMM_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+    SFMM_HIP(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    SFMM_HIP(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
+    return w.release();
+}
+
+// Holds a plan's second stream: end() makes the plan's stream wait for the
+// judge's sum; the destructor (also on an error inside the plan) waits for
+// the second stream before the plan's buffers can go, and returns it.
+struct JudgeOverlap {
+    SideStream* w = nullptr;
+    void end(hipStream_t s) {
+        if (w) SFMM_HIP(hipStreamWaitEvent(s, w->join, 0));
+    }
+    ~JudgeOverlap() {
+        if (!w) return;
+        (void)hipStreamSynchronize(w->stream);
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        g_side_free.push_back(w);
+    }
+};
+
+// Plan-time half of the judge (per-pair order policies): its targets, and
+// their direct sum over the sorted sources on a second stream beside the
+// rest of the plan.
+void judge_start(sfmm_plan_impl& P, const double* tgt, JudgeOverlap& ov, hipStream_t s) {
+    const int S = (int)std::min<int64_t>(P.M, P.opt.judge_targets > 0 ? P.opt.judge_targets : kJudgeDefault);
+    P.judge_S = S;
+    if (S <= 0) return;
+    const std::vector<int> pos = judge_positions(P.N, P.M, S);
+    P.judge_pos.resize(S);
+    P.judge_tsel.resize(S);
+    P.judge_part.resize(judge_part_doubles(P.N, S));
+    SFMM_HIP(hipMemcpyAsync(P.judge_pos.data(), pos.data(), sizeof(int) * S, hipMemcpyHostToDevice, s));
+    judge_targets(P.judge_pos.data(), S, tgt, P.M, P.judge_tsel.data(), s);
+    ov.w = side_acquire();
+    SFMM_HIP(hipEventRecord(ov.w->fork, s));
+    SFMM_HIP(hipStreamWaitEvent(ov.w->stream, ov.w->fork, 0));
+    judge_sum(P.spt.data(), P.N, P.judge_tsel.data(), S, P.judge_part.data(), ov.w->stream);
+    SFMM_HIP(hipEventRecord(ov.w->join, ov.w->stream));
+    P.judge_ready = true;
+}
+
+// The judge: psi and alpha of the last execute at the plan's S judge
+// targets against their direct sum; sets P.judge_psi / judge_alpha
+// (relative L2 errors).
+void run_judge(sfmm_plan_impl& P, const double* psi, const double* defl, hipStream_t s) {
+    const int S = P.judge_S;
+    if (S <= 0) {
+        P.judge_psi = P.judge_alpha = 0.0;
+        return;
+    }
+    if (!P.judge_ready) throw Error(ST_INTERNAL, "the judge's direct sum was not started by the plan");
+    DVec<double> ref, got;
     ref.resize(4 * (size_t)S);
     got.resize(4 * (size_t)S);
-    SFMM_HIP(hipMemcpyAsync(dpos.data(), pos.data(), sizeof(int) * S, hipMemcpyHostToDevice, s));
     const double shift = (P.opt.psi_gauge == SFMM_GAUGE_RAW) ? 0.0 : P.q_total * 0.079577471545947667884;
-    judge_direct(P.spt.data(), P.N, dpos.data(), S, P.tx.data(), P.ty.data(), P.tz.data(), P.tperm.data(), psi,
-                 defl, P.M, shift, tsel.data(), part.data(), ref.data(), got.data(), s);
+    judge_outputs(P.judge_pos.data(), S, P.judge_tsel.data(), P.judge_part.data(), P.N, shift, psi, defl, P.M,
+                  ref.data(), got.data(), s);
     std::vector<double> hr(4 * (size_t)S), hg(4 * (size_t)S);
     SFMM_HIP(hipMemcpyAsync(hr.data(), ref.data(), sizeof(double) * 4 * S, hipMemcpyDeviceToHost, s));
     SFMM_HIP(hipMemcpyAsync(hg.data(), got.data(), sizeof(double) * 4 * S, hipMemcpyDeviceToHost, s));
@@ -969,6 +1040,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         hipStream_t s = (hipStream_t)stream;
         PoolStream ps(s);
         std::unique_ptr<sfmm_plan_impl> P(new sfmm_plan_impl());
+        JudgeOverlap ov;  // after P: on any exit it waits for the judge's stream before P goes
         P->pin.reset(new Pinned());
         P->opt = o;
         P->p = o.order > 0 ? o.order : order_for_tolerance(o.tolerance);
@@ -986,6 +1058,9 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
             SFMM_HIP(hipMemcpyAsync(&P->q_total, qt.data(), sizeof(double), hipMemcpyDeviceToHost, s));
             SFMM_HIP(hipStreamSynchronize(s));
         }
+        // per-pair order policies: the judge's direct sum needs only the
+        // sorted sources, so it runs beside the tree, the walk and the targets
+        if (o.order_policy != SFMM_ORDER_FIXED && o.judge_targets >= 0 && M > 0) judge_start(*P, tgt, ov, s);
         build_tree(*P, s, prof);
         build_lists(*P, s, prof);
         {
@@ -1004,6 +1079,7 @@ sfmm_status sfmm_plan(const double* src, const double* q, int64_t N, const doubl
         P->local.resize(ne);
         P->zrec.resize(2 * (size_t)P->p + 2);
         fill_f64(P->zrec.data(), 2 * (size_t)P->p + 2, 0.0, s);
+        ov.end(s);
         SFMM_HIP(hipStreamSynchronize(s));
         P->mark_done(s);
         *out = P.release();

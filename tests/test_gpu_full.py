@@ -88,3 +88,51 @@ def test_two_lane_m2l_fixed_and_per_pair_orders(oracle_lib):
         assert st["fell_back"] == 0
         check(f"two-lane M2L clustered-1e6 leaf 12 policy {policy} p={st['order']} boxes={st['n_boxes']}",
               psi[idx], defl[:, idx], ref_p, ref_a, tol)
+
+
+@pytest.mark.timeout(600)
+def test_learned_tier_beats_plain_fp64_in_wall_time(oracle_lib):
+    """Wall time, not counted work: on clustered-1e7 at the bench's leaf size,
+    plan + execute of the precision tier with the learned per-pair order at
+    tolerance 1e-6 (judge included) is faster than plan + execute of the
+    plain FP64 sFMM at 1e-10, and meets 1e-6 against the oracle on the seeded
+    1e4-target subset.  Best of three timed runs each (one untimed first)."""
+    import time
+    import torch
+    import paper_2210_07021_amd as sf
+    from paper_2210_07021_amd import learn
+    src, q, tgt, idx, (ref_p, ref_a) = _sky_and_reference("clustered-1e7")
+    f_tr, l_tr = learn.order_training_data([skies.workload("clustered-1e6")], 1e-6, leaf_size=56,
+                                           samples_per_sky=60000, seed=1)
+    w_net, _ = learn.train_order_network(f_tr, l_tr, epochs=30)
+    srcd = torch.from_numpy(src).cuda()
+    qd = torch.from_numpy(q).cuda()
+    tgtd = torch.from_numpy(tgt).cuda()
+
+    def best(**opt):
+        times, out = [], None
+        for k in range(4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan = sf.Plan(srcd, qd, tgtd, leaf_size=56, **opt)
+            psi, defl = plan.execute()
+            torch.cuda.synchronize()
+            if k:
+                times.append(time.perf_counter() - t)
+            st = plan.stats()
+            plan.close()
+            out = (psi, defl, st)
+        return min(times), out
+
+    t64, _ = best(tolerance=1e-10)
+    tl, (psi, defl, st) = best(tolerance=1e-6, precision=sf.SFMM_FP32_MIXED, order_policy=sf.SFMM_ORDER_LEARNED,
+                               mlp_weights=w_net)
+    M = tgt.shape[1]
+    print(f"[full] wall time: FP64 at 1e-10 {1e3 * t64:.2f} ms ({M / t64 / 1e6:.0f} M targets/s), learned "
+          f"precision tier at 1e-6 {1e3 * tl:.2f} ms ({M / tl / 1e6:.0f} M targets/s), M2L work "
+          f"{st['m2l_order_sq'] / (st['n_m2l'] * st['order'] ** 2):.3f} of fixed, fell back {st['fell_back']}",
+          flush=True)
+    assert st["fell_back"] == 0
+    check("full clustered-1e7 learned precision tier", psi.cpu().numpy()[idx], defl.cpu().numpy()[:, idx], ref_p,
+          ref_a, 1e-6)
+    assert tl < t64

@@ -299,6 +299,9 @@ bool m2l_f32_tail_supported(int p);
 // of every box in one launch (boff: class-major CSR over nbox boxes)
 void fmm_m2l_f32_classes(const FmmCtx& c, const float* multf, const int* order, int n, const int* boff,
                          const int* bsrc, int nbox, hipStream_t s);
+// and its FP64 boxes (the coarse levels), likewise in one launch
+void fmm_m2l_f64_classes(const FmmCtx& c, const int* order, int n, const int* boff, const int* bsrc, int nbox,
+                         hipStream_t s);
 void fmm_l2l(const FmmCtx& c, int b0, int nb, hipStream_t s);
 // (kappa - kappa_bar, gamma_1, gamma_2, mu) [4][m] from the Hessian [3][m]
 void lensing_from_hessian(const double* hess, int64_t m, double* out, hipStream_t s);

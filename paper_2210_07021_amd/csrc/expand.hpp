@@ -301,6 +301,33 @@ SFMM_HD void translate_add(const double* in, const TransGeom& G, double* acc) {
     acc[1] += Q;
 }
 
+// translate_add for one order class of a per-pair order policy: the pair's
+// multipole part translated at order P, its monopole part (-(Q/l) a^l, the
+// source as a point mass) completed up to the record order PO; acc holds
+// 2 PO + 2 entries.
+template <int P, int PO>
+SFMM_HD void translate_add_po(const double* in, const TransGeom& G, double* acc) {
+    translate_add<P>(in, G, acc);
+    if constexpr (PO > P) {
+        const double Q = in[1];
+        cplx pw2 = G.ph2;
+        double an = G.a;
+#pragma unroll
+        for (int l = 1; l <= P; ++l) {  // powers up to P
+            pw2 = cmul(pw2, G.ph2);
+            an *= G.a;
+        }
+#pragma unroll
+        for (int l = P + 1; l <= PO; ++l) {
+            const double v = -Q * (1.0 / l) * an;
+            acc[2 * l] = fma(pw2.re, v, acc[2 * l]);
+            acc[2 * l + 1] = fma(pw2.im, v, acc[2 * l + 1]);
+            pw2 = cmul(pw2, G.ph2);
+            an *= G.a;
+        }
+    }
+}
+
 // translate_add without an accumulator: in(k) gives input entry k and
 // out(k, v) takes output entry k as soon as it is formed (entries 2..2P+1 in
 // order, then C and Q), for kernels with one translation per lane.  Without

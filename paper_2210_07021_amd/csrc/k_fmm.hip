@@ -342,6 +342,64 @@ void fmm_m2l_f32_classes(const FmmCtx& c, const float* multf, const int* order, 
     SFMM_LAUNCH_CHECK();
 }
 
+// The FP64 boxes of the precision tier (its coarse levels) under a per-pair
+// order policy, every order class in one launch: four lanes per box, each
+// lane holding the box's whole accumulator in registers (two waves per SIMD
+// at the tier's orders), running the box's classes one after another (class
+// q at order min(4q + 4, PO), each pair's monopole part completed to PO), the
+// four sums of every entry added across the quad at the end.  Writes whole
+// records.
+template <int PO, int Q>
+__device__ __forceinline__ void m2l_f64_class(const FmmCtx& c, const Frame& ft, double rho_t, const int* boff,
+                                              const int* bsrc, int nbox, int t, int r, double* acc) {
+    constexpr int P = (Q + 1) * kOrderStep < PO ? (Q + 1) * kOrderStep : PO;
+    const size_t ew = 2 * (size_t)c.p + 2;
+    const int k1 = boff[(size_t)Q * nbox + t + 1];
+    for (int k = boff[(size_t)Q * nbox + t] + r; k < k1; k += 4) {
+        const int s = bsrc[k];
+        double rho_s;
+        const Frame fs = box_frame(c.cen, s, &rho_s);
+        const TransGeom G = trans_geom<kM2L>(fs, rho_s, ft, rho_t);
+        translate_add_po<P, PO>(c.mult + (size_t)s * ew, G, acc);
+    }
+    if constexpr (P < PO) m2l_f64_class<PO, Q + 1>(c, ft, rho_t, boff, bsrc, nbox, t, r, acc);
+}
+
+template <int PO>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_team_f64_classes(FmmCtx c, const int* order, int n, const int* boff, const int* bsrc, int nbox) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid >> 2, r = gid & 3;
+    if (i >= n) return;  // the four lanes of a team leave together
+    const int t = order[i];
+    double* out = c.local + (size_t)t * (2 * (size_t)c.p + 2);
+    double rho_t;
+    const Frame ft = box_frame(c.cen, t, &rho_t);
+    double acc[2 * PO + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * PO + 2; ++k) acc[k] = 0.0;
+    m2l_f64_class<PO, 0>(c, ft, rho_t, boff, bsrc, nbox, t, r, acc);
+#pragma unroll
+    for (int k = 0; k < 2 * PO + 2; ++k) {
+        const double v = quad_sum(acc[k]);
+        if ((k & 3) == r) out[k] = v;
+    }
+}
+
+void fmm_m2l_f64_classes(const FmmCtx& c, const int* order, int n, const int* boff, const int* bsrc, int nbox,
+                         hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned g = nblk(4 * (int64_t)n, 128);
+    switch (c.p) {
+#define C_(PO) case PO: k_m2l_team_f64_classes<PO><<<g, 128, 0, s>>>(c, order, n, boff, bsrc, nbox); break;
+        C_(5) C_(6) C_(7) C_(8) C_(9) C_(10) C_(11) C_(12) C_(13) C_(14)
+        C_(15) C_(16) C_(17) C_(18) C_(19) C_(20) C_(21) C_(22) C_(23) C_(24)
+#undef C_
+        default: throw Error(ST_INTERNAL, "record order outside the per-pair order M2L instances");
+    }
+    SFMM_LAUNCH_CHECK();
+}
+
 // Lemma 4: every box of one level takes its parent's local expansion
 template <int P>
 __global__ void __launch_bounds__(128) k_l2l(FmmCtx c, int b0, int nb) {

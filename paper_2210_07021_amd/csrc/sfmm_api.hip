@@ -802,26 +802,25 @@ void execute_impl(sfmm_plan_impl& P, double* psi, double* defl, hipStream_t s, c
                         P.ord_src, P.osq_dev.data(), s);
             P.m2l_order_sq = -1;
             // class q holds the orders in (4q, 4q + 4]; the top class the plan
-            // order.  The precision tier's boxes run all their classes in one
-            // launch, each pair's monopole part completed inside its class;
-            // the FP64 boxes (the first n_m2l_fp64 in box order) take one pass
-            // per class and the monopole parts from one pass afterwards
+            // order.  In the precision tier every box runs all its classes in
+            // one launch, each pair's monopole part completed inside its
+            // class; the FP64 path takes one pass per class and the monopole
+            // parts from one pass afterwards
             const bool tail_in_pass = tier && m2l_f32_tail_supported(P.p);
-            for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q) {
-                const int pq = std::min((q + 1) * kOrderStep, P.p);
-                const int* boff = P.ord_off.data() + (size_t)q * P.nbox;
-                if (!tail_in_pass) {
-                    m2l_pass(pq, q > 0, boff, P.ord_src.data());
-                    continue;
-                }
-                fmm_m2l(c, pq, q > 0, P.m2l_order.data(), P.n_m2l_fp64, boff, P.ord_src.data(), s);
-            }
-            // the precision tier's boxes: every class in one launch
-            if (tail_in_pass)
+            if (tail_in_pass) {
+                // the precision tier: its FP64 and its FP32 boxes each take
+                // every class in one launch, monopole parts included
+                fmm_m2l_f64_classes(c, P.m2l_order.data(), P.n_m2l_fp64, P.ord_off.data(), P.ord_src.data(),
+                                    P.nbox, s);
                 fmm_m2l_f32_classes(c, multf, P.m2l_order.data() + P.n_m2l_fp64, P.nbox - P.n_m2l_fp64,
                                     P.ord_off.data(), P.ord_src.data(), P.nbox, s);
-            m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(),
-                      tail_in_pass ? P.n_m2l_fp64 : P.nbox, s);
+            } else {
+                for (int q = 0; q < (P.p + kOrderStep - 1) / kOrderStep; ++q) {
+                    const int pq = std::min((q + 1) * kOrderStep, P.p);
+                    m2l_pass(pq, q > 0, P.ord_off.data() + (size_t)q * P.nbox, P.ord_src.data());
+                }
+                m2l_qtail(c, P.m2l_off.data(), P.m2l_src.data(), P.m2l_ord.data(), P.nbox, s);
+            }
         }
     }
     // down-pass: Lemma 4 from level 1 down
